@@ -1,0 +1,382 @@
+/*
+ * CPU oracle for Static and DF-P PageRank -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, sequential FP64 implementation of what the GPU path
+ * computes. Only the test suite, the smoke check and the benchmark's CPU
+ * baseline call it; the product path never does. It shares no code with the
+ * HIP library: it reads a canonical edge list and builds its own adjacency.
+ *
+ * Build: gcc -O2 -ffp-contract=off -shared -fPIC (no FMA contraction, so every
+ * product and sum is rounded as written). Vertex loops run in ascending ID
+ * order and every in-edge sum is accumulated in ascending source order.
+ *
+ * Paper: S. Sahu, "Efficient GPU Implementation of Static and Incrementally
+ * Expanding DF-P PageRank for Dynamic Graphs" (arXiv 2404.08299).
+ *   Eq. 1  (Sec. 3.1): R[v] = alpha * sum_{u in in(v)} R[u]/|out(u)| + (1-alpha)/|V|
+ *   Eq. 2  (Sec. 4.3): closed-loop form for a vertex with a self-loop
+ *   Alg. 1 (Static), Alg. 2 (DF*), Alg. 3 (updateRanks), Alg. 5 (marking)
+ *
+ * Readings of the paper taken here (where it is silent or garbled):
+ *   - updateRanks leaves an unaffected vertex's new rank equal to its current
+ *     rank (carry forward); the printed pseudocode only skips it.
+ *   - a relative change above the frontier tolerance sets delta_N[v] = 1
+ *     (the pseudocode prints 0; the prose says such vertices are marked).
+ *   - convergence is L-infinity over all vertices with Delta <= tau, tested
+ *     after each update; the returned ranks are the ones just computed.
+ *
+ * PPR, the weighted forward and the adjoint are not in the paper; they are
+ * the textbook personalised PageRank iteration and its transposed fixed
+ * point (derivation in the adjoint function's comment).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+enum { OR_OK = 0, OR_NOT_CONVERGED = 1, OR_EINVAL = -1, OR_ENOMEM = -4 };
+
+/* Adjacency built from an edge list (src[e] -> dst[e]). */
+typedef struct {
+  int32_t n;
+  int64_t m;
+  int64_t *in_off;   /* [n+1] */
+  int32_t *in_src;   /* [m] sources of in-edges, ascending per row */
+  int64_t *in_eid;   /* [m] index of that edge in the input list   */
+  int64_t *out_off;  /* [n+1] */
+  int32_t *out_tgt;  /* [m] targets of out-edges, ascending per row */
+  int64_t *out_eid;  /* [m] */
+  int32_t *out_deg;  /* [n] |out(u)| */
+} adjacency;
+
+static void adj_free(adjacency *a) {
+  free(a->in_off); free(a->in_src); free(a->in_eid);
+  free(a->out_off); free(a->out_tgt); free(a->out_eid); free(a->out_deg);
+  memset(a, 0, sizeof(*a));
+}
+
+/* Stable counting sort of edge ids `ids` by key[id]; result in `out`. */
+static int counting_sort(int32_t n, int64_t m, const int32_t *key, const int64_t *ids,
+                         int64_t *out, int64_t *off /* [n+1] */) {
+  memset(off, 0, sizeof(int64_t) * ((size_t)n + 1));
+  for (int64_t i = 0; i < m; ++i) off[key[ids[i]] + 1]++;
+  for (int32_t v = 0; v < n; ++v) off[v + 1] += off[v];
+  int64_t *pos = (int64_t *)malloc(sizeof(int64_t) * ((size_t)n + 1));
+  if (!pos) return OR_ENOMEM;
+  memcpy(pos, off, sizeof(int64_t) * ((size_t)n + 1));
+  for (int64_t i = 0; i < m; ++i) out[pos[key[ids[i]]]++] = ids[i];
+  free(pos);
+  return OR_OK;
+}
+
+static int adj_build(adjacency *a, int32_t n, int64_t m, const int32_t *src, const int32_t *dst) {
+  memset(a, 0, sizeof(*a));
+  if (n <= 0 || m < 0 || !src || !dst) return OR_EINVAL;
+  for (int64_t e = 0; e < m; ++e)
+    if (src[e] < 0 || src[e] >= n || dst[e] < 0 || dst[e] >= n) return OR_EINVAL;
+  a->n = n; a->m = m;
+  a->in_off = malloc(sizeof(int64_t) * ((size_t)n + 1));
+  a->out_off = malloc(sizeof(int64_t) * ((size_t)n + 1));
+  a->in_src = malloc(sizeof(int32_t) * ((size_t)m + 1));
+  a->out_tgt = malloc(sizeof(int32_t) * ((size_t)m + 1));
+  a->in_eid = malloc(sizeof(int64_t) * ((size_t)m + 1));
+  a->out_eid = malloc(sizeof(int64_t) * ((size_t)m + 1));
+  a->out_deg = malloc(sizeof(int32_t) * (size_t)n);
+  int64_t *ids = malloc(sizeof(int64_t) * ((size_t)m + 1));
+  int64_t *tmp = malloc(sizeof(int64_t) * ((size_t)m + 1));
+  if (!a->in_off || !a->out_off || !a->in_src || !a->out_tgt || !a->in_eid || !a->out_eid ||
+      !a->out_deg || !ids || !tmp) {
+    free(ids); free(tmp); adj_free(a); return OR_ENOMEM;
+  }
+  for (int64_t e = 0; e < m; ++e) ids[e] = e;
+  /* in-lists: sort by source, then stably by destination (LSD radix) */
+  if (counting_sort(n, m, src, ids, tmp, a->in_off) ||
+      counting_sort(n, m, dst, tmp, a->in_eid, a->in_off)) {
+    free(ids); free(tmp); adj_free(a); return OR_ENOMEM;
+  }
+  for (int64_t i = 0; i < m; ++i) a->in_src[i] = src[a->in_eid[i]];
+  /* out-lists: sort by destination, then stably by source */
+  if (counting_sort(n, m, dst, ids, tmp, a->out_off) ||
+      counting_sort(n, m, src, tmp, a->out_eid, a->out_off)) {
+    free(ids); free(tmp); adj_free(a); return OR_ENOMEM;
+  }
+  for (int64_t i = 0; i < m; ++i) a->out_tgt[i] = dst[a->out_eid[i]];
+  for (int32_t u = 0; u < n; ++u) a->out_deg[u] = (int32_t)(a->out_off[u + 1] - a->out_off[u]);
+  free(ids); free(tmp);
+  return OR_OK;
+}
+
+static double linf_delta(int32_t n, const double *x, const double *y) {
+  double d = 0.0;
+  for (int32_t v = 0; v < n; ++v) {
+    double t = fabs(x[v] - y[v]);
+    if (t > d) d = t;
+  }
+  return d;
+}
+
+/*
+ * Static PageRank: Alg. 1 with the update of Eq. 1.
+ * R = R_new = 1/|V| (or `init` when given: the Naive-dynamic variant of
+ * Sec. 3.4.1 starts from the previous ranks); each iteration computes R_new
+ * from R for every vertex, Delta = max_v |R_new[v] - R[v]|, swaps, and stops
+ * when Delta <= tol, at most max_iter iterations.
+ * Requires |out(u)| >= 1 for every u (the self-loop convention).
+ */
+int oracle_static(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, double alpha,
+                  double tol, int32_t max_iter, const double *init, double *ranks,
+                  int32_t *iters, double *delta) {
+  if (!(alpha > 0.0 && alpha < 1.0) || !(tol >= 0.0) || max_iter <= 0 || !ranks) return OR_EINVAL;
+  adjacency a;
+  int rc = adj_build(&a, n, m, src, dst);
+  if (rc) return rc;
+  for (int32_t u = 0; u < n; ++u)
+    if (a.out_deg[u] == 0) { adj_free(&a); return OR_EINVAL; }
+  double *R = malloc(sizeof(double) * (size_t)n), *Rn = malloc(sizeof(double) * (size_t)n);
+  if (!R || !Rn) { free(R); free(Rn); adj_free(&a); return OR_ENOMEM; }
+  for (int32_t v = 0; v < n; ++v) R[v] = Rn[v] = init ? init[v] : 1.0 / (double)n;
+  const double C0 = (1.0 - alpha) / (double)n;
+  int32_t it = 0;
+  double d = 0.0;
+  int converged = 0;
+  while (it < max_iter) {
+    for (int32_t v = 0; v < n; ++v) {
+      double c = 0.0;
+      for (int64_t i = a.in_off[v]; i < a.in_off[v + 1]; ++i) {
+        int32_t u = a.in_src[i];
+        c = c + R[u] / (double)a.out_deg[u];
+      }
+      Rn[v] = C0 + alpha * c;
+    }
+    d = linf_delta(n, Rn, R);
+    double *t = R; R = Rn; Rn = t;
+    ++it;
+    if (d <= tol) { converged = 1; break; }
+  }
+  memcpy(ranks, R, sizeof(double) * (size_t)n);
+  if (iters) *iters = it;
+  if (delta) *delta = d;
+  free(R); free(Rn); adj_free(&a);
+  return converged ? OR_OK : OR_NOT_CONVERGED;
+}
+
+/* expandAffected of Alg. 5: for each u with delta_N[u], mark every v in out(u). */
+static void expand_affected(const adjacency *a, uint8_t *dV, const uint8_t *dN) {
+  for (int32_t u = 0; u < a->n; ++u)
+    if (dN[u])
+      for (int64_t i = a->out_off[u]; i < a->out_off[u + 1]; ++i) dV[a->out_tgt[i]] = 1;
+}
+
+/*
+ * Dynamic Frontier PageRank: Alg. 2 with updateRanks of Alg. 3 and the
+ * marking of Alg. 5, on G^t given as an edge list.
+ *   prune = 1: DF-P (Eq. 2 closed-loop update, pruning when the relative
+ *              change is <= tau_p);
+ *   prune = 0: DF (Eq. 1 update, no pruning).
+ * The batch (deletions and insertions) must be the set differences between
+ * G^{t-1} and G^t. Only insertion sources are read.
+ * stats (may be NULL): [0] affected after initial marking, [1] maximum
+ * affected at the start of an iteration, [2] in-edges processed (sum over
+ * iterations of the in-degrees of the updated vertices), [3] vertices ever
+ * affected.
+ * trace (may be NULL): (max_iter + 1) x n bytes; row i is delta_V at the
+ * start of iteration i (row 0 after the initial marking).
+ */
+int oracle_dfp(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, int64_t n_del,
+               const int32_t *del_src, const int32_t *del_dst, int64_t n_ins,
+               const int32_t *ins_src, const double *ranks_prev, double alpha, double tol,
+               double tau_f, double tau_p, int32_t max_iter, int32_t prune, double *ranks,
+               int32_t *iters, double *delta, int64_t *stats, uint8_t *trace) {
+  if (!(alpha > 0.0 && alpha < 1.0) || !(tol >= 0.0) || max_iter <= 0 || !ranks || !ranks_prev)
+    return OR_EINVAL;
+  if ((n_del > 0 && (!del_src || !del_dst)) || (n_ins > 0 && !ins_src)) return OR_EINVAL;
+  adjacency a;
+  int rc = adj_build(&a, n, m, src, dst);
+  if (rc) return rc;
+  for (int32_t u = 0; u < n; ++u)
+    if (a.out_deg[u] == 0) { adj_free(&a); return OR_EINVAL; }
+  for (int64_t i = 0; i < n_del; ++i)
+    if (del_src[i] < 0 || del_src[i] >= n || del_dst[i] < 0 || del_dst[i] >= n) {
+      adj_free(&a); return OR_EINVAL;
+    }
+  for (int64_t i = 0; i < n_ins; ++i)
+    if (ins_src[i] < 0 || ins_src[i] >= n) { adj_free(&a); return OR_EINVAL; }
+  double *R = malloc(sizeof(double) * (size_t)n), *Rn = malloc(sizeof(double) * (size_t)n);
+  uint8_t *dV = calloc((size_t)n, 1), *dN = calloc((size_t)n, 1), *ever = calloc((size_t)n, 1);
+  if (!R || !Rn || !dV || !dN || !ever) {
+    free(R); free(Rn); free(dV); free(dN); free(ever); adj_free(&a); return OR_ENOMEM;
+  }
+  /* initialise both rank vectors from the previous ranks (Alg. 2) */
+  for (int32_t v = 0; v < n; ++v) R[v] = Rn[v] = ranks_prev[v];
+  /* initialAffected (Alg. 5) */
+  for (int64_t i = 0; i < n_del; ++i) { dN[del_src[i]] = 1; dV[del_dst[i]] = 1; }
+  for (int64_t i = 0; i < n_ins; ++i) dN[ins_src[i]] = 1;
+  expand_affected(&a, dV, dN);
+  const double C0 = (1.0 - alpha) / (double)n;
+  int64_t aff0 = 0, affmax = 0, edges = 0, ever_n = 0;
+  for (int32_t v = 0; v < n; ++v) aff0 += dV[v];
+  int32_t it = 0;
+  double d = 0.0;
+  int converged = 0;
+  while (it < max_iter) {
+    int64_t aff = 0;
+    for (int32_t v = 0; v < n; ++v) { aff += dV[v]; if (dV[v]) ever[v] = 1; }
+    if (aff > affmax) affmax = aff;
+    if (trace) memcpy(trace + (size_t)it * (size_t)n, dV, (size_t)n);
+    memset(dN, 0, (size_t)n);
+    /* updateRanks (Alg. 3) */
+    for (int32_t v = 0; v < n; ++v) {
+      if (!dV[v]) { Rn[v] = R[v]; continue; }
+      double c = 0.0;
+      const double dv = (double)a.out_deg[v];
+      for (int64_t i = a.in_off[v]; i < a.in_off[v + 1]; ++i) {
+        int32_t u = a.in_src[i];
+        c = c + R[u] / (double)a.out_deg[u];
+      }
+      edges += a.in_off[v + 1] - a.in_off[v];
+      double r;
+      if (prune) r = 1.0 / (1.0 - alpha / dv) * (C0 + alpha * (c - R[v] / dv)); /* Eq. 2 */
+      else r = C0 + alpha * c;                                                   /* Eq. 1 */
+      double dr = fabs(r - R[v]);
+      double rel = dr / (r > R[v] ? r : R[v]);
+      if (prune && rel <= tau_p) dV[v] = 0;
+      if (rel > tau_f) dN[v] = 1;
+      Rn[v] = r;
+    }
+    d = linf_delta(n, Rn, R);
+    double *t = R; R = Rn; Rn = t;
+    ++it;
+    if (d <= tol) { converged = 1; break; }
+    expand_affected(&a, dV, dN);
+  }
+  if (trace && it <= max_iter) memcpy(trace + (size_t)it * (size_t)n, dV, (size_t)n);
+  for (int32_t v = 0; v < n; ++v) ever_n += ever[v];
+  memcpy(ranks, R, sizeof(double) * (size_t)n);
+  if (iters) *iters = it;
+  if (delta) *delta = d;
+  if (stats) { stats[0] = aff0; stats[1] = affmax; stats[2] = edges; stats[3] = ever_n; }
+  free(R); free(Rn); free(dV); free(dN); free(ever); adj_free(&a);
+  return converged ? OR_OK : OR_NOT_CONVERGED;
+}
+
+/*
+ * Personalised PageRank with k teleport vectors (vertex-major, s[v*k + j]):
+ *   R_j[v] = alpha * sum_{u in in(v)} R_j[u]/|out(u)| + (1-alpha) * s_j[v],
+ * started from 1/|V|; each vector stops on its own when its L-infinity
+ * change is <= tol. With s_j = 1/|V| everywhere this is Eq. 1.
+ */
+int oracle_ppr(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, int32_t k,
+               const double *s, double alpha, double tol, int32_t max_iter, double *ranks,
+               int32_t *iters) {
+  if (k <= 0 || !s || !ranks || !(alpha > 0.0 && alpha < 1.0) || max_iter <= 0) return OR_EINVAL;
+  adjacency a;
+  int rc = adj_build(&a, n, m, src, dst);
+  if (rc) return rc;
+  double *R = malloc(sizeof(double) * (size_t)n), *Rn = malloc(sizeof(double) * (size_t)n);
+  if (!R || !Rn) { free(R); free(Rn); adj_free(&a); return OR_ENOMEM; }
+  int all = 1;
+  for (int32_t j = 0; j < k; ++j) {
+    for (int32_t v = 0; v < n; ++v) R[v] = Rn[v] = 1.0 / (double)n;
+    int32_t it = 0;
+    int conv = 0;
+    while (it < max_iter) {
+      for (int32_t v = 0; v < n; ++v) {
+        double c = 0.0;
+        for (int64_t i = a.in_off[v]; i < a.in_off[v + 1]; ++i) {
+          int32_t u = a.in_src[i];
+          c = c + R[u] / (double)a.out_deg[u];
+        }
+        Rn[v] = (1.0 - alpha) * s[(size_t)v * (size_t)k + (size_t)j] + alpha * c;
+      }
+      double d = linf_delta(n, Rn, R);
+      double *t = R; R = Rn; Rn = t;
+      ++it;
+      if (d <= tol) { conv = 1; break; }
+    }
+    for (int32_t v = 0; v < n; ++v) ranks[(size_t)v * (size_t)k + (size_t)j] = R[v];
+    if (iters) iters[j] = it;
+    if (!conv) all = 0;
+  }
+  free(R); free(Rn); adj_free(&a);
+  return all ? OR_OK : OR_NOT_CONVERGED;
+}
+
+/*
+ * Weighted forward: r_v = alpha * sum_{u in in(v)} P_uv * r_u + (1-alpha) * s_v,
+ * with P given per edge (w[e] for edge src[e] -> dst[e]), used as given.
+ * Started from 1/|V| (or `init`); L-infinity stop as in Alg. 1.
+ */
+int oracle_weighted(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                    const double *w, const double *s, double alpha, double tol, int32_t max_iter,
+                    const double *init, double *ranks, int32_t *iters, double *delta) {
+  if (!w || !s || !ranks || !(alpha > 0.0 && alpha < 1.0) || max_iter <= 0) return OR_EINVAL;
+  adjacency a;
+  int rc = adj_build(&a, n, m, src, dst);
+  if (rc) return rc;
+  double *R = malloc(sizeof(double) * (size_t)n), *Rn = malloc(sizeof(double) * (size_t)n);
+  if (!R || !Rn) { free(R); free(Rn); adj_free(&a); return OR_ENOMEM; }
+  for (int32_t v = 0; v < n; ++v) R[v] = Rn[v] = init ? init[v] : 1.0 / (double)n;
+  int32_t it = 0;
+  double d = 0.0;
+  int conv = 0;
+  while (it < max_iter) {
+    for (int32_t v = 0; v < n; ++v) {
+      double c = 0.0;
+      for (int64_t i = a.in_off[v]; i < a.in_off[v + 1]; ++i)
+        c = c + w[a.in_eid[i]] * R[a.in_src[i]];
+      Rn[v] = (1.0 - alpha) * s[v] + alpha * c;
+    }
+    d = linf_delta(n, Rn, R);
+    double *t = R; R = Rn; Rn = t;
+    ++it;
+    if (d <= tol) { conv = 1; break; }
+  }
+  memcpy(ranks, R, sizeof(double) * (size_t)n);
+  if (iters) *iters = it;
+  if (delta) *delta = d;
+  free(R); free(Rn); adj_free(&a);
+  return conv ? OR_OK : OR_NOT_CONVERGED;
+}
+
+/*
+ * Adjoint of the weighted forward. With A[v][u] = P_uv, the forward fixed
+ * point is r = alpha*A*r + (1-alpha)*s. For a loss L(r) with g = dL/dr,
+ * lambda = (I - alpha*A^T)^{-1} g solves the transposed fixed point
+ *   lambda_u = g_u + alpha * sum_{v in out(u)} P_uv * lambda_v,
+ * iterated from lambda = 0 with an L-infinity stop (a contraction with
+ * factor alpha when P is row-stochastic). Then
+ *   dL/ds_v    = (1-alpha) * lambda_v,
+ *   dL/dP_uv   = alpha * r_u * lambda_v    (per edge, input order).
+ */
+int oracle_adjoint(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                   const double *w, const double *r, const double *g, double alpha, double tol,
+                   int32_t max_iter, double *grad_w, double *grad_s, double *lambda_out,
+                   int32_t *iters) {
+  if (!w || !r || !g || !(alpha > 0.0 && alpha < 1.0) || max_iter <= 0) return OR_EINVAL;
+  adjacency a;
+  int rc = adj_build(&a, n, m, src, dst);
+  if (rc) return rc;
+  double *L = calloc((size_t)n, sizeof(double)), *Ln = calloc((size_t)n, sizeof(double));
+  if (!L || !Ln) { free(L); free(Ln); adj_free(&a); return OR_ENOMEM; }
+  int32_t it = 0;
+  int conv = 0;
+  while (it < max_iter) {
+    for (int32_t u = 0; u < n; ++u) {
+      double c = 0.0;
+      for (int64_t i = a.out_off[u]; i < a.out_off[u + 1]; ++i)
+        c = c + w[a.out_eid[i]] * L[a.out_tgt[i]];
+      Ln[u] = g[u] + alpha * c;
+    }
+    double d = linf_delta(n, Ln, L);
+    double *t = L; L = Ln; Ln = t;
+    ++it;
+    if (d <= tol) { conv = 1; break; }
+  }
+  if (grad_s)
+    for (int32_t v = 0; v < n; ++v) grad_s[v] = (1.0 - alpha) * L[v];
+  if (grad_w)
+    for (int64_t e = 0; e < m; ++e) grad_w[e] = alpha * r[src[e]] * L[dst[e]];
+  if (lambda_out) memcpy(lambda_out, L, sizeof(double) * (size_t)n);
+  if (iters) *iters = it;
+  free(L); free(Ln); adj_free(&a);
+  return conv ? OR_OK : OR_NOT_CONVERGED;
+}
