@@ -1,0 +1,205 @@
+/*
+ * prhip -- Static and DF-P PageRank on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libprhip.so. Method: S. Sahu, "Efficient GPU Implementation of
+ * Static and Incrementally Expanding DF-P PageRank for Dynamic Graphs"
+ * (arXiv 2404.08299).
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ *  - All array pointers are DEVICE pointers owned by the caller (for example
+ *    torch tensor storage on the current HIP device). A call borrows them for
+ *    its duration only. The library owns nothing but its internal workspace,
+ *    which it allocates on first use per device, keeps for reuse, and frees
+ *    in pr_release().
+ *  - Calls are synchronous with respect to the host: when a call returns,
+ *    every output is complete on the stream given to pr_set_stream() (the
+ *    default stream if none). Convergence is decided inside the call.
+ *  - Vertex IDs are int32, ranks are FP64 (Sec. 5.1.2).
+ *  - Input contract (Sec. 3.1, "dead ends"): every vertex has exactly one
+ *    self-loop, so |out(u)| >= 1 for all u; rows hold no duplicates; each
+ *    in-row lists its sources in ascending order. pr_validate_csr() checks
+ *    this; the compute entry points trust it and read out of bounds if a
+ *    caller breaks it.
+ *  - Return value: PR_OK (0); PR_NOT_CONVERGED (1) when max_iter iterations
+ *    ran without meeting the tolerance (the ranks are still written); a
+ *    negative PR_E* code on error, with a message in pr_last_error(). The
+ *    library never aborts, exits or prints. Calls from several host threads
+ *    are serialised internally (they share one workspace per device).
+ */
+#ifndef PRHIP_H
+#define PRHIP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PR_OK 0
+#define PR_NOT_CONVERGED 1
+#define PR_EINVAL (-1) /* bad argument: NULL, n <= 0, alpha outside (0,1), tol < 0, ... */
+#define PR_EGRAPH (-2) /* pr_validate_csr: the graph breaks the input contract      */
+#define PR_EBATCH (-3) /* a batch vertex ID is outside [0, n)                        */
+#define PR_ENOMEM (-4) /* workspace allocation failed                                */
+#define PR_EHIP (-5)   /* a HIP runtime call failed (message in pr_last_error)       */
+
+/* Paper defaults (Sec. 5.1.2). */
+#define PR_ALPHA 0.85
+#define PR_TOL 1e-10
+#define PR_FRONTIER_TOL 1e-6
+#define PR_PRUNE_TOL 1e-6
+#define PR_MAX_ITERATIONS 500
+
+/*
+ * One graph G(V, E) in both CSR views (Sec. 4.1, 4.3: G' drives the rank
+ * pull, G drives the marking of affected vertices).
+ *   n, m          |V| and |E| (self-loops included)
+ *   in_offsets    [n+1] CSR of the transpose G': row v spans
+ *   in_sources    [m]   in_sources[in_offsets[v] .. in_offsets[v+1]) = the
+ *                       sources u of the edges u -> v, ascending
+ *   out_offsets   [n+1] CSR of G: |out(u)| = out_offsets[u+1] - out_offsets[u]
+ *   out_targets   [m]   targets of u's out-edges (read by pr_dfp only; may be
+ *                       NULL for pr_static)
+ */
+typedef struct pr_csr {
+  int32_t n;
+  int32_t m;
+  const int32_t *in_offsets;
+  const int32_t *in_sources;
+  const int32_t *out_offsets;
+  const int32_t *out_targets;
+} pr_csr;
+
+/* A list of edges (src[i] -> dst[i]), i < count, device arrays. */
+typedef struct pr_edges {
+  const int32_t *src;
+  const int32_t *dst;
+  int32_t count;
+} pr_edges;
+
+/*
+ * Static PageRank (Alg. 1; update of Eq. 1, Sec. 3.1):
+ *   R[v] = alpha * sum_{u in in(v)} R[u] / |out(u)| + (1 - alpha) / n,
+ * synchronous (two rank vectors), pull-based, no atomics on ranks. Starts
+ * from R = 1/n, stops when max_v |R_new[v] - R[v]| <= tol (L-infinity) or
+ * after max_iter iterations. The returned vector is the last one computed.
+ *   csr        graph (in_* and out_offsets are read)
+ *   ranks_out  [n] device, written
+ */
+int pr_static(const pr_csr *csr, double alpha, double tol, int max_iter, double *ranks_out);
+
+/*
+ * DF-P PageRank (Alg. 2 with updateRanks of Alg. 3, partitioning of Alg. 4
+ * and marking of Alg. 5; closed-loop update of Eq. 2, Sec. 4.3).
+ *   csr_old     G^{t-1}; not read by the computation (kept for the interface
+ *               of the method's problem statement, Sec. 3.3); may be NULL
+ *   csr_new     G^t, both views (in_* for the rank pull, out_* for marking)
+ *   deletions   Delta^- = E^{t-1} \ E^t (sources and targets are read)
+ *   insertions  Delta^+ = E^t \ E^{t-1} (only sources are read, Sec. 4.3);
+ *               either batch may have count 0 and NULL arrays
+ *   ranks_prev  [n] R^{t-1}
+ *   ranks_out   [n] written; may alias ranks_prev (in-place update)
+ * An affected vertex is recomputed with Eq. 2, pruned (no longer affected)
+ * when its relative change |r - R[v]| / max(r, R[v]) <= prune_tol, and flags
+ * its out-neighbours for marking when that change > frontier_tol. A vertex
+ * that is not affected keeps its rank. At most PR_MAX_ITERATIONS iterations.
+ * Batch IDs outside [0, n) give PR_EBATCH (ranks_out is then unspecified).
+ */
+int pr_dfp(const pr_csr *csr_old, const pr_csr *csr_new, const pr_edges *deletions,
+           const pr_edges *insertions, const double *ranks_prev, double alpha, double tol,
+           double frontier_tol, double prune_tol, double *ranks_out);
+
+/* Variants of the dynamic update selected by pr_dfp_ex's `mode`. */
+#define PR_MODE_DFP 0 /* Dynamic Frontier with Pruning: Eq. 2 + pruning (Sec. 4.3)    */
+#define PR_MODE_DF 1  /* Dynamic Frontier: Eq. 1, no pruning (Sec. 4.3, Alg. 3)       */
+#define PR_MODE_ND 2  /* Naive-dynamic: Static from R^{t-1}, all vertices (Sec. 3.4.1) */
+
+/* pr_dfp with an explicit iteration cap and update variant. */
+int pr_dfp_ex(const pr_csr *csr_old, const pr_csr *csr_new, const pr_edges *deletions,
+              const pr_edges *insertions, const double *ranks_prev, double alpha, double tol,
+              double frontier_tol, double prune_tol, int max_iter, int mode, double *ranks_out);
+
+/*
+ * Checks the input contract on the device: offsets start at 0, are
+ * non-decreasing and end at m; every ID is in [0, n); rows are strictly
+ * ascending (no duplicates); every vertex has its self-loop in both views;
+ * both views have equal degree sums. Returns PR_OK or PR_EGRAPH (the first
+ * violated rule is named in pr_last_error). out_targets may be NULL, in which
+ * case only the in view and the out degrees are checked.
+ */
+int pr_validate_csr(const pr_csr *csr);
+
+/*
+ * Launch parameters of the kernels. The results do not depend on them
+ * beyond the order of floating-point summation in the wave/workgroup
+ * reductions (Alg. 4 leaves the degree threshold unspecified).
+ *   lane_max_degree    in-degree <= this: one lane per vertex (Alg. 3,
+ *                      thread-per-vertex kernel)
+ *   wave_max_degree    in-degree <= this (and above lane_max_degree): one
+ *                      64-lane wavefront per vertex; above it: one 256-thread
+ *                      workgroup per vertex (Alg. 3, block-per-vertex kernel)
+ *   expand_lane_max_degree  out-degree <= this: one lane marks the
+ *                      neighbours, else one wavefront (Alg. 5)
+ *   iters_per_sync     iterations in flight before the host reads a
+ *                      convergence flag (1 = read after every iteration;
+ *                      with k > 1 the host waits on iteration i-k+1 while
+ *                      later ones run, and iterations enqueued after
+ *                      convergence exit at once on the device)
+ */
+typedef struct pr_tuning {
+  int32_t lane_max_degree;
+  int32_t wave_max_degree;
+  int32_t expand_lane_max_degree;
+  int32_t iters_per_sync;
+  int32_t reserved[4];
+} pr_tuning;
+
+/* Set (NULL = defaults) or read the process-wide tuning. PR_EINVAL if a
+ * field is out of range (degrees < 0, lane > wave, iters_per_sync < 1). */
+int pr_set_tuning(const pr_tuning *t);
+int pr_get_tuning(pr_tuning *t);
+
+/*
+ * Statistics of the calling thread's last compute call.
+ *   iterations         rank updates performed (Alg. 1/2 loop count)
+ *   converged          1 if the tolerance was met
+ *   final_delta        L-infinity change of the last iteration
+ *   affected_initial   DF-P: affected vertices after the initial marking
+ *                      (only with profiling on, else -1)
+ *   rank_kernel_ms     with profiling on: summed device time of the fused
+ *                      rank-update launches of the performed iterations
+ *   rank_kernel_launches  number of those launches
+ *   total_ms           with profiling on: device time of the whole call
+ */
+typedef struct pr_stats {
+  int32_t iterations;
+  int32_t converged;
+  double final_delta;
+  int64_t affected_initial;
+  double rank_kernel_ms;
+  int32_t rank_kernel_launches;
+  int32_t reserved0;
+  double total_ms;
+  double reserved[4];
+} pr_stats;
+
+int pr_last_stats(pr_stats *out);
+
+/* Turn per-launch HIP event timing on (1) or off (0) for this thread. */
+int pr_set_profiling(int enable);
+
+/* Stream for this thread's subsequent calls (a hipStream_t; NULL = default). */
+void pr_set_stream(void *hip_stream);
+
+/* Message for this thread's last failure ("" if none). */
+const char *pr_last_error(void);
+
+/* Free the cached workspace of every device. */
+void pr_release(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PRHIP_H */

@@ -1,0 +1,555 @@
+// Host side of libprhip.so: the C ABI of include/prhip.h.
+//
+// Method: S. Sahu, "Efficient GPU Implementation of Static and Incrementally
+// Expanding DF-P PageRank for Dynamic Graphs" (arXiv 2404.08299), Alg. 1-5.
+//
+// Control flow per call: argument checks (no HIP call before they pass),
+// workspace (grow-only, per device, reused), partition by degree (Alg. 4),
+// initialisation, then the iteration loop. Each iteration enqueues the fused
+// rank kernel, the L-infinity final reduction (which records the outcome in a
+// device control block), for DF-P the apply/expand kernel, and an 8-byte-ish
+// copy of the control block into pinned host memory. The host keeps up to
+// `iters_per_sync` iterations in flight and waits only on the oldest one's
+// copy, so the device does not idle on the host between iterations.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "prhip.h"
+
+using namespace prhip;
+
+namespace {
+
+thread_local hipStream_t t_stream = nullptr;
+thread_local std::string t_err;
+thread_local pr_stats t_stats;
+thread_local int t_profiling = 0;
+
+std::mutex g_mu;
+
+pr_tuning default_tuning() {
+  pr_tuning t;
+  std::memset(&t, 0, sizeof(t));
+  t.lane_max_degree = 32;
+  t.wave_max_degree = 4096;
+  t.expand_lane_max_degree = 32;
+  t.iters_per_sync = 2;
+  return t;
+}
+pr_tuning g_tuning = default_tuning();
+
+constexpr int kRing = 8;  // pinned control-block snapshots
+
+struct Workspace {
+  size_t cap_n = 0;
+  double *R1 = nullptr, *X0 = nullptr, *X1 = nullptr, *T = nullptr;
+  uint8_t *flags = nullptr;  // dV | dN | cv, n bytes each
+  int *hi_in = nullptr, *hi_out = nullptr;
+  int *tile_counts = nullptr;  // [2][ntiles]
+  int *counts = nullptr;       // [4]: in-class1, in-class2, out-class1, out-class2
+  double *partials = nullptr;
+  size_t cap_partials = 0;
+  Ctrl *ctrl = nullptr;
+  Ctrl *host_ctrl = nullptr;  // pinned ring
+  int *host_counts = nullptr;  // pinned
+  hipEvent_t sync_ev[kRing] = {};
+  std::vector<hipEvent_t> prof_ev;
+  hipEvent_t call_ev[2] = {};
+  bool events_ready = false;
+};
+std::map<int, Workspace> g_ws;
+
+int fail(int code, const std::string &msg) {
+  t_err = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(PR_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));        \
+  } while (0)
+
+#define LAUNCH_TRY()                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = hipGetLastError();                                                       \
+    if (e_ != hipSuccess)                                                              \
+      return fail(PR_EHIP, std::string("kernel launch: ") + hipGetErrorString(e_));   \
+  } while (0)
+
+void free_ws(Workspace &w) {
+  (void)hipFree(w.R1); (void)hipFree(w.X0); (void)hipFree(w.X1); (void)hipFree(w.T); (void)hipFree(w.flags);
+  (void)hipFree(w.hi_in); (void)hipFree(w.hi_out); (void)hipFree(w.tile_counts); (void)hipFree(w.counts);
+  (void)hipFree(w.partials); (void)hipFree(w.ctrl);
+  if (w.host_ctrl) (void)hipHostFree(w.host_ctrl);
+  if (w.host_counts) (void)hipHostFree(w.host_counts);
+  if (w.events_ready) {
+    for (auto &e : w.sync_ev) (void)hipEventDestroy(e);
+    for (auto &e : w.call_ev) (void)hipEventDestroy(e);
+  }
+  for (auto &e : w.prof_ev) (void)hipEventDestroy(e);
+  w = Workspace();
+}
+
+size_t ntiles_for(size_t n) { return (n + kPartTile - 1) / kPartTile; }
+
+// Grid of the fused rank launch for n vertices with n1/n2 hub-class counts.
+struct RankGrid {
+  int nb2, nb1, nb0;
+  int total() const { return nb2 + nb1 + nb0; }
+};
+RankGrid rank_grid(int n, int n1, int n2) {
+  RankGrid g;
+  g.nb2 = n2;
+  g.nb1 = (n1 + kWavesPerBlock - 1) / kWavesPerBlock;
+  g.nb0 = (n + kBlock - 1) / kBlock;
+  return g;
+}
+
+int get_ws(size_t n, Workspace **out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  Workspace &w = g_ws[dev];
+  if (!w.events_ready) {
+    for (auto &e : w.sync_ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    for (auto &e : w.call_ev) HIP_TRY(hipEventCreate(&e));
+    HIP_TRY(hipMalloc(&w.ctrl, sizeof(Ctrl)));
+    HIP_TRY(hipMalloc(&w.counts, 4 * sizeof(int)));
+    HIP_TRY(hipHostMalloc(&w.host_ctrl, kRing * sizeof(Ctrl), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc(&w.host_counts, 4 * sizeof(int), hipHostMallocDefault));
+    w.events_ready = true;
+  }
+  if (n > w.cap_n) {
+    (void)hipFree(w.R1); (void)hipFree(w.X0); (void)hipFree(w.X1); (void)hipFree(w.T); (void)hipFree(w.flags);
+    (void)hipFree(w.hi_in); (void)hipFree(w.hi_out); (void)hipFree(w.tile_counts); (void)hipFree(w.partials);
+    w.R1 = w.X0 = w.X1 = w.T = nullptr;
+    w.flags = nullptr;
+    w.hi_in = w.hi_out = w.tile_counts = nullptr;
+    w.partials = nullptr;
+    w.cap_n = 0;
+    size_t nt = ntiles_for(n);
+    // upper bound of blocks of any fused launch: every vertex a WG-class one
+    size_t np = n + (n + kBlock - 1) / kBlock + 16;
+    hipError_t e = hipSuccess;
+    if ((e = hipMalloc(&w.R1, n * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&w.X0, n * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&w.X1, n * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&w.T, n * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&w.flags, 3 * n)) != hipSuccess ||
+        (e = hipMalloc(&w.hi_in, n * sizeof(int))) != hipSuccess ||
+        (e = hipMalloc(&w.hi_out, n * sizeof(int))) != hipSuccess ||
+        (e = hipMalloc(&w.tile_counts, 2 * nt * sizeof(int) + 64)) != hipSuccess ||
+        (e = hipMalloc(&w.partials, np * sizeof(double))) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipFree(w.R1); (void)hipFree(w.X0); (void)hipFree(w.X1); (void)hipFree(w.T); (void)hipFree(w.flags);
+      (void)hipFree(w.hi_in); (void)hipFree(w.hi_out); (void)hipFree(w.tile_counts); (void)hipFree(w.partials);
+      w.R1 = w.X0 = w.X1 = w.T = nullptr;
+      w.flags = nullptr;
+      w.hi_in = w.hi_out = w.tile_counts = nullptr;
+      w.partials = nullptr;
+      return fail(e == hipErrorOutOfMemory ? PR_ENOMEM : PR_EHIP,
+                  std::string("workspace allocation: ") + hipGetErrorString(e));
+    }
+    w.cap_n = n;
+    w.cap_partials = np;
+  }
+  *out = &w;
+  return PR_OK;
+}
+
+hipEvent_t prof_event(Workspace &w, size_t i) {
+  while (w.prof_ev.size() <= i) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    w.prof_ev.push_back(e);
+  }
+  return w.prof_ev[i];
+}
+
+int check_csr(const pr_csr *g, bool need_out_targets) {
+  if (!g) return fail(PR_EINVAL, "csr is NULL");
+  if (g->n <= 0) return fail(PR_EINVAL, "n must be > 0");
+  if (g->m < g->n) return fail(PR_EINVAL, "m must be >= n (one self-loop per vertex)");
+  if (!g->in_offsets || !g->in_sources || !g->out_offsets)
+    return fail(PR_EINVAL, "in_offsets, in_sources and out_offsets are required");
+  if (need_out_targets && !g->out_targets) return fail(PR_EINVAL, "out_targets is required");
+  return PR_OK;
+}
+
+int check_params(double alpha, double tol, int max_iter) {
+  if (!(alpha > 0.0 && alpha < 1.0)) return fail(PR_EINVAL, "alpha must be in (0, 1)");
+  if (!(tol >= 0.0)) return fail(PR_EINVAL, "tol must be >= 0");
+  if (max_iter <= 0) return fail(PR_EINVAL, "max_iter must be > 0");
+  return PR_OK;
+}
+
+// Alg. 4 on an offsets array; hub lists into `hi`, class counts into
+// counts[slot], counts[slot+1] (device).
+int partition(Workspace &w, const int *off, int n, int t1, int t2, int *hi, int slot,
+              hipStream_t s) {
+  const int nt = (int)ntiles_for(n);
+  hipLaunchKernelGGL(k_part_count, dim3(nt), dim3(kBlock), 0, s, off, n, t1, t2, w.tile_counts,
+                     nt);
+  hipLaunchKernelGGL(k_part_scan, dim3(1), dim3(kFinalBlock), 0, s, w.tile_counts, nt,
+                     w.counts + slot);
+  hipLaunchKernelGGL(k_part_scatter, dim3(nt), dim3(kBlock), 0, s, off, n, t1, t2,
+                     w.tile_counts, nt, w.counts + slot, hi);
+  LAUNCH_TRY();
+  return PR_OK;
+}
+
+struct CallTimer {
+  Workspace &w;
+  hipStream_t s;
+  bool on;
+  CallTimer(Workspace &w_, hipStream_t s_) : w(w_), s(s_), on(t_profiling != 0) {
+    if (on) (void)hipEventRecord(w.call_ev[0], s);
+  }
+  void stop() {
+    if (on) (void)hipEventRecord(w.call_ev[1], s);
+  }
+  double ms() {
+    float f = 0.f;
+    if (on && hipEventElapsedTime(&f, w.call_ev[0], w.call_ev[1]) == hipSuccess) return f;
+    return 0.0;
+  }
+};
+
+// The iteration loop shared by Static and DF/DF-P. `launch(it)` enqueues the
+// work of iteration `it` between the profiling events.
+template <class F>
+int iterate(Workspace &w, hipStream_t s, int max_iter, F &&launch, int *iters_out,
+            int *launched_out) {
+  const int K = std::max(1, std::min(g_tuning.iters_per_sync, kRing - 1));
+  int it = 0;
+  bool done = false;
+  while (it < max_iter && !done) {
+    if (t_profiling) {
+      hipEvent_t a = prof_event(w, 2 * (size_t)it), b = prof_event(w, 2 * (size_t)it + 1);
+      if (!a || !b) return fail(PR_EHIP, "hipEventCreate failed");
+      HIP_TRY(hipEventRecord(a, s));
+      int rc = launch(it, true, b);
+      if (rc) return rc;
+    } else {
+      int rc = launch(it, false, nullptr);
+      if (rc) return rc;
+    }
+    HIP_TRY(hipMemcpyAsync(&w.host_ctrl[it % kRing], w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost,
+                           s));
+    HIP_TRY(hipEventRecord(w.sync_ev[it % kRing], s));
+    ++it;
+    const int j = it - K;
+    if (j >= 0) {
+      HIP_TRY(hipEventSynchronize(w.sync_ev[j % kRing]));
+      if (w.host_ctrl[j % kRing].done) done = true;
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  const Ctrl &last = w.host_ctrl[(it - 1) % kRing];
+  *iters_out = last.done ? last.iters : std::min(it, max_iter);
+  *launched_out = it;
+  t_stats.converged = last.done;
+  t_stats.final_delta = last.delta;
+  t_stats.iterations = *iters_out;
+  return PR_OK;
+}
+
+void collect_profile(Workspace &w, int iters) {
+  if (!t_profiling) return;
+  double tot = 0.0;
+  for (int i = 0; i < iters; ++i) {
+    float f = 0.f;
+    if (hipEventElapsedTime(&f, w.prof_ev[2 * i], w.prof_ev[2 * i + 1]) == hipSuccess) tot += f;
+  }
+  t_stats.rank_kernel_ms = tot;
+  t_stats.rank_kernel_launches = iters;
+}
+
+void reset_stats() {
+  std::memset(&t_stats, 0, sizeof(t_stats));
+  t_stats.affected_initial = -1;
+  t_err.clear();
+}
+
+// Static iteration (Alg. 1), from 1/n or from `init` (Naive-dynamic).
+int run_static(const pr_csr *g, double alpha, double tol, int max_iter, const double *init,
+               double *ranks_out) {
+  hipStream_t s = t_stream;
+  const int n = g->n;
+  Workspace *wp = nullptr;
+  int rc = get_ws((size_t)n, &wp);
+  if (rc) return rc;
+  Workspace &w = *wp;
+  CallTimer timer(w, s);
+  const pr_tuning tn = g_tuning;
+  hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, s, w.ctrl);
+  rc = partition(w, g->in_offsets, n, tn.lane_max_degree, tn.wave_max_degree, w.hi_in, 0, s);
+  if (rc) return rc;
+  // R[0] is the caller's output vector; with `init` (which may alias it) the
+  // start vector is copied into it.
+  double *R[2] = {ranks_out, w.R1};
+  double *X[2] = {w.X0, w.X1};
+  hipLaunchKernelGGL(k_static_init, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n,
+                     g->out_offsets, init, R[0], X[0]);
+  LAUNCH_TRY();
+  HIP_TRY(hipMemcpyAsync(w.host_counts, w.counts, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const int n1 = w.host_counts[0], n2 = w.host_counts[1];
+  const RankGrid grid = rank_grid(n, n1, n2);
+  const double C0 = (1.0 - alpha) / (double)n;
+  const int t1 = tn.lane_max_degree;
+  auto launch = [&](int it, bool prof, hipEvent_t after) -> int {
+    const int a = it & 1, b = a ^ 1;
+    hipLaunchKernelGGL(k_rank_static, dim3(grid.total()), dim3(kBlock), 0, s, g->in_offsets,
+                       g->in_sources, g->out_offsets, (const double *)X[a], (const double *)R[a],
+                       R[b], X[b], (const int *)w.hi_in, n1, grid.nb2, grid.nb1, n, t1, C0,
+                       alpha, w.partials, (const Ctrl *)w.ctrl);
+    if (prof) HIP_TRY(hipEventRecord(after, s));
+    hipLaunchKernelGGL(k_linf_final, dim3(1), dim3(kFinalBlock), 0, s,
+                       (const double *)w.partials, grid.total(), w.ctrl, tol, it);
+    LAUNCH_TRY();
+    return PR_OK;
+  };
+  int iters = 0, launched = 0;
+  rc = iterate(w, s, max_iter, launch, &iters, &launched);
+  if (rc) return rc;
+  double *result = R[iters & 1];
+  if (result != ranks_out)
+    HIP_TRY(hipMemcpyAsync(ranks_out, result, (size_t)n * sizeof(double),
+                           hipMemcpyDeviceToDevice, s));
+  timer.stop();
+  HIP_TRY(hipStreamSynchronize(s));
+  t_stats.total_ms = timer.ms();
+  collect_profile(w, iters);
+  return t_stats.converged ? PR_OK : PR_NOT_CONVERGED;
+}
+
+int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *ins,
+                         const double *prev, double alpha, double tol, double tau_f,
+                         double tau_p, int max_iter, bool prune, double *ranks_out) {
+  hipStream_t s = t_stream;
+  const int n = g->n;
+  Workspace *wp = nullptr;
+  int rc = get_ws((size_t)n, &wp);
+  if (rc) return rc;
+  Workspace &w = *wp;
+  CallTimer timer(w, s);
+  const pr_tuning tn = g_tuning;
+  uint8_t *dV = w.flags, *dN = w.flags + n, *cv = w.flags + 2 * (size_t)n;
+  double *R = ranks_out;
+  hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, s, w.ctrl);
+  hipLaunchKernelGGL(k_dfp_init, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, prev, R,
+                     dV, dN, cv);
+  LAUNCH_TRY();
+  rc = partition(w, g->in_offsets, n, tn.lane_max_degree, tn.wave_max_degree, w.hi_in, 0, s);
+  if (rc) return rc;
+  rc = partition(w, g->out_offsets, n, tn.expand_lane_max_degree, INT_MAX, w.hi_out, 2, s);
+  if (rc) return rc;
+  const int nd = del ? del->count : 0, ni = ins ? ins->count : 0;
+  if (nd + ni > 0) {
+    hipLaunchKernelGGL(k_mark_initial, dim3((nd + ni + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
+                       del ? del->src : nullptr, del ? del->dst : nullptr, nd,
+                       ins ? ins->src : nullptr, ni, n, dV, dN, w.ctrl);
+    LAUNCH_TRY();
+  }
+  HIP_TRY(hipMemcpyAsync(w.host_counts, w.counts, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(&w.host_ctrl[0], w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (w.host_ctrl[0].err) return fail(PR_EBATCH, "batch vertex ID outside [0, n)");
+  const int n1 = w.host_counts[0], n2 = w.host_counts[1], no1 = w.host_counts[2];
+  const RankGrid grid = rank_grid(n, n1, n2);
+  const int nbo1 = (no1 + kWavesPerBlock - 1) / kWavesPerBlock;
+  const int nb_apply = nbo1 + (n + kBlock - 1) / kBlock;
+  const int t1 = tn.lane_max_degree, t_exp = tn.expand_lane_max_degree;
+  // initial expandAffected (Alg. 2, after initialAffected)
+  hipLaunchKernelGGL(k_apply_expand, dim3(nb_apply), dim3(kBlock), 0, s, g->out_offsets,
+                     g->out_targets, R, (const double *)w.T, dV, dN, cv, (const int *)w.hi_out,
+                     no1, nbo1, n, t_exp, (const Ctrl *)w.ctrl, -1);
+  LAUNCH_TRY();
+  if (t_profiling) {
+    hipLaunchKernelGGL(k_count_flags, dim3(std::min(1024, (n + kBlock - 1) / kBlock)),
+                       dim3(kBlock), 0, s, (const uint8_t *)dV, n, w.ctrl, 0);
+    LAUNCH_TRY();
+  }
+  const double C0 = (1.0 - alpha) / (double)n;
+  auto launch = [&](int it, bool prof, hipEvent_t after) -> int {
+    if (prune)
+      hipLaunchKernelGGL(k_rank_dfp<true>, dim3(grid.total()), dim3(kBlock), 0, s, g->in_offsets,
+                         g->in_sources, g->out_offsets, (const double *)R, w.T, dV, dN, cv,
+                         (const int *)w.hi_in, n1, grid.nb2, grid.nb1, n, t1, C0, alpha, tau_f,
+                         tau_p, w.partials, (const Ctrl *)w.ctrl);
+    else
+      hipLaunchKernelGGL(k_rank_dfp<false>, dim3(grid.total()), dim3(kBlock), 0, s,
+                         g->in_offsets, g->in_sources, g->out_offsets, (const double *)R, w.T, dV,
+                         dN, cv, (const int *)w.hi_in, n1, grid.nb2, grid.nb1, n, t1, C0, alpha,
+                         tau_f, tau_p, w.partials, (const Ctrl *)w.ctrl);
+    if (prof) HIP_TRY(hipEventRecord(after, s));
+    hipLaunchKernelGGL(k_linf_final, dim3(1), dim3(kFinalBlock), 0, s,
+                       (const double *)w.partials, grid.total(), w.ctrl, tol, it);
+    hipLaunchKernelGGL(k_apply_expand, dim3(nb_apply), dim3(kBlock), 0, s, g->out_offsets,
+                       g->out_targets, R, (const double *)w.T, dV, dN, cv,
+                       (const int *)w.hi_out, no1, nbo1, n, t_exp, (const Ctrl *)w.ctrl, it);
+    LAUNCH_TRY();
+    return PR_OK;
+  };
+  int iters = 0, launched = 0;
+  rc = iterate(w, s, max_iter, launch, &iters, &launched);
+  if (rc) return rc;
+  timer.stop();
+  HIP_TRY(hipStreamSynchronize(s));
+  if (t_profiling) t_stats.affected_initial = w.host_ctrl[(launched - 1) % kRing].aux[0];
+  t_stats.total_ms = timer.ms();
+  collect_profile(w, iters);
+  return t_stats.converged ? PR_OK : PR_NOT_CONVERGED;
+}
+
+int check_edges(const pr_edges *e, const char *name) {
+  if (!e) return PR_OK;
+  if (e->count < 0) return fail(PR_EINVAL, std::string(name) + ".count < 0");
+  if (e->count > 0 && !e->src) return fail(PR_EINVAL, std::string(name) + ".src is NULL");
+  return PR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pr_static(const pr_csr *csr, double alpha, double tol, int max_iter, double *ranks_out) {
+  reset_stats();
+  int rc = check_csr(csr, false);
+  if (rc) return rc;
+  if ((rc = check_params(alpha, tol, max_iter))) return rc;
+  if (!ranks_out) return fail(PR_EINVAL, "ranks_out is NULL");
+  std::lock_guard<std::mutex> lock(g_mu);
+  return run_static(csr, alpha, tol, max_iter, nullptr, ranks_out);
+}
+
+int pr_dfp_ex(const pr_csr *csr_old, const pr_csr *csr_new, const pr_edges *deletions,
+              const pr_edges *insertions, const double *ranks_prev, double alpha, double tol,
+              double frontier_tol, double prune_tol, int max_iter, int mode, double *ranks_out) {
+  reset_stats();
+  (void)csr_old;
+  int rc = check_csr(csr_new, mode != PR_MODE_ND);
+  if (rc) return rc;
+  if ((rc = check_params(alpha, tol, max_iter))) return rc;
+  if (!ranks_prev || !ranks_out) return fail(PR_EINVAL, "ranks_prev and ranks_out are required");
+  if (mode != PR_MODE_DFP && mode != PR_MODE_DF && mode != PR_MODE_ND)
+    return fail(PR_EINVAL, "unknown mode");
+  if (std::isnan(frontier_tol) || std::isnan(prune_tol))
+    return fail(PR_EINVAL, "tolerances must not be NaN");
+  if ((rc = check_edges(deletions, "deletions"))) return rc;
+  if ((rc = check_edges(insertions, "insertions"))) return rc;
+  if (deletions && deletions->count > 0 && !deletions->dst)
+    return fail(PR_EINVAL, "deletions.dst is NULL");
+  std::lock_guard<std::mutex> lock(g_mu);
+  if (mode == PR_MODE_ND) return run_static(csr_new, alpha, tol, max_iter, ranks_prev, ranks_out);
+  return run_dynamic_frontier(csr_new, deletions, insertions, ranks_prev, alpha, tol,
+                              frontier_tol, prune_tol, max_iter, mode == PR_MODE_DFP, ranks_out);
+}
+
+int pr_dfp(const pr_csr *csr_old, const pr_csr *csr_new, const pr_edges *deletions,
+           const pr_edges *insertions, const double *ranks_prev, double alpha, double tol,
+           double frontier_tol, double prune_tol, double *ranks_out) {
+  return pr_dfp_ex(csr_old, csr_new, deletions, insertions, ranks_prev, alpha, tol, frontier_tol,
+                   prune_tol, PR_MAX_ITERATIONS, PR_MODE_DFP, ranks_out);
+}
+
+int pr_validate_csr(const pr_csr *g) {
+  reset_stats();
+  int rc = check_csr(g, false);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lock(g_mu);
+  hipStream_t s = t_stream;
+  Workspace *wp = nullptr;
+  if ((rc = get_ws(1, &wp))) return rc;
+  Workspace &w = *wp;
+  int *err = w.counts;  // reuse a device int
+  const int n = g->n, nb = (n + kBlock - 1) / kBlock;
+  HIP_TRY(hipMemsetAsync(err, 0, sizeof(int), s));
+  hipLaunchKernelGGL(k_validate_offsets, dim3(nb), dim3(kBlock), 0, s, g->in_offsets, n, g->m,
+                     err, 1);
+  hipLaunchKernelGGL(k_validate_offsets, dim3(nb), dim3(kBlock), 0, s, g->out_offsets, n, g->m,
+                     err, 16);
+  LAUNCH_TRY();
+  HIP_TRY(hipMemcpyAsync(w.host_counts, err, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  int e = w.host_counts[0];
+  if (e & 1) return fail(PR_EGRAPH, "in_offsets: not 0 .. m non-decreasing");
+  if (e & 16) return fail(PR_EGRAPH, "out_offsets: not 0 .. m non-decreasing");
+  hipLaunchKernelGGL(k_validate_rows, dim3(nb), dim3(kBlock), 0, s, g->in_offsets, g->in_sources,
+                     n, err, 0);
+  if (g->out_targets)
+    hipLaunchKernelGGL(k_validate_rows, dim3(nb), dim3(kBlock), 0, s, g->out_offsets,
+                       g->out_targets, n, err, 4);
+  LAUNCH_TRY();
+  HIP_TRY(hipMemcpyAsync(w.host_counts, err, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  e = w.host_counts[0];
+  if (e & 2) return fail(PR_EGRAPH, "in_sources: vertex ID outside [0, n)");
+  if (e & 4) return fail(PR_EGRAPH, "in_sources: a row is not strictly ascending");
+  if (e & 8) return fail(PR_EGRAPH, "in view: a vertex lacks its self-loop");
+  if (e & 32) return fail(PR_EGRAPH, "out_targets: vertex ID outside [0, n)");
+  if (e & 64) return fail(PR_EGRAPH, "out_targets: a row is not strictly ascending");
+  if (e & 128) return fail(PR_EGRAPH, "out view: a vertex lacks its self-loop");
+  return PR_OK;
+}
+
+int pr_set_tuning(const pr_tuning *t) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  if (!t) {
+    g_tuning = default_tuning();
+    return PR_OK;
+  }
+  if (t->lane_max_degree < 0 || t->wave_max_degree < t->lane_max_degree ||
+      t->expand_lane_max_degree < 0 || t->iters_per_sync < 1 || t->iters_per_sync >= kRing)
+    return fail(PR_EINVAL, "tuning field out of range");
+  g_tuning = *t;
+  return PR_OK;
+}
+
+int pr_get_tuning(pr_tuning *t) {
+  if (!t) return fail(PR_EINVAL, "NULL");
+  std::lock_guard<std::mutex> lock(g_mu);
+  *t = g_tuning;
+  return PR_OK;
+}
+
+int pr_last_stats(pr_stats *out) {
+  if (!out) return fail(PR_EINVAL, "NULL");
+  *out = t_stats;
+  return PR_OK;
+}
+
+int pr_set_profiling(int enable) {
+  t_profiling = enable ? 1 : 0;
+  return PR_OK;
+}
+
+void pr_set_stream(void *hip_stream) { t_stream = (hipStream_t)hip_stream; }
+
+const char *pr_last_error(void) { return t_err.c_str(); }
+
+void pr_release(void) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  for (auto &kv : g_ws) {
+    (void)hipSetDevice(kv.first);
+    free_ws(kv.second);
+  }
+  g_ws.clear();
+  (void)hipSetDevice(cur);
+}
+
+}  // extern "C"

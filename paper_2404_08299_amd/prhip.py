@@ -1,0 +1,266 @@
+"""Python binding of libprhip.so (the C ABI in include/prhip.h).
+
+Argument marshalling only: torch provides device memory and the stream, and
+every step of the computation runs in the library's HIP kernels. There is no
+CPU fallback; if the library is missing or no GPU is present the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import warnings
+from dataclasses import dataclass
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+SO_PATH = os.path.join(_PKG, "libprhip.so")
+
+PR_OK, PR_NOT_CONVERGED = 0, 1
+PR_EINVAL, PR_EGRAPH, PR_EBATCH, PR_ENOMEM, PR_EHIP = -1, -2, -3, -4, -5
+MODES = {"dfp": 0, "df": 1, "nd": 2}
+
+ALPHA, TOL, FRONTIER_TOL, PRUNE_TOL, MAX_ITERATIONS = 0.85, 1e-10, 1e-6, 1e-6, 500
+
+
+class PrError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"prhip error {code}: {msg}")
+        self.code = code
+
+
+class PrCsr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int32),
+                ("in_offsets", ctypes.c_void_p), ("in_sources", ctypes.c_void_p),
+                ("out_offsets", ctypes.c_void_p), ("out_targets", ctypes.c_void_p)]
+
+
+class PrEdges(ctypes.Structure):
+    _fields_ = [("src", ctypes.c_void_p), ("dst", ctypes.c_void_p), ("count", ctypes.c_int32)]
+
+
+class PrTuning(ctypes.Structure):
+    _fields_ = [("lane_max_degree", ctypes.c_int32), ("wave_max_degree", ctypes.c_int32),
+                ("expand_lane_max_degree", ctypes.c_int32), ("iters_per_sync", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
+
+
+class PrStats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("final_delta", ctypes.c_double), ("affected_initial", ctypes.c_int64),
+                ("rank_kernel_ms", ctypes.c_double), ("rank_kernel_launches", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("total_ms", ctypes.c_double),
+                ("reserved", ctypes.c_double * 4)]
+
+
+EXPORTED = ["pr_static", "pr_dfp", "pr_dfp_ex", "pr_validate_csr", "pr_set_tuning",
+            "pr_get_tuning", "pr_last_stats", "pr_set_profiling", "pr_set_stream",
+            "pr_last_error", "pr_release"]
+
+_lib = None
+
+
+def load_library(path: str = SO_PATH):
+    """Load libprhip.so and declare its signatures (no GPU needed to load)."""
+    global _lib
+    if _lib is not None and path == SO_PATH:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built: run __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    vp = ctypes.c_void_p
+    d = ctypes.c_double
+    i = ctypes.c_int
+    lib.pr_static.argtypes = [P(PrCsr), d, d, i, vp]
+    lib.pr_dfp.argtypes = [P(PrCsr), P(PrCsr), P(PrEdges), P(PrEdges), vp, d, d, d, d, vp]
+    lib.pr_dfp_ex.argtypes = [P(PrCsr), P(PrCsr), P(PrEdges), P(PrEdges), vp, d, d, d, d, i, i,
+                              vp]
+    lib.pr_validate_csr.argtypes = [P(PrCsr)]
+    lib.pr_set_tuning.argtypes = [P(PrTuning)]
+    lib.pr_get_tuning.argtypes = [P(PrTuning)]
+    lib.pr_last_stats.argtypes = [P(PrStats)]
+    lib.pr_set_profiling.argtypes = [i]
+    lib.pr_set_stream.argtypes = [vp]
+    lib.pr_set_stream.restype = None
+    lib.pr_last_error.argtypes = []
+    lib.pr_last_error.restype = ctypes.c_char_p
+    lib.pr_release.argtypes = []
+    lib.pr_release.restype = None
+    for f in ("pr_static", "pr_dfp", "pr_dfp_ex", "pr_validate_csr", "pr_set_tuning",
+              "pr_get_tuning", "pr_last_stats", "pr_set_profiling"):
+        getattr(lib, f).restype = ctypes.c_int
+    if path == SO_PATH:
+        _lib = lib
+    return lib
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("prhip needs a HIP GPU (torch.cuda.is_available() is False)")
+    return torch
+
+
+def _check(rc: int, lib) -> int:
+    if rc < 0:
+        raise PrError(rc, lib.pr_last_error().decode())
+    if rc == PR_NOT_CONVERGED:
+        warnings.warn("prhip: iteration cap reached before the tolerance", RuntimeWarning,
+                      stacklevel=3)
+    return rc
+
+
+def _bind_stream(lib, torch):
+    lib.pr_set_stream(ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+
+
+class DeviceGraph:
+    """Both CSR views of a graph as int32 device tensors (torch storage)."""
+
+    def __init__(self, n, m, in_offsets, in_sources, out_offsets, out_targets):
+        self.n, self.m = int(n), int(m)
+        self.in_offsets, self.in_sources = in_offsets, in_sources
+        self.out_offsets, self.out_targets = out_offsets, out_targets
+
+    @staticmethod
+    def from_host(g, device="cuda") -> "DeviceGraph":
+        torch = _torch()
+
+        def t(a):
+            return torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).to(device)
+
+        return DeviceGraph(g.n, g.m, t(g.in_offsets), t(g.in_sources), t(g.out_offsets),
+                           t(g.out_targets))
+
+    def csr(self) -> PrCsr:
+        def p(x):
+            return None if x is None else x.data_ptr()
+
+        return PrCsr(self.n, self.m, p(self.in_offsets), p(self.in_sources), p(self.out_offsets),
+                     p(self.out_targets))
+
+
+class DeviceBatch:
+    """A batch update (deletions src/dst, insertions src/dst) on the device."""
+
+    def __init__(self, del_src, del_dst, ins_src, ins_dst):
+        self.del_src, self.del_dst, self.ins_src, self.ins_dst = del_src, del_dst, ins_src, ins_dst
+
+    @staticmethod
+    def from_host(b, device="cuda") -> "DeviceBatch":
+        torch = _torch()
+
+        def t(a):
+            return torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).to(device)
+
+        return DeviceBatch(t(b.del_src), t(b.del_dst), t(b.ins_src), t(b.ins_dst))
+
+    def edges(self):
+        def e(s, d):
+            n = int(s.numel())
+            return PrEdges(s.data_ptr() if n else None, d.data_ptr() if (d is not None and n) else None, n)
+
+        return e(self.del_src, self.del_dst), e(self.ins_src, self.ins_dst)
+
+
+@dataclass
+class Result:
+    ranks: object  # torch float64 tensor on the device
+    status: int
+    iterations: int
+    converged: bool
+    final_delta: float
+    stats: dict
+
+
+def last_stats() -> dict:
+    lib = load_library()
+    s = PrStats()
+    lib.pr_last_stats(ctypes.byref(s))
+    return dict(iterations=s.iterations, converged=bool(s.converged), final_delta=s.final_delta,
+                affected_initial=s.affected_initial, rank_kernel_ms=s.rank_kernel_ms,
+                rank_kernel_launches=s.rank_kernel_launches, total_ms=s.total_ms)
+
+
+def _result(rc, out):
+    st = last_stats()
+    return Result(out, rc, st["iterations"], st["converged"], st["final_delta"], st)
+
+
+def static(g: DeviceGraph, alpha=ALPHA, tol=TOL, max_iter=MAX_ITERATIONS, out=None) -> Result:
+    """Static PageRank (Alg. 1, Eq. 1) through pr_static."""
+    torch = _torch()
+    lib = load_library()
+    if out is None:
+        out = torch.empty(g.n, dtype=torch.float64, device=g.in_offsets.device)
+    assert out.dtype == torch.float64 and out.is_contiguous() and out.numel() == g.n
+    _bind_stream(lib, torch)
+    csr = g.csr()
+    rc = _check(lib.pr_static(ctypes.byref(csr), alpha, tol, max_iter, out.data_ptr()), lib)
+    return _result(rc, out)
+
+
+def dfp(g_new: DeviceGraph, batch: DeviceBatch, ranks_prev, alpha=ALPHA, tol=TOL,
+        frontier_tol=FRONTIER_TOL, prune_tol=PRUNE_TOL, max_iter=MAX_ITERATIONS, mode="dfp",
+        out=None, g_old: DeviceGraph | None = None) -> Result:
+    """DF-P (default), DF or ND update through pr_dfp / pr_dfp_ex."""
+    torch = _torch()
+    lib = load_library()
+    if out is None:
+        out = torch.empty(g_new.n, dtype=torch.float64, device=g_new.in_offsets.device)
+    assert ranks_prev.dtype == torch.float64 and ranks_prev.is_contiguous()
+    assert out.dtype == torch.float64 and out.is_contiguous() and out.numel() == g_new.n
+    _bind_stream(lib, torch)
+    csr_new = g_new.csr()
+    csr_old = g_old.csr() if g_old is not None else None
+    de, ie = batch.edges()
+    if mode == "dfp" and max_iter == MAX_ITERATIONS:
+        rc = lib.pr_dfp(ctypes.byref(csr_old) if csr_old else None, ctypes.byref(csr_new),
+                        ctypes.byref(de), ctypes.byref(ie), ranks_prev.data_ptr(), alpha, tol,
+                        frontier_tol, prune_tol, out.data_ptr())
+    else:
+        rc = lib.pr_dfp_ex(ctypes.byref(csr_old) if csr_old else None, ctypes.byref(csr_new),
+                           ctypes.byref(de), ctypes.byref(ie), ranks_prev.data_ptr(), alpha, tol,
+                           frontier_tol, prune_tol, max_iter, MODES[mode], out.data_ptr())
+    _check(rc, lib)
+    return _result(rc, out)
+
+
+def validate(g: DeviceGraph) -> None:
+    """Raises PrError(PR_EGRAPH) if the graph breaks the input contract."""
+    torch = _torch()
+    lib = load_library()
+    _bind_stream(lib, torch)
+    csr = g.csr()
+    _check(lib.pr_validate_csr(ctypes.byref(csr)), lib)
+
+
+def get_tuning() -> dict:
+    lib = load_library()
+    t = PrTuning()
+    lib.pr_get_tuning(ctypes.byref(t))
+    return dict(lane_max_degree=t.lane_max_degree, wave_max_degree=t.wave_max_degree,
+                expand_lane_max_degree=t.expand_lane_max_degree, iters_per_sync=t.iters_per_sync)
+
+
+def set_tuning(**kw) -> None:
+    """Update fields of the process-wide tuning; set_tuning() with no
+    arguments restores the defaults."""
+    lib = load_library()
+    if not kw:
+        _check(lib.pr_set_tuning(None), lib)
+        return
+    cur = get_tuning()
+    cur.update(kw)
+    t = PrTuning(cur["lane_max_degree"], cur["wave_max_degree"], cur["expand_lane_max_degree"],
+                 cur["iters_per_sync"])
+    _check(lib.pr_set_tuning(ctypes.byref(t)), lib)
+
+
+def set_profiling(enable: bool) -> None:
+    load_library().pr_set_profiling(1 if enable else 0)
+
+
+def release() -> None:
+    load_library().pr_release()

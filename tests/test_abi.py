@@ -1,0 +1,96 @@
+"""The C-ABI library loads and exports every symbol include/prhip.h declares,
+and argument validation answers before any HIP call (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2404_08299_amd import prhip
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "prhip.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pr_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return prhip.load_library()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 11
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(prhip.EXPORTED) == sorted(names)
+
+
+def test_status_codes_match_header():
+    text = open(HEADER).read()
+    for name, val in [("PR_OK", 0), ("PR_NOT_CONVERGED", 1), ("PR_EINVAL", -1),
+                      ("PR_EGRAPH", -2), ("PR_EBATCH", -3), ("PR_ENOMEM", -4), ("PR_EHIP", -5)]:
+        m = re.search(r"#define %s \(?(-?\d+)\)?" % name, text)
+        assert m and int(m.group(1)) == val
+        assert getattr(prhip, name) == val
+
+
+def test_struct_layouts():
+    assert ctypes.sizeof(prhip.PrCsr) == 8 + 4 * 8
+    assert ctypes.sizeof(prhip.PrEdges) == 24
+    assert ctypes.sizeof(prhip.PrTuning) == 32
+    assert ctypes.sizeof(prhip.PrStats) == 4 + 4 + 8 + 8 + 8 + 4 + 4 + 8 + 32
+
+
+def test_argument_errors_before_hip(lib):
+    assert lib.pr_static(None, 0.85, 1e-10, 500, None) == prhip.PR_EINVAL
+    assert b"NULL" in lib.pr_last_error()
+    csr = prhip.PrCsr(0, 0, None, None, None, None)
+    assert lib.pr_static(ctypes.byref(csr), 0.85, 1e-10, 500, None) == prhip.PR_EINVAL
+    csr = prhip.PrCsr(4, 4, 8, 8, 8, None)  # non-NULL fake pointers: never dereferenced
+    for alpha, tol, it in [(0.0, 1e-10, 5), (1.0, 1e-10, 5), (0.85, -1.0, 5), (0.85, 1e-10, 0),
+                           (float("nan"), 1e-10, 5)]:
+        assert lib.pr_static(ctypes.byref(csr), alpha, tol, it, ctypes.c_void_p(8)) == prhip.PR_EINVAL
+    # pr_dfp needs out_targets
+    assert lib.pr_dfp(None, ctypes.byref(csr), None, None, ctypes.c_void_p(8), 0.85, 1e-10, 1e-6,
+                      1e-6, ctypes.c_void_p(8)) == prhip.PR_EINVAL
+    csr2 = prhip.PrCsr(4, 4, 8, 8, 8, 8)
+    bad = prhip.PrEdges(None, None, 3)
+    assert lib.pr_dfp(None, ctypes.byref(csr2), ctypes.byref(bad), None, ctypes.c_void_p(8), 0.85,
+                      1e-10, 1e-6, 1e-6, ctypes.c_void_p(8)) == prhip.PR_EINVAL
+    assert lib.pr_dfp_ex(None, ctypes.byref(csr2), None, None, ctypes.c_void_p(8), 0.85, 1e-10,
+                         1e-6, 1e-6, 500, 7, ctypes.c_void_p(8)) == prhip.PR_EINVAL
+
+
+def test_tuning_validation(lib):
+    t = prhip.PrTuning()
+    assert lib.pr_get_tuning(ctypes.byref(t)) == 0
+    default = (t.lane_max_degree, t.wave_max_degree, t.expand_lane_max_degree, t.iters_per_sync)
+    bad = prhip.PrTuning(10, 5, 3, 1)  # lane > wave
+    assert lib.pr_set_tuning(ctypes.byref(bad)) == prhip.PR_EINVAL
+    bad = prhip.PrTuning(1, 5, 3, 0)
+    assert lib.pr_set_tuning(ctypes.byref(bad)) == prhip.PR_EINVAL
+    good = prhip.PrTuning(4, 64, 8, 3)
+    assert lib.pr_set_tuning(ctypes.byref(good)) == 0
+    assert prhip.get_tuning()["wave_max_degree"] == 64
+    assert lib.pr_set_tuning(None) == 0
+    t2 = prhip.PrTuning()
+    lib.pr_get_tuning(ctypes.byref(t2))
+    assert (t2.lane_max_degree, t2.wave_max_degree, t2.expand_lane_max_degree,
+            t2.iters_per_sync) == default
+
+
+def test_binding_has_no_cpu_fallback():
+    """The product modules never import the oracle."""
+    pkg = os.path.join(ROOT, "paper_2404_08299_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
+                assert "liboracle" not in text, f

@@ -1,0 +1,243 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs. Bars: L-infinity <= 1e-9 at tol = 1e-10 for Static and
+for DF/DF-P against the oracle's DF/DF-P; when every vertex is in the
+lane-per-vertex class the GPU sums in the oracle's order and the results are
+bit-identical."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2404_08299_amd import graphgen as gg
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2404_08299_amd import prhip  # noqa: E402
+
+ALL_LANE = dict(lane_max_degree=1 << 30, wave_max_degree=1 << 30, expand_lane_max_degree=1 << 30)
+ALL_CLASSES = dict(lane_max_degree=2, wave_max_degree=12, expand_lane_max_degree=2)
+
+
+@pytest.fixture(autouse=True)
+def default_tuning():
+    prhip.set_tuning()
+    yield
+    prhip.set_tuning()
+
+
+def dev(g):
+    return prhip.DeviceGraph.from_host(g)
+
+
+def gpu_static(g, **kw):
+    r = prhip.static(dev(g), **kw)
+    return r.ranks.cpu().numpy(), r
+
+
+def ora_static(g, **kw):
+    s, d = g.edges()
+    return oracle.static(g.n, s, d, **kw)
+
+
+# ------------------------------------------------------------------ Static
+def test_static_rmat14_vs_oracle():
+    """R-MAT scale 14, edge factor 8, seed 1 (the small configuration)."""
+    g = gg.rmat_graph(14, 8, seed=1)
+    r, res = gpu_static(g)
+    o = ora_static(g)
+    print(f"rmat14 n={g.n} m={g.m} gpu iters={res.iterations} oracle iters={o.iters}")
+    assert res.converged and res.status == prhip.PR_OK
+    assert np.abs(r - o.ranks).max() <= 1e-9
+    assert abs(res.iterations - o.iters) <= 1
+
+
+def test_static_all_lane_bitwise():
+    prhip.set_tuning(**ALL_LANE)
+    for g in (gg.rmat_graph(12, 8, seed=1), gg.rmat_graph(10, 16, seed=3, scramble=False)):
+        r, res = gpu_static(g)
+        o = ora_static(g)
+        assert res.iterations == o.iters
+        assert np.array_equal(r, o.ranks)
+
+
+@pytest.mark.parametrize("tuning", [ALL_CLASSES, dict(lane_max_degree=0, wave_max_degree=0),
+                                    dict(lane_max_degree=8, wave_max_degree=200)])
+def test_static_every_class(tuning):
+    prhip.set_tuning(**tuning)
+    g = gg.rmat_graph(13, 8, seed=2)
+    r, res = gpu_static(g)
+    o = ora_static(g)
+    assert np.abs(r - o.ranks).max() <= 1e-9
+    assert abs(res.iterations - o.iters) <= 1
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 255, 257, 1023, 1025, 4097, 70001])
+def test_static_ragged_sizes(n):
+    scale = max(1, int(np.ceil(np.log2(max(n, 2)))))
+    g = gg.rmat_graph(scale, 6, seed=n, n=n)
+    assert g.n == n
+    r, res = gpu_static(g)
+    o = ora_static(g)
+    assert np.abs(r - o.ranks).max() <= 1e-9
+
+
+def test_static_closed_forms():
+    a = 0.85
+    # in-star with a hub above every lane/wave threshold (workgroup class)
+    k = 6000
+    g = gg.from_edges(k + 1, np.arange(1, k + 1, dtype=np.int32), np.zeros(k, np.int32))
+    r, res = gpu_static(g, tol=1e-14, max_iter=2000)
+    n = k + 1
+    rl = 2 * (1 - a) / (n * (2 - a))
+    assert abs(r[0] - (1 - k * rl)) <= 1e-12 and np.abs(r[1:] - rl).max() <= 1e-15
+    # out-star: the center has out-degree k+1 (wavefront/workgroup class in marking)
+    g = gg.from_edges(k + 1, np.zeros(k, np.int32), np.arange(1, k + 1, dtype=np.int32))
+    r, _ = gpu_static(g, tol=1e-14, max_iter=2000)
+    rc = (1 - a) / (n * (1 - a / (k + 1)))
+    assert abs(r[0] - rc) <= 1e-15
+    # directed cycle: converges in one iteration to 1/n
+    g = gg.from_edges(1000, np.arange(1000, dtype=np.int32), (np.arange(1000, dtype=np.int32) + 1) % 1000)
+    r, res = gpu_static(g, tol=1e-15)
+    assert res.iterations == 1 and np.abs(r - 1e-3).max() <= 1e-17
+
+
+def test_static_max_iter_and_determinism():
+    g = gg.rmat_graph(12, 8, seed=5)
+    with pytest.warns(RuntimeWarning):
+        r, res = gpu_static(g, tol=0.0, max_iter=3)
+    assert res.status == prhip.PR_NOT_CONVERGED and res.iterations == 3
+    o = ora_static(g, tol=0.0, max_iter=3)
+    assert np.abs(r - o.ranks).max() <= 1e-15
+    a, _ = gpu_static(g)
+    b, _ = gpu_static(g)
+    assert np.array_equal(a, b)
+
+
+def test_static_threshold_invariance():
+    g = gg.rmat_graph(13, 8, seed=7)
+    outs = []
+    for t in (dict(), ALL_LANE, ALL_CLASSES, dict(lane_max_degree=16, wave_max_degree=64)):
+        prhip.set_tuning()
+        prhip.set_tuning(**t)
+        outs.append(gpu_static(g, tol=1e-13, max_iter=1000)[0])
+    for o in outs[1:]:
+        assert np.abs(o - outs[0]).max() <= 1e-13
+
+
+def test_static_iters_per_sync():
+    g = gg.rmat_graph(11, 8, seed=9)
+    base, rb = gpu_static(g)
+    for k in (1, 3, 7):
+        prhip.set_tuning(iters_per_sync=k)
+        r, res = gpu_static(g)
+        assert res.iterations == rb.iterations and np.array_equal(r, base)
+
+
+def test_validate():
+    g = gg.rmat_graph(10, 8, seed=1)
+    prhip.validate(dev(g))
+    # drop vertex 5's self-loop from the in view
+    d = dev(g)
+    row = g.in_sources[g.in_offsets[5]:g.in_offsets[6]].copy()
+    assert 5 in row
+    bad = g.in_sources.copy()
+    pos = g.in_offsets[5] + int(np.nonzero(row == 5)[0][0])
+    bad[pos] = (5 + 1) % g.n if (5 + 1) % g.n not in row else 0
+    d.in_sources = torch.from_numpy(bad).cuda()
+    with pytest.raises(prhip.PrError) as e:
+        prhip.validate(d)
+    assert e.value.code in (prhip.PR_EGRAPH,)
+    d2 = dev(g)
+    off = g.in_offsets.copy()
+    off[-1] += 1
+    d2.in_offsets = torch.from_numpy(off).cuda()
+    with pytest.raises(prhip.PrError):
+        prhip.validate(d2)
+
+
+# ------------------------------------------------------------------ DF / DF-P
+def dynamic_case(scale=12, ef=8, frac=1e-3, seed=1):
+    g0 = gg.rmat_graph(scale, ef, seed=seed)
+    b = gg.random_batch(g0, gg.batch_size_for(g0, frac), seed=seed + 10)
+    g1 = gg.apply_batch(g0, b)
+    prev = oracle.static(g0.n, *g0.edges()).ranks
+    return g0, g1, b, prev
+
+
+def gpu_dfp(g1, b, prev, mode="dfp", **kw):
+    p = torch.from_numpy(prev).cuda()
+    r = prhip.dfp(dev(g1), prhip.DeviceBatch.from_host(b), p, mode=mode, **kw)
+    return r.ranks.cpu().numpy(), r
+
+
+@pytest.mark.parametrize("frac", [1e-4, 1e-3, 1e-2])
+def test_dfp_vs_oracle(frac):
+    g0, g1, b, prev = dynamic_case(frac=frac)
+    r, res = gpu_dfp(g1, b, prev)
+    o = oracle.dfp(g1.n, *g1.edges(), b, prev)
+    print(f"frac={frac} batch={b.size} gpu iters={res.iterations} oracle iters={o.iters}")
+    assert res.converged
+    assert np.abs(r - o.ranks).max() <= 1e-9
+    ref = oracle.static(g1.n, *g1.edges(), tol=1e-14, max_iter=5000).ranks
+    assert np.abs(r - ref).max() <= 10 * 1e-6 * ref.max()
+
+
+def test_dfp_all_lane_bitwise():
+    prhip.set_tuning(**ALL_LANE)
+    g0, g1, b, prev = dynamic_case(scale=11, frac=1e-3, seed=4)
+    r, res = gpu_dfp(g1, b, prev)
+    o = oracle.dfp(g1.n, *g1.edges(), b, prev)
+    assert res.iterations == o.iters
+    assert np.array_equal(r, o.ranks)
+
+
+@pytest.mark.parametrize("mode", ["df", "nd"])
+def test_df_nd_vs_oracle(mode):
+    g0, g1, b, prev = dynamic_case(scale=12, frac=1e-3, seed=2)
+    r, res = gpu_dfp(g1, b, prev, mode=mode)
+    if mode == "df":
+        o = oracle.dfp(g1.n, *g1.edges(), b, prev, prune=False)
+    else:
+        o = oracle.static(g1.n, *g1.edges(), init=prev)
+    assert np.abs(r - o.ranks).max() <= 1e-9
+    assert abs(res.iterations - o.iters) <= 1
+
+
+def test_dfp_every_class():
+    prhip.set_tuning(**ALL_CLASSES)
+    g0, g1, b, prev = dynamic_case(scale=13, frac=1e-3, seed=3)
+    r, res = gpu_dfp(g1, b, prev)
+    o = oracle.dfp(g1.n, *g1.edges(), b, prev)
+    assert np.abs(r - o.ranks).max() <= 1e-9
+
+
+def test_dfp_empty_batch_and_inplace():
+    g0, g1, b, prev = dynamic_case(scale=10, frac=1e-3, seed=5)
+    r, res = gpu_dfp(g1, gg.Batch.empty(), prev, tol=0.0)
+    assert res.iterations == 1 and np.array_equal(r, prev)
+    p = torch.from_numpy(prev).cuda()
+    out = prhip.dfp(dev(g1), prhip.DeviceBatch.from_host(b), p, out=p)
+    assert out.ranks.data_ptr() == p.data_ptr()
+    o = oracle.dfp(g1.n, *g1.edges(), b, prev)
+    assert np.abs(p.cpu().numpy() - o.ranks).max() <= 1e-9
+
+
+def test_dfp_affected_count_and_bad_batch():
+    g0, g1, b, prev = dynamic_case(scale=11, frac=1e-3, seed=6)
+    prhip.set_profiling(True)
+    try:
+        r, res = gpu_dfp(g1, b, prev)
+    finally:
+        prhip.set_profiling(False)
+    o = oracle.dfp(g1.n, *g1.edges(), b, prev)
+    assert res.stats["affected_initial"] == o.stats["affected_initial"]
+    assert res.stats["rank_kernel_launches"] == res.iterations
+    assert res.stats["rank_kernel_ms"] > 0
+    bad = gg.Batch(b.del_src.copy(), b.del_dst.copy(), b.ins_src.copy(), b.ins_dst.copy())
+    bad.del_dst[0] = g1.n + 5
+    with pytest.raises(prhip.PrError) as e:
+        gpu_dfp(g1, bad, prev)
+    assert e.value.code == prhip.PR_EBATCH
