@@ -57,6 +57,8 @@ def _bind(lib):
     c = ctypes
     lib.oracle_static.argtypes = [c.c_int32, c.c_int64, _I32P, _I32P, c.c_double, c.c_double,
                                   c.c_int32, _F64P, _F64P, _I32P, _F64P]
+    lib.oracle_static_csr.argtypes = [c.c_int32, _I32P, _I32P, _I32P, c.c_double, c.c_double,
+                                      c.c_int32, _F64P, _I32P, _F64P, _F64P]
     lib.oracle_dfp.argtypes = [c.c_int32, c.c_int64, _I32P, _I32P, c.c_int64, _I32P, _I32P,
                                c.c_int64, _I32P, _F64P, c.c_double, c.c_double, c.c_double,
                                c.c_double, c.c_int32, c.c_int32, _F64P, _I32P, _F64P, _I64P,
@@ -67,7 +69,7 @@ def _bind(lib):
                                     c.c_double, c.c_double, c.c_int32, _F64P, _F64P, _I32P, _F64P]
     lib.oracle_adjoint.argtypes = [c.c_int32, c.c_int64, _I32P, _I32P, _F64P, _F64P, _F64P,
                                    c.c_double, c.c_double, c.c_int32, _F64P, _F64P, _F64P, _I32P]
-    for f in (lib.oracle_static, lib.oracle_dfp, lib.oracle_ppr, lib.oracle_weighted,
+    for f in (lib.oracle_static, lib.oracle_static_csr, lib.oracle_dfp, lib.oracle_ppr, lib.oracle_weighted,
               lib.oracle_adjoint):
         f.restype = c.c_int
     return lib
@@ -128,6 +130,24 @@ def static(n, src, dst, alpha=ALPHA, tol=TOL, max_iter=MAX_ITERATIONS, init=None
                            r.ctypes.data_as(_F64P), ctypes.byref(it), ctypes.byref(d))
     _check(rc, "oracle_static")
     return Result(r, it.value, d.value, rc)
+
+
+def static_csr(n, in_offsets, in_sources, out_offsets, alpha=ALPHA, tol=TOL,
+               max_iter=MAX_ITERATIONS, lib=None):
+    """Alg. 1 over a given in-CSR (rows ascending). Returns (Result, seconds
+    spent in the iteration loop)."""
+    lib = lib or load()
+    io, pio = _i32(in_offsets)
+    isrc, pis = _i32(in_sources)
+    oo, poo = _i32(out_offsets)
+    r = np.empty(n, np.float64)
+    it = ctypes.c_int32(0)
+    d = ctypes.c_double(0.0)
+    sec = ctypes.c_double(0.0)
+    rc = lib.oracle_static_csr(n, pio, pis, poo, alpha, tol, max_iter, r.ctypes.data_as(_F64P),
+                               ctypes.byref(it), ctypes.byref(d), ctypes.byref(sec))
+    _check(rc, "oracle_static_csr")
+    return Result(r, it.value, d.value, rc), sec.value
 
 
 def dfp(n, src, dst, batch, ranks_prev, alpha=ALPHA, tol=TOL, tau_f=TAU_F, tau_p=TAU_P,

@@ -28,10 +28,12 @@
  * the textbook personalised PageRank iteration and its transposed fixed
  * point (derivation in the adjoint function's comment).
  */
+#define _POSIX_C_SOURCE 199309L
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <time.h>
 
 enum { OR_OK = 0, OR_NOT_CONVERGED = 1, OR_EINVAL = -1, OR_ENOMEM = -4 };
 
@@ -114,6 +116,29 @@ static double linf_delta(int32_t n, const double *x, const double *y) {
   return d;
 }
 
+/* Adjacency over a caller's in-CSR (int32, rows ascending) and out-offsets;
+ * the in-source array is borrowed, not copied. */
+static int adj_wrap_csr(adjacency *a, int32_t n, const int32_t *in_off, const int32_t *in_src,
+                        const int32_t *out_off) {
+  memset(a, 0, sizeof(*a));
+  if (n <= 0 || !in_off || !in_src || !out_off) return OR_EINVAL;
+  a->n = n;
+  a->m = in_off[n];
+  a->in_off = malloc(sizeof(int64_t) * ((size_t)n + 1));
+  a->out_deg = malloc(sizeof(int32_t) * (size_t)n);
+  if (!a->in_off || !a->out_deg) { free(a->in_off); free(a->out_deg); return OR_ENOMEM; }
+  for (int32_t v = 0; v <= n; ++v) a->in_off[v] = in_off[v];
+  for (int32_t u = 0; u < n; ++u) a->out_deg[u] = out_off[u + 1] - out_off[u];
+  a->in_src = (int32_t *)in_src;
+  return OR_OK;
+}
+
+static double now_seconds(void) {
+  struct timespec ts;
+  clock_gettime(CLOCK_MONOTONIC, &ts);
+  return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
+
 /*
  * Static PageRank: Alg. 1 with the update of Eq. 1.
  * R = R_new = 1/|V| (or `init` when given: the Naive-dynamic variant of
@@ -121,29 +146,28 @@ static double linf_delta(int32_t n, const double *x, const double *y) {
  * from R for every vertex, Delta = max_v |R_new[v] - R[v]|, swaps, and stops
  * when Delta <= tol, at most max_iter iterations.
  * Requires |out(u)| >= 1 for every u (the self-loop convention).
+ * `seconds` (may be NULL) receives the wall time of the iteration loop.
  */
-int oracle_static(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, double alpha,
-                  double tol, int32_t max_iter, const double *init, double *ranks,
-                  int32_t *iters, double *delta) {
-  if (!(alpha > 0.0 && alpha < 1.0) || !(tol >= 0.0) || max_iter <= 0 || !ranks) return OR_EINVAL;
-  adjacency a;
-  int rc = adj_build(&a, n, m, src, dst);
-  if (rc) return rc;
+static int static_iterate(const adjacency *a, double alpha, double tol, int32_t max_iter,
+                          const double *init, double *ranks, int32_t *iters, double *delta,
+                          double *seconds) {
+  const int32_t n = a->n;
   for (int32_t u = 0; u < n; ++u)
-    if (a.out_deg[u] == 0) { adj_free(&a); return OR_EINVAL; }
+    if (a->out_deg[u] == 0) return OR_EINVAL;
   double *R = malloc(sizeof(double) * (size_t)n), *Rn = malloc(sizeof(double) * (size_t)n);
-  if (!R || !Rn) { free(R); free(Rn); adj_free(&a); return OR_ENOMEM; }
+  if (!R || !Rn) { free(R); free(Rn); return OR_ENOMEM; }
   for (int32_t v = 0; v < n; ++v) R[v] = Rn[v] = init ? init[v] : 1.0 / (double)n;
   const double C0 = (1.0 - alpha) / (double)n;
   int32_t it = 0;
   double d = 0.0;
   int converged = 0;
+  const double t0 = now_seconds();
   while (it < max_iter) {
     for (int32_t v = 0; v < n; ++v) {
       double c = 0.0;
-      for (int64_t i = a.in_off[v]; i < a.in_off[v + 1]; ++i) {
-        int32_t u = a.in_src[i];
-        c = c + R[u] / (double)a.out_deg[u];
+      for (int64_t i = a->in_off[v]; i < a->in_off[v + 1]; ++i) {
+        int32_t u = a->in_src[i];
+        c = c + R[u] / (double)a->out_deg[u];
       }
       Rn[v] = C0 + alpha * c;
     }
@@ -152,11 +176,41 @@ int oracle_static(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, 
     ++it;
     if (d <= tol) { converged = 1; break; }
   }
+  if (seconds) *seconds = now_seconds() - t0;
   memcpy(ranks, R, sizeof(double) * (size_t)n);
   if (iters) *iters = it;
   if (delta) *delta = d;
-  free(R); free(Rn); adj_free(&a);
+  free(R); free(Rn);
   return converged ? OR_OK : OR_NOT_CONVERGED;
+}
+
+int oracle_static(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, double alpha,
+                  double tol, int32_t max_iter, const double *init, double *ranks,
+                  int32_t *iters, double *delta) {
+  if (!(alpha > 0.0 && alpha < 1.0) || !(tol >= 0.0) || max_iter <= 0 || !ranks) return OR_EINVAL;
+  adjacency a;
+  int rc = adj_build(&a, n, m, src, dst);
+  if (rc) return rc;
+  rc = static_iterate(&a, alpha, tol, max_iter, init, ranks, iters, delta, NULL);
+  adj_free(&a);
+  return rc;
+}
+
+/* Static PageRank over a given in-CSR (rows ascending by source) and
+ * out-offsets, with the wall time of the iteration loop in `seconds`. Same
+ * iteration as oracle_static; used to time the oracle without its own
+ * adjacency construction. */
+int oracle_static_csr(int32_t n, const int32_t *in_off, const int32_t *in_src,
+                      const int32_t *out_off, double alpha, double tol, int32_t max_iter,
+                      double *ranks, int32_t *iters, double *delta, double *seconds) {
+  if (!(alpha > 0.0 && alpha < 1.0) || !(tol >= 0.0) || max_iter <= 0 || !ranks) return OR_EINVAL;
+  adjacency a;
+  int rc = adj_wrap_csr(&a, n, in_off, in_src, out_off);
+  if (rc) return rc;
+  rc = static_iterate(&a, alpha, tol, max_iter, NULL, ranks, iters, delta, seconds);
+  free(a.in_off);
+  free(a.out_deg);
+  return rc;
 }
 
 /* expandAffected of Alg. 5: for each u with delta_N[u], mark every v in out(u). */

@@ -18,14 +18,13 @@ MUTANTS = {
     "eq2_sign": ("1.0 / (1.0 - alpha / dv)", "1.0 / (1.0 + alpha / dv)"),
     "frontier_flag_literal_zero": ("if (rel > tau_f) dN[v] = 1;", "if (rel > tau_f) dN[v] = 0;"),
     "no_carry_forward": ("if (!dV[v]) { Rn[v] = R[v]; continue; }", "if (!dV[v]) { continue; }"),
-    "teleport_not_divided_by_n": ("const double C0 = (1.0 - alpha) / (double)n;\n  int32_t it = 0;\n  double d = 0.0;\n  int converged = 0;\n  while",
-                                  "const double C0 = (1.0 - alpha);\n  int32_t it = 0;\n  double d = 0.0;\n  int converged = 0;\n  while"),
+    "teleport_not_divided_by_n": ("const double C0 = (1.0 - alpha) / (double)n;\n  int32_t it = 0;\n  double d = 0.0;\n  int converged = 0;\n  const double t0",
+                                  "const double C0 = (1.0 - alpha);\n  int32_t it = 0;\n  double d = 0.0;\n  int converged = 0;\n  const double t0"),
     "static_no_damping": ("Rn[v] = C0 + alpha * c;\n    }", "Rn[v] = C0 + c;\n    }"),
     "in_lists_transposed": ("a->in_src[i] = src[a->in_eid[i]];", "a->in_src[i] = dst[a->in_eid[i]];"),
     "outdeg_from_in_lists": ("a->out_deg[u] = (int32_t)(a->out_off[u + 1] - a->out_off[u]);",
                              "a->out_deg[u] = (int32_t)(a->in_off[u + 1] - a->in_off[u]);"),
-    "stop_strict_less": ("if (d <= tol) { converged = 1; break; }\n  }\n  memcpy(ranks, R, sizeof(double) * (size_t)n);\n  if (iters) *iters = it;\n  if (delta) *delta = d;\n  free(R); free(Rn); adj_free(&a);",
-                         "if (d < tol) { converged = 1; break; }\n  }\n  memcpy(ranks, R, sizeof(double) * (size_t)n);\n  if (iters) *iters = it;\n  if (delta) *delta = d;\n  free(R); free(Rn); adj_free(&a);"),
+    "stop_strict_less": ("if (d <= tol) { converged = 1; break; }\n  }\n  if (seconds)", "if (d < tol) { converged = 1; break; }\n  }\n  if (seconds)"),
     "dfp_stop_strict_less": ("if (d <= tol) { converged = 1; break; }\n    expand_affected", "if (d < tol) { converged = 1; break; }\n    expand_affected"),
     "linf_is_l1": ("if (t > d) d = t;", "d += t;"),
     "deletion_target_unmarked": ("dN[del_src[i]] = 1; dV[del_dst[i]] = 1;", "dN[del_src[i]] = 1;"),
