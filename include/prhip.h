@@ -137,22 +137,31 @@ int pr_validate_csr(const pr_csr *csr);
  *   lane_max_degree    in-degree <= this: one lane per vertex (Alg. 3,
  *                      thread-per-vertex kernel)
  *   wave_max_degree    in-degree <= this (and above lane_max_degree): one
- *                      64-lane wavefront per vertex; above it: one 256-thread
- *                      workgroup per vertex (Alg. 3, block-per-vertex kernel)
+ *                      64-lane wavefront per vertex (Alg. 3, block-per-vertex
+ *                      kernel); above it: the split class (hub_chunk_edges)
  *   expand_lane_max_degree  out-degree <= this: one lane marks the
- *                      neighbours, else one wavefront (Alg. 5)
+ *                      neighbours; up to wave_max_degree one wavefront;
+ *                      above it one workgroup per chunk of out-edges (Alg. 5)
  *   iters_per_sync     iterations in flight before the host reads a
  *                      convergence flag (1 = read after every iteration;
  *                      with k > 1 the host waits on iteration i-k+1 while
  *                      later ones run, and iterations enqueued after
  *                      convergence exit at once on the device)
+ *   hub_chunk_edges    edges per chunk of the split class: a vertex with
+ *                      degree above wave_max_degree is cut into chunks of
+ *                      this many edges, one workgroup each; their partial
+ *                      sums are added in chunk order (0 = default 4096)
+ *   grid_blocks        workgroups of the fixed-size launches that stride over
+ *                      the work (0 = eight per compute unit)
  */
 typedef struct pr_tuning {
   int32_t lane_max_degree;
   int32_t wave_max_degree;
   int32_t expand_lane_max_degree;
   int32_t iters_per_sync;
-  int32_t reserved[4];
+  int32_t hub_chunk_edges;
+  int32_t grid_blocks;
+  int32_t reserved[2];
 } pr_tuning;
 
 /* Set (NULL = defaults) or read the process-wide tuning. PR_EINVAL if a

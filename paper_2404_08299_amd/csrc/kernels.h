@@ -9,22 +9,33 @@
 //                  of the vertices updated in this iteration
 //   dV, dN, cv:    uint8 flags: affected, neighbours-to-mark, updated-now
 //   hi:            partition output, vertices of the wavefront class then
-//                  of the workgroup class, each ascending (Alg. 4)
+//                  of the split class, each ascending (Alg. 4)
+//   hub_start, chunk_hub, hub_part: the split class cut into chunks of a
+//                  fixed number of edges, and one partial sum per chunk
 //
-// Vertex classes by degree (Alg. 4 with two thresholds): lane-per-vertex
-// (deg <= t1), wavefront-per-vertex (t1 < deg <= t2), workgroup-per-vertex
-// (deg > t2). The lane class is not materialised: tiles of 256 consecutive
-// vertex IDs are swept and the lanes whose vertex belongs to another class
-// sit out, which keeps the lane class in ID order (coalesced offsets, rank
-// and flag accesses) without a permutation array.
+// Vertex classes by degree (Alg. 4 with two thresholds):
+//   lane class      deg <= t1        one lane per vertex, sequential sum
+//   wavefront class t1 < deg <= t2   one 64-lane wavefront per vertex
+//   split class     deg > t2         the row is cut into chunks of CH edges;
+//                                    one workgroup per chunk writes a partial
+//                                    sum, a second kernel adds the partials
+//                                    of each vertex in chunk order
+// The lane class is not materialised: 256-vertex ID tiles are swept and the
+// lanes whose vertex is in another class sit out, so the lane class stays in
+// ID order (coalesced offsets, rank and flag accesses) without a permutation.
 //
-// One fused launch per rank update holds three block ranges:
-//   [0, nb2)            one workgroup per workgroup-class vertex
-//   [nb2, nb2+nb1)      four wavefronts, one vertex each (wavefront class)
-//   [nb2+nb1, ...)      one 256-vertex ID tile, one lane per vertex
-// so the long rows are dispatched first. Every block writes the maximum
-// |R_new - R| of its vertices to partials[block]; a second small kernel
-// reduces them (Sec. 4.1, convergence detection).
+// Launch shape: a fixed grid of B workgroups (about eight per compute unit)
+// strides over the three classes, so every workgroup gets a similar mix of
+// work whatever the class sizes, the class counts never travel to the host,
+// and a launch made after convergence exits in a few microseconds. Each
+// workgroup writes the maximum |R_new - R| of its vertices to
+// partials[blockIdx]; a one-workgroup kernel reduces the B + F partials
+// (Sec. 4.1, convergence detection).
+//
+// Candidates of the wavefront and split classes are checked lane-parallel
+// (a ballot over 64 candidates, or one chunk per thread) and only the
+// selected ones are processed cooperatively, so sweeping those lists in DF-P
+// costs one round of loads per 64 candidates.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -37,6 +48,7 @@ constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kPartTile = 1024;  // vertices per partition block
 constexpr int kFinalBlock = 1024;
+constexpr int kHubFinalizeBlocks = 64;
 
 // Device-side control block of one call.
 struct Ctrl {
@@ -48,6 +60,17 @@ struct Ctrl {
   long long aux[4];
 };
 
+// Device array of class counts, written by the partition and plan kernels.
+enum CountSlot {
+  kInWave = 0,     // in-degree wavefront class size (n1)
+  kInSplit = 1,    // in-degree split class size (n2)
+  kOutWave = 2,    // out-degree wavefront class size
+  kOutSplit = 3,   // out-degree split class size
+  kInChunks = 4,   // chunks of the in-degree split class
+  kOutChunks = 5,  // chunks of the out-degree split class
+  kNumCounts = 8
+};
+
 __device__ __forceinline__ int deg_class(int deg, int t1, int t2) {
   return deg <= t1 ? 0 : (deg <= t2 ? 1 : 2);
 }
@@ -56,6 +79,31 @@ __device__ __forceinline__ int wave_sum_int(int x) {
 #pragma unroll
   for (int o = kWave / 2; o > 0; o >>= 1) x += __shfl_xor(x, o);
   return x;
+}
+
+// Exclusive scan over a 1024-thread workgroup; *total gets the sum.
+__device__ __forceinline__ int block_exclusive_scan_1024(int s, int *total) {
+  __shared__ int wsum[kFinalBlock / kWave];
+  __shared__ int tot;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+  int x = s;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == kWave - 1) wsum[w] = x;
+  __syncthreads();
+  if (tid == 0) {
+    int run = 0;
+    for (int i = 0; i < kFinalBlock / kWave; ++i) { const int t = wsum[i]; wsum[i] = run; run += t; }
+    tot = run;
+  }
+  __syncthreads();
+  const int r = wsum[w] + x - s;
+  *total = tot;
+  __syncthreads();
+  return r;
 }
 
 __global__ void k_ctrl_reset(Ctrl *ctrl) {
@@ -72,7 +120,8 @@ __global__ void k_ctrl_reset(Ctrl *ctrl) {
 // ------------------------------------------------------------ partition
 // Alg. 4 as a stable split into three classes in three passes: per-tile class
 // counts, one exclusive scan over the tiles, then a scatter that ranks each
-// vertex inside its tile with wavefront ballots.
+// vertex inside its tile with wavefront ballots. Output: hi = [wavefront
+// class ascending][split class ascending]; counts[slot], counts[slot + 1].
 
 __global__ __launch_bounds__(kBlock) void k_part_count(const int *__restrict__ off, int n, int t1,
                                                        int t2, int *__restrict__ tile_counts,
@@ -105,34 +154,17 @@ __global__ __launch_bounds__(kBlock) void k_part_count(const int *__restrict__ o
 // Exclusive scan of tile_counts[cls][0..ntiles) in place; counts[cls] = total.
 __global__ __launch_bounds__(kFinalBlock) void k_part_scan(int *__restrict__ tile_counts,
                                                            int ntiles, int *__restrict__ counts) {
-  __shared__ int wsum[kFinalBlock / kWave];
-  __shared__ int total_s;
-  const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+  const int tid = threadIdx.x;
   const int per = (ntiles + kFinalBlock - 1) / kFinalBlock;
   for (int cls = 0; cls < 2; ++cls) {
     int *tc = tile_counts + (size_t)cls * ntiles;
     const int beg = min(tid * per, ntiles), end = min(beg + per, ntiles);
     int s = 0;
     for (int i = beg; i < end; ++i) s += tc[i];
-    // inclusive wave scan
-    int x = s;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-      int y = __shfl_up(x, o);
-      if (lane >= o) x += y;
-    }
-    if (lane == kWave - 1) wsum[w] = x;
-    __syncthreads();
-    if (tid == 0) {
-      int run = 0;
-      for (int i = 0; i < kFinalBlock / kWave; ++i) { int t = wsum[i]; wsum[i] = run; run += t; }
-      total_s = run;
-    }
-    __syncthreads();
-    int run = wsum[w] + x - s;  // exclusive prefix of this thread's chunk
-    for (int i = beg; i < end; ++i) { int t = tc[i]; tc[i] = run; run += t; }
-    if (tid == 0) counts[cls] = total_s;
-    __syncthreads();
+    int total;
+    int run = block_exclusive_scan_1024(s, &total);
+    for (int i = beg; i < end; ++i) { const int t = tc[i]; tc[i] = run; run += t; }
+    if (tid == 0) counts[cls] = total;
   }
 }
 
@@ -170,9 +202,42 @@ __global__ __launch_bounds__(kBlock) void k_part_scatter(const int *__restrict__
   }
 }
 
-// ------------------------------------------------------------ Static
+// Chunk plan of the split class: vertex i of the class (hi[n1 + i]) owns
+// chunks [hub_start[i], hub_start[i+1]) of CH edges each (the last one
+// shorter); chunk_hub[c] = i. counts[chunk_slot] = number of chunks.
+__global__ __launch_bounds__(kFinalBlock) void k_hub_plan(const int *__restrict__ off,
+                                                          const int *__restrict__ hi,
+                                                          int *__restrict__ counts, int slot,
+                                                          int chunk_slot, int CH,
+                                                          int *__restrict__ hub_start,
+                                                          int *__restrict__ chunk_hub) {
+  const int n1 = counts[slot], n2 = counts[slot + 1];
+  const int tid = threadIdx.x;
+  const int per = (n2 + kFinalBlock - 1) / kFinalBlock;
+  const int beg = min(tid * per, n2), end = min(beg + per, n2);
+  int s = 0;
+  for (int i = beg; i < end; ++i) {
+    const int v = hi[n1 + i];
+    s += (off[v + 1] - off[v] + CH - 1) / CH;
+  }
+  int total;
+  int run = block_exclusive_scan_1024(s, &total);
+  for (int i = beg; i < end; ++i) {
+    const int v = hi[n1 + i];
+    const int cnt = (off[v + 1] - off[v] + CH - 1) / CH;
+    hub_start[i] = run;
+    for (int c = 0; c < cnt; ++c) chunk_hub[run + c] = i;
+    run += cnt;
+  }
+  if (tid == 0) {
+    hub_start[n2] = total;
+    counts[chunk_slot] = total;
+  }
+}
+
+// ------------------------------------------------------------ Static init
 // R = 1/n, X = R / |out(v)| (Alg. 1 initialisation). With `init` the start
-// vector is given (Naive-dynamic, Sec. 3.4.1).
+// vector is given (Naive-dynamic, Sec. 3.4.1); it may alias R.
 __global__ __launch_bounds__(kBlock) void k_static_init(int n, const int *__restrict__ out_off,
                                                         const double *init, double *R,
                                                         double *__restrict__ X) {
@@ -184,8 +249,9 @@ __global__ __launch_bounds__(kBlock) void k_static_init(int n, const int *__rest
   }
 }
 
+// ------------------------------------------------------------ row sums
 // Sequential in-row sum of X over sources, ascending (four loads in flight,
-// additions in row order).
+// additions in row order, so the result equals a plain sequential sum).
 __device__ __forceinline__ double row_sum_seq(const int *__restrict__ src,
                                               const double *__restrict__ X, int e0, int e1) {
   double c = 0.0;
@@ -202,58 +268,275 @@ __device__ __forceinline__ double row_sum_seq(const int *__restrict__ src,
   return c;
 }
 
-// Eq. 1 for one vertex: R_new, its contribution, and |R_new - R|.
-__device__ __forceinline__ double static_finish(int v, double c, const int *__restrict__ out_off,
-                                                const double *__restrict__ R,
-                                                double *__restrict__ Rn,
-                                                double *__restrict__ Xn, double C0,
-                                                double alpha) {
-  const double r = C0 + alpha * c;
-  Rn[v] = r;
-  Xn[v] = r / (double)(out_off[v + 1] - out_off[v]);
-  return fabs(r - R[v]);
+// Same for DF-P, which reads ranks and degrees directly (only affected rows
+// are read, so there is no per-vertex contribution pass).
+__device__ __forceinline__ double row_sum_seq_rd(const int *__restrict__ src,
+                                                 const int *__restrict__ out_off,
+                                                 const double *__restrict__ R, int e0, int e1) {
+  double c = 0.0;
+  int e = e0;
+  for (; e + 2 <= e1; e += 2) {
+    const int u0 = src[e], u1 = src[e + 1];
+    const double r0 = R[u0], r1 = R[u1];
+    const int d0 = out_off[u0 + 1] - out_off[u0], d1 = out_off[u1 + 1] - out_off[u1];
+    c = c + r0 / (double)d0;
+    c = c + r1 / (double)d1;
+  }
+  for (; e < e1; ++e) {
+    const int u = src[e];
+    c = c + R[u] / (double)(out_off[u + 1] - out_off[u]);
+  }
+  return c;
+}
+
+// Contribution of in-edge e: X[src[e]] (Static) or R[u]/|out(u)| (DF-P).
+template <bool DYN>
+__device__ __forceinline__ double contrib(int e, const int *__restrict__ src,
+                                          const int *__restrict__ out_off,
+                                          const double *__restrict__ XR) {
+  const int u = src[e];
+  if (DYN) return XR[u] / (double)(out_off[u + 1] - out_off[u]);
+  return XR[u];
+}
+
+// Strided partial sum over [e0, e1) with stride S starting at e0 + t, four
+// independent accumulators combined in a fixed order.
+template <bool DYN, int S>
+__device__ __forceinline__ double strided_sum(int e0, int e1, int t, const int *__restrict__ src,
+                                              const int *__restrict__ out_off,
+                                              const double *__restrict__ XR) {
+  double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
+  int e = e0 + t;
+  for (; e + 3 * S < e1; e += 4 * S) {
+    c0 += contrib<DYN>(e, src, out_off, XR);
+    c1 += contrib<DYN>(e + S, src, out_off, XR);
+    c2 += contrib<DYN>(e + 2 * S, src, out_off, XR);
+    c3 += contrib<DYN>(e + 3 * S, src, out_off, XR);
+  }
+  for (; e < e1; e += S) c0 += contrib<DYN>(e, src, out_off, XR);
+  return (c0 + c1) + (c2 + c3);
+}
+
+// ------------------------------------------------------------ finishing
+struct StaticOut {
+  const int *out_off;
+  const double *R;
+  double *Rn, *Xn;
+  double C0, alpha;
+  // Eq. 1 for one vertex: R_new, its contribution, and |R_new - R|.
+  __device__ __forceinline__ double finish(int v, double c) const {
+    const double r = C0 + alpha * c;
+    Rn[v] = r;
+    Xn[v] = r / (double)(out_off[v + 1] - out_off[v]);
+    return fabs(r - R[v]);
+  }
+};
+
+template <bool PRUNE>
+struct DynOut {
+  const int *out_off;
+  const double *R;
+  double *T;
+  uint8_t *dV, *dN, *cv;
+  double C0, alpha, tau_f, tau_p;
+  // updateRanks (Alg. 3) for one affected vertex: Eq. 2 (DF-P) or Eq. 1
+  // (DF), pruning (DF-P), frontier flag, staged new rank. Returns |r - R[v]|.
+  __device__ __forceinline__ double finish(int v, double c) const {
+    const double Rv = R[v];
+    const double d = (double)(out_off[v + 1] - out_off[v]);
+    double r;
+    if (PRUNE) r = 1.0 / (1.0 - alpha / d) * (C0 + alpha * (c - Rv / d));
+    else r = C0 + alpha * c;
+    const double dr = fabs(r - Rv);
+    const double rel = dr / fmax(r, Rv);
+    if (PRUNE && rel <= tau_p) dV[v] = 0;
+    dN[v] = rel > tau_f ? 1 : 0;
+    T[v] = r;
+    cv[v] = 1;
+    return dr;
+  }
+};
+
+// ------------------------------------------------------------ rank update
+// One rank update (Alg. 3 / Eq. 1 for Static, Eq. 2 for DF-P) over all three
+// classes; see the file comment for the launch shape. DYN = DF/DF-P mode:
+// only vertices with dV set are updated, and every vertex processed here
+// rewrites its dN flag (cleared when unaffected), which is the clearing of
+// delta_N at the start of the iteration in Alg. 2.
+template <bool DYN, class Out>
+__device__ __forceinline__ void rank_update(
+    const int *__restrict__ in_off, const int *__restrict__ in_src,
+    const int *__restrict__ out_off, const double *__restrict__ XR, const uint8_t *dV,
+    uint8_t *dN, const int *__restrict__ hi, const int *__restrict__ counts,
+    const int *__restrict__ hub_start, const int *__restrict__ chunk_hub,
+    double *__restrict__ hub_part, int CH, int n, int t1, const Out &out,
+    double *__restrict__ partials) {
+  __shared__ double lds[kWavesPerBlock];
+  __shared__ int s_v[kBlock], s_e0[kBlock], s_e1[kBlock], s_c[kBlock];
+  __shared__ int s_wcnt[kWavesPerBlock];
+  const int n1 = counts[kInWave], nch = counts[kInChunks];
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+  const int B = gridDim.x;
+  double dmax = 0.0;
+
+  // 1) split class: this workgroup's chunks are blockIdx + k*B; in each
+  // round thread tid checks one of them, and the selected ones are summed by
+  // the whole workgroup.
+  for (long long base = blockIdx.x; base < nch; base += (long long)kBlock * B) {
+    const long long cl = base + (long long)tid * B;
+    const int c = cl < nch ? (int)cl : 0;
+    bool f = false;
+    int v = 0, e0 = 0, e1 = 0;
+    if (cl < nch) {
+      const int i = chunk_hub[c];
+      v = hi[n1 + i];
+      f = DYN ? (dV[v] != 0) : true;
+      const int r0 = in_off[v], r1 = in_off[v + 1];
+      e0 = r0 + (c - hub_start[i]) * CH;
+      e1 = min(e0 + CH, r1);
+    }
+    int wt;
+    const int p = wave_prefix_count(f, &wt);
+    if (lane == 0) s_wcnt[wid] = wt;
+    __syncthreads();
+    int off = 0, cnt = 0;
+#pragma unroll
+    for (int i = 0; i < kWavesPerBlock; ++i) {
+      if (i < wid) off += s_wcnt[i];
+      cnt += s_wcnt[i];
+    }
+    if (f) { s_c[off + p] = c; s_v[off + p] = v; s_e0[off + p] = e0; s_e1[off + p] = e1; }
+    __syncthreads();
+    for (int k = 0; k < cnt; ++k) {
+      double s = strided_sum<DYN, kBlock>(s_e0[k], s_e1[k], tid, in_src, out_off, XR);
+      s = block_sum<kBlock>(s, lds);
+      if (tid == 0) hub_part[s_c[k]] = s;
+    }
+    __syncthreads();
+  }
+
+  // 2) wavefront class: wavefront gw takes candidates gw + k*W, 64 at a time
+  {
+    const int W = B * kWavesPerBlock;
+    const int gw = blockIdx.x * kWavesPerBlock + wid;
+    for (long long k0 = 0; gw + k0 * W < n1; k0 += kWave) {
+      const long long ii = gw + (k0 + lane) * W;
+      int v = -1;
+      bool f = false;
+      if (ii < n1) {
+        v = hi[ii];
+        f = DYN ? (dV[v] != 0) : true;
+        if (DYN && !f) dN[v] = 0;
+      }
+      unsigned long long mask = __ballot(f);
+      while (mask) {
+        const int j = __ffsll(mask) - 1;
+        mask &= mask - 1;
+        const int vv = __shfl(v, j);
+        const int e0 = in_off[vv], e1 = in_off[vv + 1];
+        double c = strided_sum<DYN, kWave>(e0, e1, lane, in_src, out_off, XR);
+        c = wave_sum(c);
+        if (lane == 0) dmax = fmax(dmax, out.finish(vv, c));
+      }
+    }
+  }
+
+  // 3) lane class over 256-vertex ID tiles
+  {
+    const int ntiles = (n + kBlock - 1) / kBlock;
+    for (int t = blockIdx.x; t < ntiles; t += B) {
+      const int v = t * kBlock + tid;
+      if (v < n) {
+        const int e0 = in_off[v], e1 = in_off[v + 1];
+        if (e1 - e0 <= t1) {
+          if (!DYN || dV[v]) {
+            const double c = DYN ? row_sum_seq_rd(in_src, out_off, XR, e0, e1)
+                                 : row_sum_seq(in_src, XR, e0, e1);
+            dmax = fmax(dmax, out.finish(v, c));
+          } else {
+            dN[v] = 0;
+          }
+        }
+      }
+    }
+  }
+  dmax = block_max<kBlock>(dmax, lds);
+  if (tid == 0) partials[blockIdx.x] = dmax;
 }
 
 __global__ __launch_bounds__(kBlock) void k_rank_static(
     const int *__restrict__ in_off, const int *__restrict__ in_src,
     const int *__restrict__ out_off, const double *__restrict__ X, const double *__restrict__ R,
-    double *__restrict__ Rn, double *__restrict__ Xn, const int *__restrict__ hi, int n1,
-    int nb2, int nb1, int n, int t1, double C0, double alpha, double *__restrict__ partials,
+    double *__restrict__ Rn, double *__restrict__ Xn, const int *__restrict__ hi,
+    const int *__restrict__ counts, const int *__restrict__ hub_start,
+    const int *__restrict__ chunk_hub, double *__restrict__ hub_part, int CH, int n, int t1,
+    double C0, double alpha, double *__restrict__ partials, const Ctrl *__restrict__ ctrl) {
+  if (ctrl->done) return;
+  const StaticOut out{out_off, R, Rn, Xn, C0, alpha};
+  rank_update<false>(in_off, in_src, out_off, X, nullptr, nullptr, hi, counts, hub_start,
+                     chunk_hub, hub_part, CH, n, t1, out, partials);
+}
+
+template <bool PRUNE>
+__global__ __launch_bounds__(kBlock) void k_rank_dfp(
+    const int *__restrict__ in_off, const int *__restrict__ in_src,
+    const int *__restrict__ out_off, const double *__restrict__ R, double *__restrict__ T,
+    uint8_t *dV, uint8_t *dN, uint8_t *cv, const int *__restrict__ hi,
+    const int *__restrict__ counts, const int *__restrict__ hub_start,
+    const int *__restrict__ chunk_hub, double *__restrict__ hub_part, int CH, int n, int t1,
+    double C0, double alpha, double tau_f, double tau_p, double *__restrict__ partials,
     const Ctrl *__restrict__ ctrl) {
   if (ctrl->done) return;
+  const DynOut<PRUNE> out{out_off, R, T, dV, dN, cv, C0, alpha, tau_f, tau_p};
+  rank_update<true>(in_off, in_src, out_off, R, dV, dN, hi, counts, hub_start, chunk_hub,
+                    hub_part, CH, n, t1, out, partials);
+}
+
+// Split-class vertices: add the chunk partials in chunk order and finish.
+template <bool DYN, class Out>
+__device__ __forceinline__ void hub_finalize(const int *__restrict__ hi,
+                                             const int *__restrict__ counts,
+                                             const int *__restrict__ hub_start,
+                                             const double *__restrict__ hub_part,
+                                             const uint8_t *dV, uint8_t *dN, const Out &out,
+                                             double *__restrict__ partials) {
   __shared__ double lds[kWavesPerBlock];
+  const int n1 = counts[kInWave], n2 = counts[kInSplit];
   double dmax = 0.0;
-  const int b = blockIdx.x;
-  if (b < nb2) {  // workgroup per vertex
-    const int v = hi[n1 + b];
-    const int e0 = in_off[v], e1 = in_off[v + 1];
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n2; i += gridDim.x * kBlock) {
+    const int v = hi[n1 + i];
+    if (DYN && !dV[v]) {
+      dN[v] = 0;
+      continue;
+    }
     double c = 0.0;
-    for (int e = e0 + (int)threadIdx.x; e < e1; e += kBlock) c += X[in_src[e]];
-    c = block_sum<kBlock>(c, lds);
-    if (threadIdx.x == 0) dmax = static_finish(v, c, out_off, R, Rn, Xn, C0, alpha);
-  } else if (b < nb2 + nb1) {  // wavefront per vertex
-    const int lane = threadIdx.x & (kWave - 1);
-    const int i = (b - nb2) * kWavesPerBlock + (int)threadIdx.x / kWave;
-    if (i < n1) {
-      const int v = hi[i];
-      const int e0 = in_off[v], e1 = in_off[v + 1];
-      double c = 0.0;
-      for (int e = e0 + lane; e < e1; e += kWave) c += X[in_src[e]];
-      c = wave_sum(c);
-      if (lane == 0) dmax = static_finish(v, c, out_off, R, Rn, Xn, C0, alpha);
-    }
-  } else {  // lane per vertex over an ID tile
-    const int v = (b - nb2 - nb1) * kBlock + (int)threadIdx.x;
-    if (v < n) {
-      const int e0 = in_off[v], e1 = in_off[v + 1];
-      if (e1 - e0 <= t1) {
-        const double c = row_sum_seq(in_src, X, e0, e1);
-        dmax = static_finish(v, c, out_off, R, Rn, Xn, C0, alpha);
-      }
-    }
+    for (int k = hub_start[i]; k < hub_start[i + 1]; ++k) c = c + hub_part[k];
+    dmax = fmax(dmax, out.finish(v, c));
   }
   dmax = block_max<kBlock>(dmax, lds);
-  if (threadIdx.x == 0) partials[b] = dmax;
+  if (threadIdx.x == 0) partials[blockIdx.x] = dmax;
+}
+
+__global__ __launch_bounds__(kBlock) void k_hub_finalize_static(
+    const int *__restrict__ hi, const int *__restrict__ counts, const int *__restrict__ hub_start,
+    const double *__restrict__ hub_part, const int *__restrict__ out_off,
+    const double *__restrict__ R, double *__restrict__ Rn, double *__restrict__ Xn, double C0,
+    double alpha, double *__restrict__ partials, const Ctrl *__restrict__ ctrl) {
+  if (ctrl->done) return;
+  const StaticOut out{out_off, R, Rn, Xn, C0, alpha};
+  hub_finalize<false>(hi, counts, hub_start, hub_part, nullptr, nullptr, out, partials);
+}
+
+template <bool PRUNE>
+__global__ __launch_bounds__(kBlock) void k_hub_finalize_dfp(
+    const int *__restrict__ hi, const int *__restrict__ counts, const int *__restrict__ hub_start,
+    const double *__restrict__ hub_part, const int *__restrict__ out_off,
+    const double *__restrict__ R, double *__restrict__ T, uint8_t *dV, uint8_t *dN, uint8_t *cv,
+    double C0, double alpha, double tau_f, double tau_p, double *__restrict__ partials,
+    const Ctrl *__restrict__ ctrl) {
+  if (ctrl->done) return;
+  const DynOut<PRUNE> out{out_off, R, T, dV, dN, cv, C0, alpha, tau_f, tau_p};
+  hub_finalize<true>(hi, counts, hub_start, hub_part, dV, dN, out, partials);
 }
 
 // Second stage of the L-infinity norm; records the iteration's outcome.
@@ -262,9 +545,14 @@ __global__ __launch_bounds__(kFinalBlock) void k_linf_final(const double *__rest
                                                            double tol, int it) {
   if (ctrl->done) return;
   __shared__ double lds[kFinalBlock / kWave];
-  double m = 0.0;
-  for (int i = threadIdx.x; i < np; i += kFinalBlock) m = fmax(m, partials[i]);
-  m = block_max<kFinalBlock>(m, lds);
+  double m0 = 0.0, m1 = 0.0;
+  int i = threadIdx.x;
+  for (; i + kFinalBlock < np; i += 2 * kFinalBlock) {
+    m0 = fmax(m0, partials[i]);
+    m1 = fmax(m1, partials[i + kFinalBlock]);
+  }
+  if (i < np) m0 = fmax(m0, partials[i]);
+  double m = block_max<kFinalBlock>(fmax(m0, m1), lds);
   if (threadIdx.x == 0) {
     ctrl->delta = m;
     ctrl->iters = it + 1;
@@ -273,9 +561,8 @@ __global__ __launch_bounds__(kFinalBlock) void k_linf_final(const double *__rest
 }
 
 // ------------------------------------------------------------ DF / DF-P
-__global__ __launch_bounds__(kBlock) void k_dfp_init(int n, const double *__restrict__ prev,
-                                                     double *__restrict__ R, uint8_t *dV,
-                                                     uint8_t *dN, uint8_t *cv) {
+__global__ __launch_bounds__(kBlock) void k_dfp_init(int n, const double *prev, double *R,
+                                                     uint8_t *dV, uint8_t *dN, uint8_t *cv) {
   const int v = blockIdx.x * kBlock + threadIdx.x;
   if (v < n) {
     if (prev != R) R[v] = prev[v];
@@ -308,136 +595,82 @@ __global__ __launch_bounds__(kBlock) void k_mark_initial(const int *__restrict__
   }
 }
 
-// Sequential in-row sum of R[u]/|out(u)| (DF-P gathers ranks and degrees
-// directly: only affected rows are read, so no per-vertex contribution pass).
-__device__ __forceinline__ double row_sum_seq_rd(const int *__restrict__ src,
-                                                 const int *__restrict__ out_off,
-                                                 const double *__restrict__ R, int e0, int e1) {
-  double c = 0.0;
-  int e = e0;
-  for (; e + 2 <= e1; e += 2) {
-    const int u0 = src[e], u1 = src[e + 1];
-    const double r0 = R[u0], r1 = R[u1];
-    const int d0 = out_off[u0 + 1] - out_off[u0], d1 = out_off[u1 + 1] - out_off[u1];
-    c = c + r0 / (double)d0;
-    c = c + r1 / (double)d1;
-  }
-  for (; e < e1; ++e) {
-    const int u = src[e];
-    c = c + R[u] / (double)(out_off[u + 1] - out_off[u]);
-  }
-  return c;
-}
-
-// updateRanks (Alg. 3) for one affected vertex v with in-row sum c.
-// prune: Eq. 2 closed-loop update plus pruning (DF-P); else Eq. 1 (DF).
-// Returns |r - R[v]| for the L-infinity norm.
-template <bool PRUNE>
-__device__ __forceinline__ double dfp_finish(int v, double c, const int *__restrict__ out_off,
-                                             const double *__restrict__ R,
-                                             double *__restrict__ T, uint8_t *dV, uint8_t *dN,
-                                             uint8_t *cv, double C0, double alpha, double tau_f,
-                                             double tau_p) {
-  const double Rv = R[v];
-  const double d = (double)(out_off[v + 1] - out_off[v]);
-  double r;
-  if (PRUNE) r = 1.0 / (1.0 - alpha / d) * (C0 + alpha * (c - Rv / d));
-  else r = C0 + alpha * c;
-  const double dr = fabs(r - Rv);
-  const double rel = dr / fmax(r, Rv);
-  if (PRUNE && rel <= tau_p) dV[v] = 0;
-  if (rel > tau_f) dN[v] = 1;
-  T[v] = r;
-  cv[v] = 1;
-  return dr;
-}
-
-template <bool PRUNE>
-__global__ __launch_bounds__(kBlock) void k_rank_dfp(
-    const int *__restrict__ in_off, const int *__restrict__ in_src,
-    const int *__restrict__ out_off, const double *__restrict__ R, double *__restrict__ T,
-    uint8_t *dV, uint8_t *dN, uint8_t *cv, const int *__restrict__ hi, int n1, int nb2, int nb1,
-    int n, int t1, double C0, double alpha, double tau_f, double tau_p,
-    double *__restrict__ partials, const Ctrl *__restrict__ ctrl) {
-  if (ctrl->done) return;
-  __shared__ double lds[kWavesPerBlock];
-  double dmax = 0.0;
-  const int b = blockIdx.x;
-  if (b < nb2) {
-    const int v = hi[n1 + b];
-    if (dV[v]) {  // uniform over the block
-      const int e0 = in_off[v], e1 = in_off[v + 1];
-      double c = 0.0;
-      for (int e = e0 + (int)threadIdx.x; e < e1; e += kBlock) {
-        const int u = in_src[e];
-        c += R[u] / (double)(out_off[u + 1] - out_off[u]);
-      }
-      c = block_sum<kBlock>(c, lds);
-      if (threadIdx.x == 0)
-        dmax = dfp_finish<PRUNE>(v, c, out_off, R, T, dV, dN, cv, C0, alpha, tau_f, tau_p);
-    }
-  } else if (b < nb2 + nb1) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int i = (b - nb2) * kWavesPerBlock + (int)threadIdx.x / kWave;
-    if (i < n1) {
-      const int v = hi[i];
-      if (dV[v]) {  // uniform over the wavefront
-        const int e0 = in_off[v], e1 = in_off[v + 1];
-        double c = 0.0;
-        for (int e = e0 + lane; e < e1; e += kWave) {
-          const int u = in_src[e];
-          c += R[u] / (double)(out_off[u + 1] - out_off[u]);
-        }
-        c = wave_sum(c);
-        if (lane == 0)
-          dmax = dfp_finish<PRUNE>(v, c, out_off, R, T, dV, dN, cv, C0, alpha, tau_f, tau_p);
-      }
-    }
-  } else {
-    const int v = (b - nb2 - nb1) * kBlock + (int)threadIdx.x;
-    if (v < n && dV[v]) {
-      const int e0 = in_off[v], e1 = in_off[v + 1];
-      if (e1 - e0 <= t1) {
-        const double c = row_sum_seq_rd(in_src, out_off, R, e0, e1);
-        dmax = dfp_finish<PRUNE>(v, c, out_off, R, T, dV, dN, cv, C0, alpha, tau_f, tau_p);
-      }
-    }
-  }
-  dmax = block_max<kBlock>(dmax, lds);
-  if (threadIdx.x == 0) partials[b] = dmax;
-}
-
 // After the convergence check of iteration `it`: copy the new ranks of the
 // vertices updated in it (the swap of Alg. 2; vertices not updated keep
 // their rank), then, unless it converged, expandAffected (Alg. 5): every u
-// with dN[u] marks out(u) in dV and clears dN[u] (the clearing of dN at the
-// start of the next iteration in Alg. 2). Lane per vertex for out-degree
-// <= t_exp over ID tiles; a wavefront per vertex of the high out-degree
-// list. dV stores are all 1s (benign races, no atomics). it = -1 is the
-// initial expansion.
+// with dN[u] marks out(u) in dV. Out-degree classes as for the rank update:
+// lane per vertex over ID tiles, a wavefront per vertex, or one workgroup per
+// chunk of out-edges. dV stores are all 1s (benign races, no atomics).
+// it = -1 is the initial expansion.
 __global__ __launch_bounds__(kBlock) void k_apply_expand(
     const int *__restrict__ out_off, const int *__restrict__ out_tgt, double *__restrict__ R,
-    const double *__restrict__ T, uint8_t *dV, uint8_t *dN, uint8_t *cv,
-    const int *__restrict__ hi_out, int no1, int nbo1, int n, int t_exp,
-    const Ctrl *__restrict__ ctrl, int it) {
+    const double *__restrict__ T, uint8_t *dV, const uint8_t *dN, uint8_t *cv,
+    const int *__restrict__ hi_out, const int *__restrict__ counts,
+    const int *__restrict__ hub_start, const int *__restrict__ chunk_hub, int CH, int n,
+    int t_exp, const Ctrl *__restrict__ ctrl, int it) {
   const int done = ctrl->done;
   if (done && ctrl->iters < it + 1) return;  // converged before this iteration
   const bool expand = !done;
-  const int b = blockIdx.x;
-  if (b < nbo1) {
-    if (!expand) return;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int i = b * kWavesPerBlock + (int)threadIdx.x / kWave;
-    if (i < no1) {
-      const int u = hi_out[i];
-      if (dN[u]) {
-        const int e0 = out_off[u], e1 = out_off[u + 1];
-        for (int e = e0 + lane; e < e1; e += kWave) dV[out_tgt[e]] = 1;
-        if (lane == 0) dN[u] = 0;
+  __shared__ int s_e0[kBlock], s_e1[kBlock];
+  __shared__ int s_wcnt[kWavesPerBlock];
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+  const int B = gridDim.x;
+  if (expand) {
+    const int n1 = counts[kOutWave], nch = counts[kOutChunks];
+    // split class: chunks blockIdx + k*B, one per thread and round
+    for (long long base = blockIdx.x; base < nch; base += (long long)kBlock * B) {
+    const long long cl = base + (long long)tid * B;
+    const int c = cl < nch ? (int)cl : 0;
+    bool f = false;
+    int e0 = 0, e1 = 0;
+    if (cl < nch) {
+      const int i = chunk_hub[c];
+      const int u = hi_out[n1 + i];
+      f = dN[u] != 0;
+      e0 = out_off[u] + (c - hub_start[i]) * CH;
+      e1 = min(e0 + CH, out_off[u + 1]);
+    }
+    int wt;
+    const int p = wave_prefix_count(f, &wt);
+    if (lane == 0) s_wcnt[wid] = wt;
+    __syncthreads();
+    int off = 0, cnt = 0;
+#pragma unroll
+    for (int i = 0; i < kWavesPerBlock; ++i) {
+      if (i < wid) off += s_wcnt[i];
+      cnt += s_wcnt[i];
+    }
+    if (f) { s_e0[off + p] = e0; s_e1[off + p] = e1; }
+    __syncthreads();
+    for (int k = 0; k < cnt; ++k)
+      for (int e = s_e0[k] + tid; e < s_e1[k]; e += kBlock) dV[out_tgt[e]] = 1;
+    __syncthreads();
+    }
+    // wavefront class
+    const int W = B * kWavesPerBlock;
+    const int gw = blockIdx.x * kWavesPerBlock + wid;
+    for (long long k0 = 0; gw + k0 * W < n1; k0 += kWave) {
+      const long long ii = gw + (k0 + lane) * W;
+      int u = -1;
+      bool g = false;
+      if (ii < n1) {
+        u = hi_out[ii];
+        g = dN[u] != 0;
+      }
+      unsigned long long mask = __ballot(g);
+      while (mask) {
+        const int j = __ffsll(mask) - 1;
+        mask &= mask - 1;
+        const int uu = __shfl(u, j);
+        const int a = out_off[uu], b = out_off[uu + 1];
+        for (int e = a + lane; e < b; e += kWave) dV[out_tgt[e]] = 1;
       }
     }
-  } else {
-    const int v = (b - nbo1) * kBlock + (int)threadIdx.x;
+  }
+  // lane class and the apply step over ID tiles
+  const int ntiles = (n + kBlock - 1) / kBlock;
+  for (int t = blockIdx.x; t < ntiles; t += B) {
+    const int v = t * kBlock + tid;
     if (v < n) {
       if (cv[v]) {
         R[v] = T[v];
@@ -445,10 +678,8 @@ __global__ __launch_bounds__(kBlock) void k_apply_expand(
       }
       if (expand && dN[v]) {
         const int e0 = out_off[v], e1 = out_off[v + 1];
-        if (e1 - e0 <= t_exp) {
+        if (e1 - e0 <= t_exp)
           for (int e = e0; e < e1; ++e) dV[out_tgt[e]] = 1;
-          dN[v] = 0;
-        }
       }
     }
   }
@@ -460,14 +691,15 @@ __global__ __launch_bounds__(kBlock) void k_count_flags(const uint8_t *__restric
   int c = 0;
   for (int v = blockIdx.x * kBlock + threadIdx.x; v < n; v += gridDim.x * kBlock) c += f[v] != 0;
   c = wave_sum_int(c);
-  if ((threadIdx.x & (kWave - 1)) == 0 && c) atomicAdd((unsigned long long *)&ctrl->aux[slot],
-                                                     (unsigned long long)c);
+  if ((threadIdx.x & (kWave - 1)) == 0 && c)
+    atomicAdd((unsigned long long *)&ctrl->aux[slot], (unsigned long long)c);
 }
 
 // ------------------------------------------------------------ validation
 // Pass 1 reads only offsets; pass 2 (run only when pass 1 found nothing)
-// reads the rows. Error bits: 1 offsets, 2 ID range, 4 row order, 8 missing
-// self-loop, 16 out view, 32 degree sums.
+// reads the rows. Error bits: 1 / 16 offsets (in / out view), then
+// 2, 4, 8 (in view) and 32, 64, 128 (out view) for an ID out of range, a row
+// not strictly ascending, a missing self-loop.
 __global__ __launch_bounds__(kBlock) void k_validate_offsets(const int *__restrict__ off, int n,
                                                              int m, int *err, int bit) {
   const int v = blockIdx.x * kBlock + threadIdx.x;

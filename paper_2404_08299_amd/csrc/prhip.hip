@@ -44,6 +44,8 @@ pr_tuning default_tuning() {
   t.wave_max_degree = 4096;
   t.expand_lane_max_degree = 32;
   t.iters_per_sync = 2;
+  t.hub_chunk_edges = 4096;
+  t.grid_blocks = 0;
   return t;
 }
 pr_tuning g_tuning = default_tuning();
@@ -51,14 +53,17 @@ pr_tuning g_tuning = default_tuning();
 constexpr int kRing = 8;  // pinned control-block snapshots
 
 struct Workspace {
-  size_t cap_n = 0;
+  size_t cap_n = 0, cap_chunks = 0, cap_partials = 0;
+  int num_cus = 0;
   double *R1 = nullptr, *X0 = nullptr, *X1 = nullptr, *T = nullptr;
   uint8_t *flags = nullptr;  // dV | dN | cv, n bytes each
   int *hi_in = nullptr, *hi_out = nullptr;
+  int *hub_start_in = nullptr, *hub_start_out = nullptr;  // [n + 1]
+  int *chunk_hub_in = nullptr, *chunk_hub_out = nullptr;  // [cap_chunks]
+  double *hub_part = nullptr;                             // [cap_chunks]
   int *tile_counts = nullptr;  // [2][ntiles]
-  int *counts = nullptr;       // [4]: in-class1, in-class2, out-class1, out-class2
-  double *partials = nullptr;
-  size_t cap_partials = 0;
+  int *counts = nullptr;       // [kNumCounts]
+  double *partials = nullptr;  // [cap_partials]
   Ctrl *ctrl = nullptr;
   Ctrl *host_ctrl = nullptr;  // pinned ring
   int *host_counts = nullptr;  // pinned
@@ -88,10 +93,25 @@ int fail(int code, const std::string &msg) {
       return fail(PR_EHIP, std::string("kernel launch: ") + hipGetErrorString(e_));   \
   } while (0)
 
+void free_arrays(Workspace &w) {
+  (void)hipFree(w.R1); (void)hipFree(w.X0); (void)hipFree(w.X1); (void)hipFree(w.T);
+  (void)hipFree(w.flags); (void)hipFree(w.hi_in); (void)hipFree(w.hi_out);
+  (void)hipFree(w.hub_start_in); (void)hipFree(w.hub_start_out);
+  (void)hipFree(w.chunk_hub_in); (void)hipFree(w.chunk_hub_out); (void)hipFree(w.hub_part);
+  (void)hipFree(w.tile_counts); (void)hipFree(w.partials);
+  w.R1 = w.X0 = w.X1 = w.T = nullptr;
+  w.flags = nullptr;
+  w.hi_in = w.hi_out = w.hub_start_in = w.hub_start_out = nullptr;
+  w.chunk_hub_in = w.chunk_hub_out = nullptr;
+  w.hub_part = nullptr;
+  w.tile_counts = nullptr;
+  w.partials = nullptr;
+  w.cap_n = w.cap_chunks = w.cap_partials = 0;
+}
+
 void free_ws(Workspace &w) {
-  (void)hipFree(w.R1); (void)hipFree(w.X0); (void)hipFree(w.X1); (void)hipFree(w.T); (void)hipFree(w.flags);
-  (void)hipFree(w.hi_in); (void)hipFree(w.hi_out); (void)hipFree(w.tile_counts); (void)hipFree(w.counts);
-  (void)hipFree(w.partials); (void)hipFree(w.ctrl);
+  free_arrays(w);
+  (void)hipFree(w.counts); (void)hipFree(w.ctrl);
   if (w.host_ctrl) (void)hipHostFree(w.host_ctrl);
   if (w.host_counts) (void)hipHostFree(w.host_counts);
   if (w.events_ready) {
@@ -104,20 +124,20 @@ void free_ws(Workspace &w) {
 
 size_t ntiles_for(size_t n) { return (n + kPartTile - 1) / kPartTile; }
 
-// Grid of the fused rank launch for n vertices with n1/n2 hub-class counts.
-struct RankGrid {
-  int nb2, nb1, nb0;
-  int total() const { return nb2 + nb1 + nb0; }
-};
-RankGrid rank_grid(int n, int n1, int n2) {
-  RankGrid g;
-  g.nb2 = n2;
-  g.nb1 = (n1 + kWavesPerBlock - 1) / kWavesPerBlock;
-  g.nb0 = (n + kBlock - 1) / kBlock;
-  return g;
+// Workgroups of a fixed-size launch: the tuning value, else as many as can
+// be resident at once (occupancy of `kernel` times the compute units).
+template <class K>
+int grid_blocks(const Workspace &w, const pr_tuning &tn, K kernel) {
+  if (tn.grid_blocks > 0) return tn.grid_blocks;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess ||
+      per_cu <= 0)
+    per_cu = 4;
+  return per_cu * std::max(1, w.num_cus);
 }
 
-int get_ws(size_t n, Workspace **out) {
+// Workspace for n vertices, m edges and chunk size CH (grow-only, per device).
+int get_ws(size_t n, size_t m, int CH, int B, Workspace **out) {
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   Workspace &w = g_ws[dev];
@@ -125,43 +145,45 @@ int get_ws(size_t n, Workspace **out) {
     for (auto &e : w.sync_ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     for (auto &e : w.call_ev) HIP_TRY(hipEventCreate(&e));
     HIP_TRY(hipMalloc(&w.ctrl, sizeof(Ctrl)));
-    HIP_TRY(hipMalloc(&w.counts, 4 * sizeof(int)));
+    HIP_TRY(hipMalloc(&w.counts, kNumCounts * sizeof(int)));
     HIP_TRY(hipHostMalloc(&w.host_ctrl, kRing * sizeof(Ctrl), hipHostMallocDefault));
-    HIP_TRY(hipHostMalloc(&w.host_counts, 4 * sizeof(int), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc(&w.host_counts, kNumCounts * sizeof(int), hipHostMallocDefault));
+    HIP_TRY(hipDeviceGetAttribute(&w.num_cus, hipDeviceAttributeMultiprocessorCount, dev));
     w.events_ready = true;
   }
-  if (n > w.cap_n) {
-    (void)hipFree(w.R1); (void)hipFree(w.X0); (void)hipFree(w.X1); (void)hipFree(w.T); (void)hipFree(w.flags);
-    (void)hipFree(w.hi_in); (void)hipFree(w.hi_out); (void)hipFree(w.tile_counts); (void)hipFree(w.partials);
-    w.R1 = w.X0 = w.X1 = w.T = nullptr;
-    w.flags = nullptr;
-    w.hi_in = w.hi_out = w.tile_counts = nullptr;
-    w.partials = nullptr;
-    w.cap_n = 0;
-    size_t nt = ntiles_for(n);
-    // upper bound of blocks of any fused launch: every vertex a WG-class one
-    size_t np = n + (n + kBlock - 1) / kBlock + 16;
+  if (B <= 0) B = 32 * std::max(1, w.num_cus);  // bound on any occupancy-derived grid
+  // chunks of the split class: sum over its vertices of ceil(deg / CH)
+  // <= m / CH + (number of split vertices) <= m / CH + n
+  const size_t need_chunks = m / (size_t)CH + n + 1;
+  const size_t need_partials = (size_t)B + kHubFinalizeBlocks + 16;
+  if (n > w.cap_n || need_chunks > w.cap_chunks || need_partials > w.cap_partials) {
+    const size_t nn = std::max(n, w.cap_n);
+    const size_t nc = std::max(need_chunks, w.cap_chunks);
+    const size_t np = std::max(need_partials, w.cap_partials);
+    free_arrays(w);
+    const size_t nt = ntiles_for(nn);
     hipError_t e = hipSuccess;
-    if ((e = hipMalloc(&w.R1, n * sizeof(double))) != hipSuccess ||
-        (e = hipMalloc(&w.X0, n * sizeof(double))) != hipSuccess ||
-        (e = hipMalloc(&w.X1, n * sizeof(double))) != hipSuccess ||
-        (e = hipMalloc(&w.T, n * sizeof(double))) != hipSuccess ||
-        (e = hipMalloc(&w.flags, 3 * n)) != hipSuccess ||
-        (e = hipMalloc(&w.hi_in, n * sizeof(int))) != hipSuccess ||
-        (e = hipMalloc(&w.hi_out, n * sizeof(int))) != hipSuccess ||
+    if ((e = hipMalloc(&w.R1, nn * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&w.X0, nn * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&w.X1, nn * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&w.T, nn * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&w.flags, 3 * nn)) != hipSuccess ||
+        (e = hipMalloc(&w.hi_in, nn * sizeof(int))) != hipSuccess ||
+        (e = hipMalloc(&w.hi_out, nn * sizeof(int))) != hipSuccess ||
+        (e = hipMalloc(&w.hub_start_in, (nn + 1) * sizeof(int))) != hipSuccess ||
+        (e = hipMalloc(&w.hub_start_out, (nn + 1) * sizeof(int))) != hipSuccess ||
+        (e = hipMalloc(&w.chunk_hub_in, nc * sizeof(int))) != hipSuccess ||
+        (e = hipMalloc(&w.chunk_hub_out, nc * sizeof(int))) != hipSuccess ||
+        (e = hipMalloc(&w.hub_part, nc * sizeof(double))) != hipSuccess ||
         (e = hipMalloc(&w.tile_counts, 2 * nt * sizeof(int) + 64)) != hipSuccess ||
         (e = hipMalloc(&w.partials, np * sizeof(double))) != hipSuccess) {
       (void)hipGetLastError();
-      (void)hipFree(w.R1); (void)hipFree(w.X0); (void)hipFree(w.X1); (void)hipFree(w.T); (void)hipFree(w.flags);
-      (void)hipFree(w.hi_in); (void)hipFree(w.hi_out); (void)hipFree(w.tile_counts); (void)hipFree(w.partials);
-      w.R1 = w.X0 = w.X1 = w.T = nullptr;
-      w.flags = nullptr;
-      w.hi_in = w.hi_out = w.tile_counts = nullptr;
-      w.partials = nullptr;
+      free_arrays(w);
       return fail(e == hipErrorOutOfMemory ? PR_ENOMEM : PR_EHIP,
                   std::string("workspace allocation: ") + hipGetErrorString(e));
     }
-    w.cap_n = n;
+    w.cap_n = nn;
+    w.cap_chunks = nc;
     w.cap_partials = np;
   }
   *out = &w;
@@ -194,17 +216,19 @@ int check_params(double alpha, double tol, int max_iter) {
   return PR_OK;
 }
 
-// Alg. 4 on an offsets array; hub lists into `hi`, class counts into
-// counts[slot], counts[slot+1] (device).
-int partition(Workspace &w, const int *off, int n, int t1, int t2, int *hi, int slot,
-              hipStream_t s) {
+// Alg. 4 on an offsets array: class lists into `hi`, class sizes into
+// counts[slot], counts[slot + 1]; then the chunk plan of the split class.
+int partition(Workspace &w, const int *off, int n, int t1, int t2, int CH, int *hi, int slot,
+              int chunk_slot, int *hub_start, int *chunk_hub, hipStream_t s) {
   const int nt = (int)ntiles_for(n);
   hipLaunchKernelGGL(k_part_count, dim3(nt), dim3(kBlock), 0, s, off, n, t1, t2, w.tile_counts,
                      nt);
   hipLaunchKernelGGL(k_part_scan, dim3(1), dim3(kFinalBlock), 0, s, w.tile_counts, nt,
                      w.counts + slot);
   hipLaunchKernelGGL(k_part_scatter, dim3(nt), dim3(kBlock), 0, s, off, n, t1, t2,
-                     w.tile_counts, nt, w.counts + slot, hi);
+                     w.tile_counts, nt, (const int *)(w.counts + slot), hi);
+  hipLaunchKernelGGL(k_hub_plan, dim3(1), dim3(kFinalBlock), 0, s, off, (const int *)hi, w.counts,
+                     slot, chunk_slot, CH, hub_start, chunk_hub);
   LAUNCH_TRY();
   return PR_OK;
 }
@@ -287,14 +311,18 @@ int run_static(const pr_csr *g, double alpha, double tol, int max_iter, const do
                double *ranks_out) {
   hipStream_t s = t_stream;
   const int n = g->n;
+  const pr_tuning tn = g_tuning;
   Workspace *wp = nullptr;
-  int rc = get_ws((size_t)n, &wp);
+  int rc = get_ws((size_t)n, (size_t)g->m, tn.hub_chunk_edges, tn.grid_blocks, &wp);
   if (rc) return rc;
   Workspace &w = *wp;
+  const int B = grid_blocks(w, tn, k_rank_static);
+  const int np = B + kHubFinalizeBlocks;
   CallTimer timer(w, s);
-  const pr_tuning tn = g_tuning;
   hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, s, w.ctrl);
-  rc = partition(w, g->in_offsets, n, tn.lane_max_degree, tn.wave_max_degree, w.hi_in, 0, s);
+  rc = partition(w, g->in_offsets, n, tn.lane_max_degree, tn.wave_max_degree,
+                 tn.hub_chunk_edges, w.hi_in, kInWave, kInChunks, w.hub_start_in, w.chunk_hub_in,
+                 s);
   if (rc) return rc;
   // R[0] is the caller's output vector; with `init` (which may alias it) the
   // start vector is copied into it.
@@ -303,21 +331,22 @@ int run_static(const pr_csr *g, double alpha, double tol, int max_iter, const do
   hipLaunchKernelGGL(k_static_init, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n,
                      g->out_offsets, init, R[0], X[0]);
   LAUNCH_TRY();
-  HIP_TRY(hipMemcpyAsync(w.host_counts, w.counts, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  const int n1 = w.host_counts[0], n2 = w.host_counts[1];
-  const RankGrid grid = rank_grid(n, n1, n2);
   const double C0 = (1.0 - alpha) / (double)n;
-  const int t1 = tn.lane_max_degree;
+  const int t1 = tn.lane_max_degree, CH = tn.hub_chunk_edges;
   auto launch = [&](int it, bool prof, hipEvent_t after) -> int {
     const int a = it & 1, b = a ^ 1;
-    hipLaunchKernelGGL(k_rank_static, dim3(grid.total()), dim3(kBlock), 0, s, g->in_offsets,
-                       g->in_sources, g->out_offsets, (const double *)X[a], (const double *)R[a],
-                       R[b], X[b], (const int *)w.hi_in, n1, grid.nb2, grid.nb1, n, t1, C0,
-                       alpha, w.partials, (const Ctrl *)w.ctrl);
+    hipLaunchKernelGGL(k_rank_static, dim3(B), dim3(kBlock), 0, s, g->in_offsets, g->in_sources,
+                       g->out_offsets, (const double *)X[a], (const double *)R[a], R[b], X[b],
+                       (const int *)w.hi_in, (const int *)w.counts, (const int *)w.hub_start_in,
+                       (const int *)w.chunk_hub_in, w.hub_part, CH, n, t1, C0, alpha, w.partials,
+                       (const Ctrl *)w.ctrl);
     if (prof) HIP_TRY(hipEventRecord(after, s));
+    hipLaunchKernelGGL(k_hub_finalize_static, dim3(kHubFinalizeBlocks), dim3(kBlock), 0, s,
+                       (const int *)w.hi_in, (const int *)w.counts, (const int *)w.hub_start_in,
+                       (const double *)w.hub_part, g->out_offsets, (const double *)R[a], R[b],
+                       X[b], C0, alpha, w.partials + B, (const Ctrl *)w.ctrl);
     hipLaunchKernelGGL(k_linf_final, dim3(1), dim3(kFinalBlock), 0, s,
-                       (const double *)w.partials, grid.total(), w.ctrl, tol, it);
+                       (const double *)w.partials, np, w.ctrl, tol, it);
     LAUNCH_TRY();
     return PR_OK;
   };
@@ -340,21 +369,26 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
                          double tau_p, int max_iter, bool prune, double *ranks_out) {
   hipStream_t s = t_stream;
   const int n = g->n;
+  const pr_tuning tn = g_tuning;
   Workspace *wp = nullptr;
-  int rc = get_ws((size_t)n, &wp);
+  int rc = get_ws((size_t)n, (size_t)g->m, tn.hub_chunk_edges, tn.grid_blocks, &wp);
   if (rc) return rc;
   Workspace &w = *wp;
+  const int B = prune ? grid_blocks(w, tn, k_rank_dfp<true>) : grid_blocks(w, tn, k_rank_dfp<false>);
+  const int np = B + kHubFinalizeBlocks;
   CallTimer timer(w, s);
-  const pr_tuning tn = g_tuning;
   uint8_t *dV = w.flags, *dN = w.flags + n, *cv = w.flags + 2 * (size_t)n;
   double *R = ranks_out;
+  const int t1 = tn.lane_max_degree, t_exp = tn.expand_lane_max_degree, CH = tn.hub_chunk_edges;
   hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, s, w.ctrl);
   hipLaunchKernelGGL(k_dfp_init, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, prev, R,
                      dV, dN, cv);
   LAUNCH_TRY();
-  rc = partition(w, g->in_offsets, n, tn.lane_max_degree, tn.wave_max_degree, w.hi_in, 0, s);
+  rc = partition(w, g->in_offsets, n, t1, tn.wave_max_degree, CH, w.hi_in, kInWave, kInChunks,
+                 w.hub_start_in, w.chunk_hub_in, s);
   if (rc) return rc;
-  rc = partition(w, g->out_offsets, n, tn.expand_lane_max_degree, INT_MAX, w.hi_out, 2, s);
+  rc = partition(w, g->out_offsets, n, t_exp, tn.wave_max_degree, CH, w.hi_out, kOutWave,
+                 kOutChunks, w.hub_start_out, w.chunk_hub_out, s);
   if (rc) return rc;
   const int nd = del ? del->count : 0, ni = ins ? ins->count : 0;
   if (nd + ni > 0) {
@@ -363,19 +397,15 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
                        ins ? ins->src : nullptr, ni, n, dV, dN, w.ctrl);
     LAUNCH_TRY();
   }
-  HIP_TRY(hipMemcpyAsync(w.host_counts, w.counts, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync(&w.host_ctrl[0], w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  if (w.host_ctrl[0].err) return fail(PR_EBATCH, "batch vertex ID outside [0, n)");
-  const int n1 = w.host_counts[0], n2 = w.host_counts[1], no1 = w.host_counts[2];
-  const RankGrid grid = rank_grid(n, n1, n2);
-  const int nbo1 = (no1 + kWavesPerBlock - 1) / kWavesPerBlock;
-  const int nb_apply = nbo1 + (n + kBlock - 1) / kBlock;
-  const int t1 = tn.lane_max_degree, t_exp = tn.expand_lane_max_degree;
+  auto apply_expand = [&](int it) {
+    hipLaunchKernelGGL(k_apply_expand, dim3(B), dim3(kBlock), 0, s, g->out_offsets,
+                       g->out_targets, R, (const double *)w.T, dV, (const uint8_t *)dN, cv,
+                       (const int *)w.hi_out, (const int *)w.counts,
+                       (const int *)w.hub_start_out, (const int *)w.chunk_hub_out, CH, n, t_exp,
+                       (const Ctrl *)w.ctrl, it);
+  };
   // initial expandAffected (Alg. 2, after initialAffected)
-  hipLaunchKernelGGL(k_apply_expand, dim3(nb_apply), dim3(kBlock), 0, s, g->out_offsets,
-                     g->out_targets, R, (const double *)w.T, dV, dN, cv, (const int *)w.hi_out,
-                     no1, nbo1, n, t_exp, (const Ctrl *)w.ctrl, -1);
+  apply_expand(-1);
   LAUNCH_TRY();
   if (t_profiling) {
     hipLaunchKernelGGL(k_count_flags, dim3(std::min(1024, (n + kBlock - 1) / kBlock)),
@@ -384,22 +414,32 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
   }
   const double C0 = (1.0 - alpha) / (double)n;
   auto launch = [&](int it, bool prof, hipEvent_t after) -> int {
-    if (prune)
-      hipLaunchKernelGGL(k_rank_dfp<true>, dim3(grid.total()), dim3(kBlock), 0, s, g->in_offsets,
+    if (prune) {
+      hipLaunchKernelGGL(k_rank_dfp<true>, dim3(B), dim3(kBlock), 0, s, g->in_offsets,
                          g->in_sources, g->out_offsets, (const double *)R, w.T, dV, dN, cv,
-                         (const int *)w.hi_in, n1, grid.nb2, grid.nb1, n, t1, C0, alpha, tau_f,
-                         tau_p, w.partials, (const Ctrl *)w.ctrl);
-    else
-      hipLaunchKernelGGL(k_rank_dfp<false>, dim3(grid.total()), dim3(kBlock), 0, s,
-                         g->in_offsets, g->in_sources, g->out_offsets, (const double *)R, w.T, dV,
-                         dN, cv, (const int *)w.hi_in, n1, grid.nb2, grid.nb1, n, t1, C0, alpha,
-                         tau_f, tau_p, w.partials, (const Ctrl *)w.ctrl);
-    if (prof) HIP_TRY(hipEventRecord(after, s));
+                         (const int *)w.hi_in, (const int *)w.counts,
+                         (const int *)w.hub_start_in, (const int *)w.chunk_hub_in, w.hub_part, CH,
+                         n, t1, C0, alpha, tau_f, tau_p, w.partials, (const Ctrl *)w.ctrl);
+      if (prof) HIP_TRY(hipEventRecord(after, s));
+      hipLaunchKernelGGL(k_hub_finalize_dfp<true>, dim3(kHubFinalizeBlocks), dim3(kBlock), 0, s,
+                         (const int *)w.hi_in, (const int *)w.counts, (const int *)w.hub_start_in,
+                         (const double *)w.hub_part, g->out_offsets, (const double *)R, w.T, dV,
+                         dN, cv, C0, alpha, tau_f, tau_p, w.partials + B, (const Ctrl *)w.ctrl);
+    } else {
+      hipLaunchKernelGGL(k_rank_dfp<false>, dim3(B), dim3(kBlock), 0, s, g->in_offsets,
+                         g->in_sources, g->out_offsets, (const double *)R, w.T, dV, dN, cv,
+                         (const int *)w.hi_in, (const int *)w.counts,
+                         (const int *)w.hub_start_in, (const int *)w.chunk_hub_in, w.hub_part, CH,
+                         n, t1, C0, alpha, tau_f, tau_p, w.partials, (const Ctrl *)w.ctrl);
+      if (prof) HIP_TRY(hipEventRecord(after, s));
+      hipLaunchKernelGGL(k_hub_finalize_dfp<false>, dim3(kHubFinalizeBlocks), dim3(kBlock), 0, s,
+                         (const int *)w.hi_in, (const int *)w.counts, (const int *)w.hub_start_in,
+                         (const double *)w.hub_part, g->out_offsets, (const double *)R, w.T, dV,
+                         dN, cv, C0, alpha, tau_f, tau_p, w.partials + B, (const Ctrl *)w.ctrl);
+    }
     hipLaunchKernelGGL(k_linf_final, dim3(1), dim3(kFinalBlock), 0, s,
-                       (const double *)w.partials, grid.total(), w.ctrl, tol, it);
-    hipLaunchKernelGGL(k_apply_expand, dim3(nb_apply), dim3(kBlock), 0, s, g->out_offsets,
-                       g->out_targets, R, (const double *)w.T, dV, dN, cv,
-                       (const int *)w.hi_out, no1, nbo1, n, t_exp, (const Ctrl *)w.ctrl, it);
+                       (const double *)w.partials, np, w.ctrl, tol, it);
+    apply_expand(it);
     LAUNCH_TRY();
     return PR_OK;
   };
@@ -408,7 +448,9 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
   if (rc) return rc;
   timer.stop();
   HIP_TRY(hipStreamSynchronize(s));
-  if (t_profiling) t_stats.affected_initial = w.host_ctrl[(launched - 1) % kRing].aux[0];
+  const Ctrl &last = w.host_ctrl[(launched - 1) % kRing];
+  if (last.err) return fail(PR_EBATCH, "batch vertex ID outside [0, n)");
+  if (t_profiling) t_stats.affected_initial = last.aux[0];
   t_stats.total_ms = timer.ms();
   collect_profile(w, iters);
   return t_stats.converged ? PR_OK : PR_NOT_CONVERGED;
@@ -472,7 +514,7 @@ int pr_validate_csr(const pr_csr *g) {
   std::lock_guard<std::mutex> lock(g_mu);
   hipStream_t s = t_stream;
   Workspace *wp = nullptr;
-  if ((rc = get_ws(1, &wp))) return rc;
+  if ((rc = get_ws(1, 1, 4096, 0, &wp))) return rc;
   Workspace &w = *wp;
   int *err = w.counts;  // reuse a device int
   const int n = g->n, nb = (n + kBlock - 1) / kBlock;
@@ -512,9 +554,12 @@ int pr_set_tuning(const pr_tuning *t) {
     return PR_OK;
   }
   if (t->lane_max_degree < 0 || t->wave_max_degree < t->lane_max_degree ||
-      t->expand_lane_max_degree < 0 || t->iters_per_sync < 1 || t->iters_per_sync >= kRing)
+      t->expand_lane_max_degree < 0 || t->expand_lane_max_degree > t->wave_max_degree ||
+      t->iters_per_sync < 1 || t->iters_per_sync >= kRing || t->hub_chunk_edges < 0 ||
+      t->grid_blocks < 0 || t->grid_blocks > (1 << 20))
     return fail(PR_EINVAL, "tuning field out of range");
   g_tuning = *t;
+  if (g_tuning.hub_chunk_edges == 0) g_tuning.hub_chunk_edges = 4096;
   return PR_OK;
 }
 

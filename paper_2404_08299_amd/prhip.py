@@ -42,7 +42,12 @@ class PrEdges(ctypes.Structure):
 class PrTuning(ctypes.Structure):
     _fields_ = [("lane_max_degree", ctypes.c_int32), ("wave_max_degree", ctypes.c_int32),
                 ("expand_lane_max_degree", ctypes.c_int32), ("iters_per_sync", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("hub_chunk_edges", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
+
+
+TUNING_FIELDS = ("lane_max_degree", "wave_max_degree", "expand_lane_max_degree",
+                 "iters_per_sync", "hub_chunk_edges", "grid_blocks")
 
 
 class PrStats(ctypes.Structure):
@@ -240,8 +245,7 @@ def get_tuning() -> dict:
     lib = load_library()
     t = PrTuning()
     lib.pr_get_tuning(ctypes.byref(t))
-    return dict(lane_max_degree=t.lane_max_degree, wave_max_degree=t.wave_max_degree,
-                expand_lane_max_degree=t.expand_lane_max_degree, iters_per_sync=t.iters_per_sync)
+    return {f: getattr(t, f) for f in TUNING_FIELDS}
 
 
 def set_tuning(**kw) -> None:
@@ -252,9 +256,11 @@ def set_tuning(**kw) -> None:
         _check(lib.pr_set_tuning(None), lib)
         return
     cur = get_tuning()
+    unknown = set(kw) - set(TUNING_FIELDS)
+    if unknown:
+        raise KeyError(f"unknown tuning fields {sorted(unknown)}")
     cur.update(kw)
-    t = PrTuning(cur["lane_max_degree"], cur["wave_max_degree"], cur["expand_lane_max_degree"],
-                 cur["iters_per_sync"])
+    t = PrTuning(*[cur[f] for f in TUNING_FIELDS])
     _check(lib.pr_set_tuning(ctypes.byref(t)), lib)
 
 

@@ -70,19 +70,24 @@ def test_argument_errors_before_hip(lib):
 def test_tuning_validation(lib):
     t = prhip.PrTuning()
     assert lib.pr_get_tuning(ctypes.byref(t)) == 0
-    default = (t.lane_max_degree, t.wave_max_degree, t.expand_lane_max_degree, t.iters_per_sync)
-    bad = prhip.PrTuning(10, 5, 3, 1)  # lane > wave
-    assert lib.pr_set_tuning(ctypes.byref(bad)) == prhip.PR_EINVAL
-    bad = prhip.PrTuning(1, 5, 3, 0)
-    assert lib.pr_set_tuning(ctypes.byref(bad)) == prhip.PR_EINVAL
-    good = prhip.PrTuning(4, 64, 8, 3)
+    default = prhip.get_tuning()
+    assert default["hub_chunk_edges"] > 0
+    for bad in [prhip.PrTuning(10, 5, 3, 1, 4096, 0),   # lane > wave
+                prhip.PrTuning(1, 5, 3, 0, 4096, 0),    # iters_per_sync < 1
+                prhip.PrTuning(1, 5, 9, 1, 4096, 0),    # expand lane > wave
+                prhip.PrTuning(1, 5, 3, 1, -1, 0),      # chunk < 0
+                prhip.PrTuning(1, 5, 3, 1, 64, -2)]:    # grid < 0
+        assert lib.pr_set_tuning(ctypes.byref(bad)) == prhip.PR_EINVAL
+    good = prhip.PrTuning(4, 64, 8, 3, 0, 100)
     assert lib.pr_set_tuning(ctypes.byref(good)) == 0
-    assert prhip.get_tuning()["wave_max_degree"] == 64
+    got = prhip.get_tuning()
+    assert got["wave_max_degree"] == 64 and got["hub_chunk_edges"] == 4096 and got["grid_blocks"] == 100
+    prhip.set_tuning(hub_chunk_edges=128)
+    assert prhip.get_tuning()["hub_chunk_edges"] == 128
+    with pytest.raises(KeyError):
+        prhip.set_tuning(bogus=1)
     assert lib.pr_set_tuning(None) == 0
-    t2 = prhip.PrTuning()
-    lib.pr_get_tuning(ctypes.byref(t2))
-    assert (t2.lane_max_degree, t2.wave_max_degree, t2.expand_lane_max_degree,
-            t2.iters_per_sync) == default
+    assert prhip.get_tuning() == default
 
 
 def test_binding_has_no_cpu_fallback():

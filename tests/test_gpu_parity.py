@@ -18,7 +18,8 @@ if not torch.cuda.is_available():
 from paper_2404_08299_amd import prhip  # noqa: E402
 
 ALL_LANE = dict(lane_max_degree=1 << 30, wave_max_degree=1 << 30, expand_lane_max_degree=1 << 30)
-ALL_CLASSES = dict(lane_max_degree=2, wave_max_degree=12, expand_lane_max_degree=2)
+ALL_CLASSES = dict(lane_max_degree=2, wave_max_degree=12, expand_lane_max_degree=2,
+                   hub_chunk_edges=16)
 
 
 @pytest.fixture(autouse=True)
@@ -63,8 +64,12 @@ def test_static_all_lane_bitwise():
         assert np.array_equal(r, o.ranks)
 
 
-@pytest.mark.parametrize("tuning", [ALL_CLASSES, dict(lane_max_degree=0, wave_max_degree=0),
-                                    dict(lane_max_degree=8, wave_max_degree=200)])
+@pytest.mark.parametrize("tuning", [ALL_CLASSES, dict(lane_max_degree=0, wave_max_degree=0,
+                                                         expand_lane_max_degree=0),
+                                    dict(lane_max_degree=8, wave_max_degree=200),
+                                    dict(lane_max_degree=4, wave_max_degree=8, hub_chunk_edges=8,
+                                         expand_lane_max_degree=4, grid_blocks=7),
+                                    dict(grid_blocks=1), dict(hub_chunk_edges=64, grid_blocks=3000)])
 def test_static_every_class(tuning):
     prhip.set_tuning(**tuning)
     g = gg.rmat_graph(13, 8, seed=2)
@@ -85,6 +90,7 @@ def test_static_ragged_sizes(n):
 
 
 def test_static_closed_forms():
+    prhip.set_tuning(hub_chunk_edges=512)
     a = 0.85
     # in-star with a hub above every lane/wave threshold (workgroup class)
     k = 6000
@@ -206,12 +212,16 @@ def test_df_nd_vs_oracle(mode):
     assert abs(res.iterations - o.iters) <= 1
 
 
-def test_dfp_every_class():
-    prhip.set_tuning(**ALL_CLASSES)
+@pytest.mark.parametrize("tuning", [ALL_CLASSES, dict(grid_blocks=1),
+                                    dict(lane_max_degree=4, wave_max_degree=8, hub_chunk_edges=8,
+                                         expand_lane_max_degree=4, grid_blocks=5)])
+def test_dfp_every_class(tuning):
+    prhip.set_tuning(**tuning)
     g0, g1, b, prev = dynamic_case(scale=13, frac=1e-3, seed=3)
     r, res = gpu_dfp(g1, b, prev)
     o = oracle.dfp(g1.n, *g1.edges(), b, prev)
     assert np.abs(r - o.ranks).max() <= 1e-9
+    assert abs(res.iterations - o.iters) <= 1
 
 
 def test_dfp_empty_batch_and_inplace():
