@@ -97,6 +97,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=2)
+    ap.add_argument("--order", default="scrambled", choices=["scrambled", "natural", "degree"],
+                    help="vertex numbering of the input: Graph500 scrambled IDs, R-MAT's own "
+                         "IDs, or relabelled by descending out-degree")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run the calibration copy kernel")
     args = ap.parse_args()
@@ -123,7 +126,10 @@ def main():
 
     fracs = [float(x) for x in args.fractions.split(",")]
     t = time.time()
-    g0 = gg.rmat_graph(args.scale, args.edge_factor, seed=args.seed)
+    g0 = gg.rmat_graph(args.scale, args.edge_factor, seed=args.seed,
+                       scramble=(args.order == "scrambled"))
+    if args.order == "degree":
+        g0 = gg.relabel(g0, gg.degree_order(g0, "out"))
     n = g0.n
     log(f"R-MAT scale {args.scale}: n={n} m={g0.m} ({time.time() - t:.1f} s)")
     dg0 = prhip.DeviceGraph.from_host(g0)
@@ -259,6 +265,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"rmat{args.scale}_ef{int(args.edge_factor)}_static_and_dfp",
+                   "vertex_order": args.order,
                    "n": n, "m": g0.m, "scale": args.scale, "edge_factor": args.edge_factor,
                    "seed": args.seed, "batch_fractions": fracs, "alpha": 0.85, "tol": 1e-10,
                    "frontier_tol": 1e-6, "prune_tol": 1e-6, "max_iter": 500,

@@ -152,7 +152,11 @@ int pr_validate_csr(const pr_csr *csr);
  *                      this many edges, one workgroup each; their partial
  *                      sums are added in chunk order (0 = default 4096)
  *   grid_blocks        workgroups of the fixed-size launches that stride over
- *                      the work (0 = eight per compute unit)
+ *                      the work (0 = as many as can be resident at once)
+ *   relabel            gather-side locality renumbering (degree-based
+ *                      grouping of the sources, built inside each call):
+ *                      1 on, 0 off, -1 automatic (on when n >= 2^20). Rows and
+ *                      their summation order are unchanged.
  */
 typedef struct pr_tuning {
   int32_t lane_max_degree;
@@ -161,7 +165,8 @@ typedef struct pr_tuning {
   int32_t iters_per_sync;
   int32_t hub_chunk_edges;
   int32_t grid_blocks;
-  int32_t reserved[2];
+  int32_t relabel;
+  int32_t reserved;
 } pr_tuning;
 
 /* Set (NULL = defaults) or read the process-wide tuning. PR_EINVAL if a

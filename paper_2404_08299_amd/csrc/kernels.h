@@ -71,6 +71,24 @@ enum CountSlot {
   kNumCounts = 8
 };
 
+// Streamed data (CSR arrays, a vertex's own rank, new ranks) is read and
+// written with the non-temporal hint so that it does not push the gathered
+// contribution vector out of the caches.
+template <class T>
+__device__ __forceinline__ T ld_nt(const T *p) {
+  return __builtin_nontemporal_load(p);
+}
+template <class T>
+__device__ __forceinline__ void st_nt(T *p, T v) {
+  __builtin_nontemporal_store(v, p);
+}
+
+// Position of vertex v in the contribution vector (the gather-side
+// numbering; identity when no relabelling is in use).
+__device__ __forceinline__ int xpos(const int *__restrict__ pos, int v) {
+  return pos ? ld_nt(pos + v) : v;
+}
+
 __device__ __forceinline__ int deg_class(int deg, int t1, int t2) {
   return deg <= t1 ? 0 : (deg <= t2 ? 1 : 2);
 }
@@ -239,13 +257,14 @@ __global__ __launch_bounds__(kFinalBlock) void k_hub_plan(const int *__restrict_
 // R = 1/n, X = R / |out(v)| (Alg. 1 initialisation). With `init` the start
 // vector is given (Naive-dynamic, Sec. 3.4.1); it may alias R.
 __global__ __launch_bounds__(kBlock) void k_static_init(int n, const int *__restrict__ out_off,
+                                                        const int *__restrict__ pos,
                                                         const double *init, double *R,
                                                         double *__restrict__ X) {
   const int v = blockIdx.x * kBlock + threadIdx.x;
   if (v < n) {
     const double r = init ? init[v] : 1.0 / (double)n;
     R[v] = r;
-    X[v] = r / (double)(out_off[v + 1] - out_off[v]);
+    X[xpos(pos, v)] = r / (double)(out_off[v + 1] - out_off[v]);
   }
 }
 
@@ -257,78 +276,54 @@ __device__ __forceinline__ double row_sum_seq(const int *__restrict__ src,
   double c = 0.0;
   int e = e0;
   for (; e + 4 <= e1; e += 4) {
-    const int u0 = src[e], u1 = src[e + 1], u2 = src[e + 2], u3 = src[e + 3];
+    const int u0 = ld_nt(src + e), u1 = ld_nt(src + e + 1), u2 = ld_nt(src + e + 2),
+              u3 = ld_nt(src + e + 3);
     const double x0 = X[u0], x1 = X[u1], x2 = X[u2], x3 = X[u3];
     c = c + x0;
     c = c + x1;
     c = c + x2;
     c = c + x3;
   }
-  for (; e < e1; ++e) c = c + X[src[e]];
+  for (; e < e1; ++e) c = c + X[ld_nt(src + e)];
   return c;
 }
 
-// Same for DF-P, which reads ranks and degrees directly (only affected rows
-// are read, so there is no per-vertex contribution pass).
-__device__ __forceinline__ double row_sum_seq_rd(const int *__restrict__ src,
-                                                 const int *__restrict__ out_off,
-                                                 const double *__restrict__ R, int e0, int e1) {
-  double c = 0.0;
-  int e = e0;
-  for (; e + 2 <= e1; e += 2) {
-    const int u0 = src[e], u1 = src[e + 1];
-    const double r0 = R[u0], r1 = R[u1];
-    const int d0 = out_off[u0 + 1] - out_off[u0], d1 = out_off[u1 + 1] - out_off[u1];
-    c = c + r0 / (double)d0;
-    c = c + r1 / (double)d1;
-  }
-  for (; e < e1; ++e) {
-    const int u = src[e];
-    c = c + R[u] / (double)(out_off[u + 1] - out_off[u]);
-  }
-  return c;
-}
-
-// Contribution of in-edge e: X[src[e]] (Static) or R[u]/|out(u)| (DF-P).
-template <bool DYN>
+// Contribution of in-edge e: X[src[e]].
 __device__ __forceinline__ double contrib(int e, const int *__restrict__ src,
-                                          const int *__restrict__ out_off,
-                                          const double *__restrict__ XR) {
-  const int u = src[e];
-  if (DYN) return XR[u] / (double)(out_off[u + 1] - out_off[u]);
-  return XR[u];
+                                          const double *__restrict__ X) {
+  return X[ld_nt(src + e)];
 }
 
 // Strided partial sum over [e0, e1) with stride S starting at e0 + t, four
 // independent accumulators combined in a fixed order.
-template <bool DYN, int S>
+template <int S>
 __device__ __forceinline__ double strided_sum(int e0, int e1, int t, const int *__restrict__ src,
-                                              const int *__restrict__ out_off,
-                                              const double *__restrict__ XR) {
+                                              const double *__restrict__ X) {
   double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
   int e = e0 + t;
   for (; e + 3 * S < e1; e += 4 * S) {
-    c0 += contrib<DYN>(e, src, out_off, XR);
-    c1 += contrib<DYN>(e + S, src, out_off, XR);
-    c2 += contrib<DYN>(e + 2 * S, src, out_off, XR);
-    c3 += contrib<DYN>(e + 3 * S, src, out_off, XR);
+    c0 += contrib(e, src, X);
+    c1 += contrib(e + S, src, X);
+    c2 += contrib(e + 2 * S, src, X);
+    c3 += contrib(e + 3 * S, src, X);
   }
-  for (; e < e1; e += S) c0 += contrib<DYN>(e, src, out_off, XR);
+  for (; e < e1; e += S) c0 += contrib(e, src, X);
   return (c0 + c1) + (c2 + c3);
 }
 
 // ------------------------------------------------------------ finishing
 struct StaticOut {
   const int *out_off;
+  const int *pos;
   const double *R;
   double *Rn, *Xn;
   double C0, alpha;
   // Eq. 1 for one vertex: R_new, its contribution, and |R_new - R|.
   __device__ __forceinline__ double finish(int v, double c) const {
     const double r = C0 + alpha * c;
-    Rn[v] = r;
-    Xn[v] = r / (double)(out_off[v + 1] - out_off[v]);
-    return fabs(r - R[v]);
+    st_nt(Rn + v, r);
+    Xn[xpos(pos, v)] = r / (double)(ld_nt(out_off + v + 1) - ld_nt(out_off + v));
+    return fabs(r - ld_nt(R + v));
   }
 };
 
@@ -366,7 +361,7 @@ struct DynOut {
 template <bool DYN, class Out>
 __device__ __forceinline__ void rank_update(
     const int *__restrict__ in_off, const int *__restrict__ in_src,
-    const int *__restrict__ out_off, const double *__restrict__ XR, const uint8_t *dV,
+    const double *__restrict__ X, const uint8_t *dV,
     uint8_t *dN, const int *__restrict__ hi, const int *__restrict__ counts,
     const int *__restrict__ hub_start, const int *__restrict__ chunk_hub,
     double *__restrict__ hub_part, int CH, int n, int t1, const Out &out,
@@ -408,7 +403,7 @@ __device__ __forceinline__ void rank_update(
     if (f) { s_c[off + p] = c; s_v[off + p] = v; s_e0[off + p] = e0; s_e1[off + p] = e1; }
     __syncthreads();
     for (int k = 0; k < cnt; ++k) {
-      double s = strided_sum<DYN, kBlock>(s_e0[k], s_e1[k], tid, in_src, out_off, XR);
+      double s = strided_sum<kBlock>(s_e0[k], s_e1[k], tid, in_src, X);
       s = block_sum<kBlock>(s, lds);
       if (tid == 0) hub_part[s_c[k]] = s;
     }
@@ -434,7 +429,7 @@ __device__ __forceinline__ void rank_update(
         mask &= mask - 1;
         const int vv = __shfl(v, j);
         const int e0 = in_off[vv], e1 = in_off[vv + 1];
-        double c = strided_sum<DYN, kWave>(e0, e1, lane, in_src, out_off, XR);
+        double c = strided_sum<kWave>(e0, e1, lane, in_src, X);
         c = wave_sum(c);
         if (lane == 0) dmax = fmax(dmax, out.finish(vv, c));
       }
@@ -447,11 +442,10 @@ __device__ __forceinline__ void rank_update(
     for (int t = blockIdx.x; t < ntiles; t += B) {
       const int v = t * kBlock + tid;
       if (v < n) {
-        const int e0 = in_off[v], e1 = in_off[v + 1];
+        const int e0 = ld_nt(in_off + v), e1 = ld_nt(in_off + v + 1);
         if (e1 - e0 <= t1) {
           if (!DYN || dV[v]) {
-            const double c = DYN ? row_sum_seq_rd(in_src, out_off, XR, e0, e1)
-                                 : row_sum_seq(in_src, XR, e0, e1);
+            const double c = row_sum_seq(in_src, X, e0, e1);
             dmax = fmax(dmax, out.finish(v, c));
           } else {
             dN[v] = 0;
@@ -464,32 +458,35 @@ __device__ __forceinline__ void rank_update(
   if (tid == 0) partials[blockIdx.x] = dmax;
 }
 
+// in_src: the sources of the in-CSR in the gather-side numbering (pos);
+// X, Xn: contributions in that numbering; R, Rn: ranks in vertex order.
 __global__ __launch_bounds__(kBlock) void k_rank_static(
     const int *__restrict__ in_off, const int *__restrict__ in_src,
-    const int *__restrict__ out_off, const double *__restrict__ X, const double *__restrict__ R,
-    double *__restrict__ Rn, double *__restrict__ Xn, const int *__restrict__ hi,
-    const int *__restrict__ counts, const int *__restrict__ hub_start,
-    const int *__restrict__ chunk_hub, double *__restrict__ hub_part, int CH, int n, int t1,
-    double C0, double alpha, double *__restrict__ partials, const Ctrl *__restrict__ ctrl) {
+    const int *__restrict__ out_off, const int *__restrict__ pos, const double *__restrict__ X,
+    const double *__restrict__ R, double *__restrict__ Rn, double *__restrict__ Xn,
+    const int *__restrict__ hi, const int *__restrict__ counts,
+    const int *__restrict__ hub_start, const int *__restrict__ chunk_hub,
+    double *__restrict__ hub_part, int CH, int n, int t1, double C0, double alpha,
+    double *__restrict__ partials, const Ctrl *__restrict__ ctrl) {
   if (ctrl->done) return;
-  const StaticOut out{out_off, R, Rn, Xn, C0, alpha};
-  rank_update<false>(in_off, in_src, out_off, X, nullptr, nullptr, hi, counts, hub_start,
-                     chunk_hub, hub_part, CH, n, t1, out, partials);
+  const StaticOut out{out_off, pos, R, Rn, Xn, C0, alpha};
+  rank_update<false>(in_off, in_src, X, nullptr, nullptr, hi, counts, hub_start, chunk_hub,
+                     hub_part, CH, n, t1, out, partials);
 }
 
 template <bool PRUNE>
 __global__ __launch_bounds__(kBlock) void k_rank_dfp(
     const int *__restrict__ in_off, const int *__restrict__ in_src,
-    const int *__restrict__ out_off, const double *__restrict__ R, double *__restrict__ T,
-    uint8_t *dV, uint8_t *dN, uint8_t *cv, const int *__restrict__ hi,
+    const int *__restrict__ out_off, const double *__restrict__ X, const double *__restrict__ R,
+    double *__restrict__ T, uint8_t *dV, uint8_t *dN, uint8_t *cv, const int *__restrict__ hi,
     const int *__restrict__ counts, const int *__restrict__ hub_start,
     const int *__restrict__ chunk_hub, double *__restrict__ hub_part, int CH, int n, int t1,
     double C0, double alpha, double tau_f, double tau_p, double *__restrict__ partials,
     const Ctrl *__restrict__ ctrl) {
   if (ctrl->done) return;
   const DynOut<PRUNE> out{out_off, R, T, dV, dN, cv, C0, alpha, tau_f, tau_p};
-  rank_update<true>(in_off, in_src, out_off, R, dV, dN, hi, counts, hub_start, chunk_hub,
-                    hub_part, CH, n, t1, out, partials);
+  rank_update<true>(in_off, in_src, X, dV, dN, hi, counts, hub_start, chunk_hub, hub_part, CH, n,
+                    t1, out, partials);
 }
 
 // Split-class vertices: add the chunk partials in chunk order and finish.
@@ -520,10 +517,11 @@ __device__ __forceinline__ void hub_finalize(const int *__restrict__ hi,
 __global__ __launch_bounds__(kBlock) void k_hub_finalize_static(
     const int *__restrict__ hi, const int *__restrict__ counts, const int *__restrict__ hub_start,
     const double *__restrict__ hub_part, const int *__restrict__ out_off,
-    const double *__restrict__ R, double *__restrict__ Rn, double *__restrict__ Xn, double C0,
-    double alpha, double *__restrict__ partials, const Ctrl *__restrict__ ctrl) {
+    const int *__restrict__ pos, const double *__restrict__ R, double *__restrict__ Rn,
+    double *__restrict__ Xn, double C0, double alpha, double *__restrict__ partials,
+    const Ctrl *__restrict__ ctrl) {
   if (ctrl->done) return;
-  const StaticOut out{out_off, R, Rn, Xn, C0, alpha};
+  const StaticOut out{out_off, pos, R, Rn, Xn, C0, alpha};
   hub_finalize<false>(hi, counts, hub_start, hub_part, nullptr, nullptr, out, partials);
 }
 
@@ -561,11 +559,18 @@ __global__ __launch_bounds__(kFinalBlock) void k_linf_final(const double *__rest
 }
 
 // ------------------------------------------------------------ DF / DF-P
-__global__ __launch_bounds__(kBlock) void k_dfp_init(int n, const double *prev, double *R,
-                                                     uint8_t *dV, uint8_t *dN, uint8_t *cv) {
+// R = R^{t-1} (Alg. 2), its contributions X (gather-side numbering), and
+// cleared flags.
+__global__ __launch_bounds__(kBlock) void k_dfp_init(int n, const int *__restrict__ out_off,
+                                                     const int *__restrict__ pos,
+                                                     const double *prev, double *R,
+                                                     double *__restrict__ X, uint8_t *dV,
+                                                     uint8_t *dN, uint8_t *cv) {
   const int v = blockIdx.x * kBlock + threadIdx.x;
   if (v < n) {
-    if (prev != R) R[v] = prev[v];
+    const double r = prev[v];
+    if (prev != R) R[v] = r;
+    X[xpos(pos, v)] = r / (double)(out_off[v + 1] - out_off[v]);
     dV[v] = 0;
     dN[v] = 0;
     cv[v] = 0;
@@ -596,15 +601,16 @@ __global__ __launch_bounds__(kBlock) void k_mark_initial(const int *__restrict__
 }
 
 // After the convergence check of iteration `it`: copy the new ranks of the
-// vertices updated in it (the swap of Alg. 2; vertices not updated keep
-// their rank), then, unless it converged, expandAffected (Alg. 5): every u
+// vertices updated in it, with their contributions (the swap of Alg. 2;
+// vertices not updated keep their rank), then, unless it converged, expandAffected (Alg. 5): every u
 // with dN[u] marks out(u) in dV. Out-degree classes as for the rank update:
 // lane per vertex over ID tiles, a wavefront per vertex, or one workgroup per
 // chunk of out-edges. dV stores are all 1s (benign races, no atomics).
 // it = -1 is the initial expansion.
 __global__ __launch_bounds__(kBlock) void k_apply_expand(
-    const int *__restrict__ out_off, const int *__restrict__ out_tgt, double *__restrict__ R,
-    const double *__restrict__ T, uint8_t *dV, const uint8_t *dN, uint8_t *cv,
+    const int *__restrict__ out_off, const int *__restrict__ out_tgt, const int *__restrict__ pos,
+    double *__restrict__ R, double *__restrict__ X, const double *__restrict__ T, uint8_t *dV,
+    const uint8_t *dN, uint8_t *cv,
     const int *__restrict__ hi_out, const int *__restrict__ counts,
     const int *__restrict__ hub_start, const int *__restrict__ chunk_hub, int CH, int n,
     int t_exp, const Ctrl *__restrict__ ctrl, int it) {
@@ -673,7 +679,9 @@ __global__ __launch_bounds__(kBlock) void k_apply_expand(
     const int v = t * kBlock + tid;
     if (v < n) {
       if (cv[v]) {
-        R[v] = T[v];
+        const double r = T[v];
+        R[v] = r;
+        X[xpos(pos, v)] = r / (double)(out_off[v + 1] - out_off[v]);
         cv[v] = 0;
       }
       if (expand && dN[v]) {
@@ -683,6 +691,86 @@ __global__ __launch_bounds__(kBlock) void k_apply_expand(
       }
     }
   }
+}
+
+// ------------------------------------------------------------ locality
+// Gather-side renumbering by degree-based grouping: vertices are grouped by
+// floor(log2(out-degree)), highest group first, and keep their ID order
+// inside a group. The contributions of high out-degree vertices (the sources
+// most in-edges read) then share cache lines. It is a stable partition into
+// kGroups classes, the k-class form of Alg. 4: per-tile class counts, one
+// exclusive scan over the class-major counts, a ranking scatter.
+constexpr int kGroups = 32;
+
+__device__ __forceinline__ int group_key(int outdeg) {  // 0 = highest degrees
+  // kGroups - 1 - floor(log2(outdeg)) = clz(outdeg); clamped for safety
+  return min(__clz(outdeg), kGroups - 1);
+}
+
+__global__ __launch_bounds__(kBlock) void k_group_count(const int *__restrict__ out_off, int n,
+                                                        int *__restrict__ counts, int ntiles) {
+  __shared__ int c[kGroups];
+  if (threadIdx.x < kGroups) c[threadIdx.x] = 0;
+  __syncthreads();
+  for (int k = 0; k < kPartTile / kBlock; ++k) {
+    const int v = blockIdx.x * kPartTile + k * kBlock + threadIdx.x;
+    if (v < n) atomicAdd(&c[group_key(out_off[v + 1] - out_off[v])], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x < kGroups) counts[(size_t)threadIdx.x * ntiles + blockIdx.x] = c[threadIdx.x];
+}
+
+// In-place exclusive scan of a[0 .. len) by one 1024-thread workgroup.
+__global__ __launch_bounds__(kFinalBlock) void k_scan_flat(int *__restrict__ a, int len) {
+  const int per = (len + kFinalBlock - 1) / kFinalBlock;
+  const int beg = min((int)threadIdx.x * per, len), end = min(beg + per, len);
+  int s = 0;
+  for (int i = beg; i < end; ++i) s += a[i];
+  int total;
+  int run = block_exclusive_scan_1024(s, &total);
+  for (int i = beg; i < end; ++i) { const int x = a[i]; a[i] = run; run += x; }
+}
+
+__global__ __launch_bounds__(kBlock) void k_group_scatter(const int *__restrict__ out_off, int n,
+                                                          const int *__restrict__ base,
+                                                          int ntiles, int *__restrict__ newid) {
+  __shared__ int s_base[kGroups];
+  __shared__ int s_cnt[kWavesPerBlock][kGroups];
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  if (threadIdx.x < kGroups) s_base[threadIdx.x] = base[(size_t)threadIdx.x * ntiles + blockIdx.x];
+  for (int k = 0; k < kPartTile / kBlock; ++k) {
+    const int v = blockIdx.x * kPartTile + k * kBlock + threadIdx.x;
+    const int key = v < n ? group_key(out_off[v + 1] - out_off[v]) : -1;
+    int rank = 0;
+    for (int g = 0; g < kGroups; ++g) {
+      int tot;
+      const int p = wave_prefix_count(key == g, &tot);
+      if (key == g) rank = p;
+      if (lane == 0) s_cnt[w][g] = tot;
+    }
+    __syncthreads();
+    if (v < n) {
+      int off = s_base[key] + rank;
+      for (int i = 0; i < w; ++i) off += s_cnt[i][key];
+      newid[v] = off;
+    }
+    __syncthreads();
+    if (threadIdx.x < kGroups) {
+      int a = 0;
+      for (int i = 0; i < kWavesPerBlock; ++i) a += s_cnt[i][threadIdx.x];
+      s_base[threadIdx.x] += a;
+    }
+    __syncthreads();
+  }
+}
+
+// dst[e] = newid[src[e]]: the in-CSR sources in the gather-side numbering
+// (rows keep their order, so every row sum runs in the original order).
+__global__ __launch_bounds__(kBlock) void k_map_sources(const int *__restrict__ src, int m,
+                                                        const int *__restrict__ newid,
+                                                        int *__restrict__ dst) {
+  for (int e = blockIdx.x * kBlock + threadIdx.x; e < m; e += gridDim.x * kBlock)
+    st_nt(dst + e, newid[ld_nt(src + e)]);
 }
 
 // Count of affected vertices (profiling only).

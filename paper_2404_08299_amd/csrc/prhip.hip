@@ -46,6 +46,7 @@ pr_tuning default_tuning() {
   t.iters_per_sync = 2;
   t.hub_chunk_edges = 4096;
   t.grid_blocks = 0;
+  t.relabel = -1;
   return t;
 }
 pr_tuning g_tuning = default_tuning();
@@ -53,7 +54,7 @@ pr_tuning g_tuning = default_tuning();
 constexpr int kRing = 8;  // pinned control-block snapshots
 
 struct Workspace {
-  size_t cap_n = 0, cap_chunks = 0, cap_partials = 0;
+  size_t cap_n = 0, cap_chunks = 0, cap_partials = 0, cap_m = 0;
   int num_cus = 0;
   double *R1 = nullptr, *X0 = nullptr, *X1 = nullptr, *T = nullptr;
   uint8_t *flags = nullptr;  // dV | dN | cv, n bytes each
@@ -61,7 +62,9 @@ struct Workspace {
   int *hub_start_in = nullptr, *hub_start_out = nullptr;  // [n + 1]
   int *chunk_hub_in = nullptr, *chunk_hub_out = nullptr;  // [cap_chunks]
   double *hub_part = nullptr;                             // [cap_chunks]
-  int *tile_counts = nullptr;  // [2][ntiles]
+  int *newid = nullptr;        // [n] gather-side numbering
+  int *src_p = nullptr;        // [m] in-CSR sources in that numbering
+  int *tile_counts = nullptr;  // [kGroups][ntiles]
   int *counts = nullptr;       // [kNumCounts]
   double *partials = nullptr;  // [cap_partials]
   Ctrl *ctrl = nullptr;
@@ -99,6 +102,8 @@ void free_arrays(Workspace &w) {
   (void)hipFree(w.hub_start_in); (void)hipFree(w.hub_start_out);
   (void)hipFree(w.chunk_hub_in); (void)hipFree(w.chunk_hub_out); (void)hipFree(w.hub_part);
   (void)hipFree(w.tile_counts); (void)hipFree(w.partials);
+  (void)hipFree(w.newid); (void)hipFree(w.src_p);
+  w.newid = w.src_p = nullptr;
   w.R1 = w.X0 = w.X1 = w.T = nullptr;
   w.flags = nullptr;
   w.hi_in = w.hi_out = w.hub_start_in = w.hub_start_out = nullptr;
@@ -106,7 +111,7 @@ void free_arrays(Workspace &w) {
   w.hub_part = nullptr;
   w.tile_counts = nullptr;
   w.partials = nullptr;
-  w.cap_n = w.cap_chunks = w.cap_partials = 0;
+  w.cap_n = w.cap_chunks = w.cap_partials = w.cap_m = 0;
 }
 
 void free_ws(Workspace &w) {
@@ -156,8 +161,10 @@ int get_ws(size_t n, size_t m, int CH, int B, Workspace **out) {
   // <= m / CH + (number of split vertices) <= m / CH + n
   const size_t need_chunks = m / (size_t)CH + n + 1;
   const size_t need_partials = (size_t)B + kHubFinalizeBlocks + 16;
-  if (n > w.cap_n || need_chunks > w.cap_chunks || need_partials > w.cap_partials) {
+  if (n > w.cap_n || m > w.cap_m || need_chunks > w.cap_chunks ||
+      need_partials > w.cap_partials) {
     const size_t nn = std::max(n, w.cap_n);
+    const size_t mm = std::max(m, w.cap_m);
     const size_t nc = std::max(need_chunks, w.cap_chunks);
     const size_t np = std::max(need_partials, w.cap_partials);
     free_arrays(w);
@@ -175,7 +182,9 @@ int get_ws(size_t n, size_t m, int CH, int B, Workspace **out) {
         (e = hipMalloc(&w.chunk_hub_in, nc * sizeof(int))) != hipSuccess ||
         (e = hipMalloc(&w.chunk_hub_out, nc * sizeof(int))) != hipSuccess ||
         (e = hipMalloc(&w.hub_part, nc * sizeof(double))) != hipSuccess ||
-        (e = hipMalloc(&w.tile_counts, 2 * nt * sizeof(int) + 64)) != hipSuccess ||
+        (e = hipMalloc(&w.tile_counts, (size_t)kGroups * nt * sizeof(int) + 64)) != hipSuccess ||
+        (e = hipMalloc(&w.newid, nn * sizeof(int))) != hipSuccess ||
+        (e = hipMalloc(&w.src_p, mm * sizeof(int))) != hipSuccess ||
         (e = hipMalloc(&w.partials, np * sizeof(double))) != hipSuccess) {
       (void)hipGetLastError();
       free_arrays(w);
@@ -183,6 +192,7 @@ int get_ws(size_t n, size_t m, int CH, int B, Workspace **out) {
                   std::string("workspace allocation: ") + hipGetErrorString(e));
     }
     w.cap_n = nn;
+    w.cap_m = mm;
     w.cap_chunks = nc;
     w.cap_partials = np;
   }
@@ -230,6 +240,33 @@ int partition(Workspace &w, const int *off, int n, int t1, int t2, int CH, int *
   hipLaunchKernelGGL(k_hub_plan, dim3(1), dim3(kFinalBlock), 0, s, off, (const int *)hi, w.counts,
                      slot, chunk_slot, CH, hub_start, chunk_hub);
   LAUNCH_TRY();
+  return PR_OK;
+}
+
+// Gather-side numbering (degree-based grouping) and the in-CSR sources
+// mapped into it. Returns the numbering to use (nullptr = identity) and the
+// source array the rank kernels gather through.
+struct Locality {
+  const int *pos;
+  const int *src;
+};
+int locality(Workspace &w, const pr_csr *g, const pr_tuning &tn, hipStream_t s, Locality *out) {
+  const bool on = tn.relabel > 0 || (tn.relabel < 0 && g->n >= (1 << 20));
+  if (!on) {
+    *out = Locality{nullptr, g->in_sources};
+    return PR_OK;
+  }
+  const int n = g->n, nt = (int)ntiles_for(n);
+  hipLaunchKernelGGL(k_group_count, dim3(nt), dim3(kBlock), 0, s, g->out_offsets, n,
+                     w.tile_counts, nt);
+  hipLaunchKernelGGL(k_scan_flat, dim3(1), dim3(kFinalBlock), 0, s, w.tile_counts, kGroups * nt);
+  hipLaunchKernelGGL(k_group_scatter, dim3(nt), dim3(kBlock), 0, s, g->out_offsets, n,
+                     (const int *)w.tile_counts, nt, w.newid);
+  const int mb = std::min((g->m + kBlock - 1) / kBlock, 8 * std::max(1, w.num_cus) * 4);
+  hipLaunchKernelGGL(k_map_sources, dim3(mb), dim3(kBlock), 0, s, g->in_sources, g->m,
+                     (const int *)w.newid, w.src_p);
+  LAUNCH_TRY();
+  *out = Locality{w.newid, w.src_p};
   return PR_OK;
 }
 
@@ -324,27 +361,31 @@ int run_static(const pr_csr *g, double alpha, double tol, int max_iter, const do
                  tn.hub_chunk_edges, w.hi_in, kInWave, kInChunks, w.hub_start_in, w.chunk_hub_in,
                  s);
   if (rc) return rc;
+  Locality loc;
+  if ((rc = locality(w, g, tn, s, &loc))) return rc;
   // R[0] is the caller's output vector; with `init` (which may alias it) the
   // start vector is copied into it.
   double *R[2] = {ranks_out, w.R1};
   double *X[2] = {w.X0, w.X1};
   hipLaunchKernelGGL(k_static_init, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n,
-                     g->out_offsets, init, R[0], X[0]);
+                     g->out_offsets, loc.pos, init, R[0], X[0]);
   LAUNCH_TRY();
   const double C0 = (1.0 - alpha) / (double)n;
   const int t1 = tn.lane_max_degree, CH = tn.hub_chunk_edges;
   auto launch = [&](int it, bool prof, hipEvent_t after) -> int {
     const int a = it & 1, b = a ^ 1;
-    hipLaunchKernelGGL(k_rank_static, dim3(B), dim3(kBlock), 0, s, g->in_offsets, g->in_sources,
-                       g->out_offsets, (const double *)X[a], (const double *)R[a], R[b], X[b],
+    hipLaunchKernelGGL(k_rank_static, dim3(B), dim3(kBlock), 0, s, g->in_offsets, loc.src,
+                       g->out_offsets, loc.pos, (const double *)X[a], (const double *)R[a], R[b],
+                       X[b],
                        (const int *)w.hi_in, (const int *)w.counts, (const int *)w.hub_start_in,
                        (const int *)w.chunk_hub_in, w.hub_part, CH, n, t1, C0, alpha, w.partials,
                        (const Ctrl *)w.ctrl);
     if (prof) HIP_TRY(hipEventRecord(after, s));
     hipLaunchKernelGGL(k_hub_finalize_static, dim3(kHubFinalizeBlocks), dim3(kBlock), 0, s,
                        (const int *)w.hi_in, (const int *)w.counts, (const int *)w.hub_start_in,
-                       (const double *)w.hub_part, g->out_offsets, (const double *)R[a], R[b],
-                       X[b], C0, alpha, w.partials + B, (const Ctrl *)w.ctrl);
+                       (const double *)w.hub_part, g->out_offsets, loc.pos,
+                       (const double *)R[a], R[b], X[b], C0, alpha, w.partials + B,
+                       (const Ctrl *)w.ctrl);
     hipLaunchKernelGGL(k_linf_final, dim3(1), dim3(kFinalBlock), 0, s,
                        (const double *)w.partials, np, w.ctrl, tol, it);
     LAUNCH_TRY();
@@ -381,8 +422,11 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
   double *R = ranks_out;
   const int t1 = tn.lane_max_degree, t_exp = tn.expand_lane_max_degree, CH = tn.hub_chunk_edges;
   hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, s, w.ctrl);
-  hipLaunchKernelGGL(k_dfp_init, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, prev, R,
-                     dV, dN, cv);
+  Locality loc;
+  if ((rc = locality(w, g, tn, s, &loc))) return rc;
+  double *X = w.X0;
+  hipLaunchKernelGGL(k_dfp_init, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n,
+                     g->out_offsets, loc.pos, prev, R, X, dV, dN, cv);
   LAUNCH_TRY();
   rc = partition(w, g->in_offsets, n, t1, tn.wave_max_degree, CH, w.hi_in, kInWave, kInChunks,
                  w.hub_start_in, w.chunk_hub_in, s);
@@ -399,7 +443,8 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
   }
   auto apply_expand = [&](int it) {
     hipLaunchKernelGGL(k_apply_expand, dim3(B), dim3(kBlock), 0, s, g->out_offsets,
-                       g->out_targets, R, (const double *)w.T, dV, (const uint8_t *)dN, cv,
+                       g->out_targets, loc.pos, R, X, (const double *)w.T, dV,
+                       (const uint8_t *)dN, cv,
                        (const int *)w.hi_out, (const int *)w.counts,
                        (const int *)w.hub_start_out, (const int *)w.chunk_hub_out, CH, n, t_exp,
                        (const Ctrl *)w.ctrl, it);
@@ -416,7 +461,8 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
   auto launch = [&](int it, bool prof, hipEvent_t after) -> int {
     if (prune) {
       hipLaunchKernelGGL(k_rank_dfp<true>, dim3(B), dim3(kBlock), 0, s, g->in_offsets,
-                         g->in_sources, g->out_offsets, (const double *)R, w.T, dV, dN, cv,
+                         loc.src, g->out_offsets, (const double *)X, (const double *)R, w.T, dV,
+                         dN, cv,
                          (const int *)w.hi_in, (const int *)w.counts,
                          (const int *)w.hub_start_in, (const int *)w.chunk_hub_in, w.hub_part, CH,
                          n, t1, C0, alpha, tau_f, tau_p, w.partials, (const Ctrl *)w.ctrl);
@@ -427,7 +473,8 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
                          dN, cv, C0, alpha, tau_f, tau_p, w.partials + B, (const Ctrl *)w.ctrl);
     } else {
       hipLaunchKernelGGL(k_rank_dfp<false>, dim3(B), dim3(kBlock), 0, s, g->in_offsets,
-                         g->in_sources, g->out_offsets, (const double *)R, w.T, dV, dN, cv,
+                         loc.src, g->out_offsets, (const double *)X, (const double *)R, w.T, dV,
+                         dN, cv,
                          (const int *)w.hi_in, (const int *)w.counts,
                          (const int *)w.hub_start_in, (const int *)w.chunk_hub_in, w.hub_part, CH,
                          n, t1, C0, alpha, tau_f, tau_p, w.partials, (const Ctrl *)w.ctrl);
@@ -556,7 +603,7 @@ int pr_set_tuning(const pr_tuning *t) {
   if (t->lane_max_degree < 0 || t->wave_max_degree < t->lane_max_degree ||
       t->expand_lane_max_degree < 0 || t->expand_lane_max_degree > t->wave_max_degree ||
       t->iters_per_sync < 1 || t->iters_per_sync >= kRing || t->hub_chunk_edges < 0 ||
-      t->grid_blocks < 0 || t->grid_blocks > (1 << 20))
+      t->grid_blocks < 0 || t->grid_blocks > (1 << 20) || t->relabel < -1 || t->relabel > 1)
     return fail(PR_EINVAL, "tuning field out of range");
   g_tuning = *t;
   if (g_tuning.hub_chunk_edges == 0) g_tuning.hub_chunk_edges = 4096;

@@ -248,6 +248,24 @@ def uniform(count: int, seed: int) -> np.ndarray:
     return out
 
 
+def relabel(g: Graph, perm) -> Graph:
+    """The same graph with vertex v renamed perm[v] (perm a permutation)."""
+    perm = np.ascontiguousarray(perm, dtype=np.int32)
+    s, d = g.edges()
+    out = from_edges(g.n, perm[s], perm[d])
+    return out
+
+
+def degree_order(g: Graph, by: str = "out") -> np.ndarray:
+    """perm[v] = position of v when vertices are sorted by descending degree
+    (ties by ID)."""
+    deg = g.out_degree() if by == "out" else g.in_degree()
+    order = np.argsort(-deg.astype(np.int64), kind="stable")
+    perm = np.empty(g.n, np.int32)
+    perm[order] = np.arange(g.n, dtype=np.int32)
+    return perm
+
+
 def graph_from_arrays(n, out_offsets, out_targets, in_offsets, in_sources) -> Graph:
     return Graph(int(n), int(out_offsets[-1]), np.ascontiguousarray(out_offsets, np.int32),
                  np.ascontiguousarray(out_targets, np.int32),

@@ -19,7 +19,7 @@ from paper_2404_08299_amd import prhip  # noqa: E402
 
 ALL_LANE = dict(lane_max_degree=1 << 30, wave_max_degree=1 << 30, expand_lane_max_degree=1 << 30)
 ALL_CLASSES = dict(lane_max_degree=2, wave_max_degree=12, expand_lane_max_degree=2,
-                   hub_chunk_edges=16)
+                   hub_chunk_edges=16, relabel=1)
 
 
 @pytest.fixture(autouse=True)
@@ -55,8 +55,9 @@ def test_static_rmat14_vs_oracle():
     assert abs(res.iterations - o.iters) <= 1
 
 
-def test_static_all_lane_bitwise():
-    prhip.set_tuning(**ALL_LANE)
+@pytest.mark.parametrize("relabel", [0, 1])
+def test_static_all_lane_bitwise(relabel):
+    prhip.set_tuning(**ALL_LANE, relabel=relabel)
     for g in (gg.rmat_graph(12, 8, seed=1), gg.rmat_graph(10, 16, seed=3, scramble=False)):
         r, res = gpu_static(g)
         o = ora_static(g)
@@ -69,7 +70,8 @@ def test_static_all_lane_bitwise():
                                     dict(lane_max_degree=8, wave_max_degree=200),
                                     dict(lane_max_degree=4, wave_max_degree=8, hub_chunk_edges=8,
                                          expand_lane_max_degree=4, grid_blocks=7),
-                                    dict(grid_blocks=1), dict(hub_chunk_edges=64, grid_blocks=3000)])
+                                    dict(grid_blocks=1), dict(hub_chunk_edges=64, grid_blocks=3000),
+                                    dict(relabel=1), dict(relabel=1, grid_blocks=5)])
 def test_static_every_class(tuning):
     prhip.set_tuning(**tuning)
     g = gg.rmat_graph(13, 8, seed=2)
@@ -191,8 +193,9 @@ def test_dfp_vs_oracle(frac):
     assert np.abs(r - ref).max() <= 10 * 1e-6 * ref.max()
 
 
-def test_dfp_all_lane_bitwise():
-    prhip.set_tuning(**ALL_LANE)
+@pytest.mark.parametrize("relabel", [0, 1])
+def test_dfp_all_lane_bitwise(relabel):
+    prhip.set_tuning(**ALL_LANE, relabel=relabel)
     g0, g1, b, prev = dynamic_case(scale=11, frac=1e-3, seed=4)
     r, res = gpu_dfp(g1, b, prev)
     o = oracle.dfp(g1.n, *g1.edges(), b, prev)
@@ -201,7 +204,9 @@ def test_dfp_all_lane_bitwise():
 
 
 @pytest.mark.parametrize("mode", ["df", "nd"])
-def test_df_nd_vs_oracle(mode):
+@pytest.mark.parametrize("relabel", [0, 1])
+def test_df_nd_vs_oracle(mode, relabel):
+    prhip.set_tuning(relabel=relabel)
     g0, g1, b, prev = dynamic_case(scale=12, frac=1e-3, seed=2)
     r, res = gpu_dfp(g1, b, prev, mode=mode)
     if mode == "df":
@@ -212,9 +217,9 @@ def test_df_nd_vs_oracle(mode):
     assert abs(res.iterations - o.iters) <= 1
 
 
-@pytest.mark.parametrize("tuning", [ALL_CLASSES, dict(grid_blocks=1),
+@pytest.mark.parametrize("tuning", [ALL_CLASSES, dict(grid_blocks=1), dict(relabel=1),
                                     dict(lane_max_degree=4, wave_max_degree=8, hub_chunk_edges=8,
-                                         expand_lane_max_degree=4, grid_blocks=5)])
+                                         expand_lane_max_degree=4, grid_blocks=5, relabel=1)])
 def test_dfp_every_class(tuning):
     prhip.set_tuning(**tuning)
     g0, g1, b, prev = dynamic_case(scale=13, frac=1e-3, seed=3)
