@@ -169,21 +169,19 @@ __global__ __launch_bounds__(kBlock) void k_part_count(const int *__restrict__ o
   }
 }
 
-// Exclusive scan of tile_counts[cls][0..ntiles) in place; counts[cls] = total.
-__global__ __launch_bounds__(kFinalBlock) void k_part_scan(int *__restrict__ tile_counts,
-                                                           int ntiles, int *__restrict__ counts) {
-  const int tid = threadIdx.x;
+// Exclusive scan of each class row rows[cls][0..ntiles) in place, one
+// workgroup per class (blockIdx.x); totals[cls] = the row's sum.
+__global__ __launch_bounds__(kFinalBlock) void k_scan_rows(int *__restrict__ rows, int ntiles,
+                                                           int *__restrict__ totals) {
+  int *tc = rows + (size_t)blockIdx.x * ntiles;
   const int per = (ntiles + kFinalBlock - 1) / kFinalBlock;
-  for (int cls = 0; cls < 2; ++cls) {
-    int *tc = tile_counts + (size_t)cls * ntiles;
-    const int beg = min(tid * per, ntiles), end = min(beg + per, ntiles);
-    int s = 0;
-    for (int i = beg; i < end; ++i) s += tc[i];
-    int total;
-    int run = block_exclusive_scan_1024(s, &total);
-    for (int i = beg; i < end; ++i) { const int t = tc[i]; tc[i] = run; run += t; }
-    if (tid == 0) counts[cls] = total;
-  }
+  const int beg = min((int)threadIdx.x * per, ntiles), end = min(beg + per, ntiles);
+  int s = 0;
+  for (int i = beg; i < end; ++i) s += tc[i];
+  int total;
+  int run = block_exclusive_scan_1024(s, &total);
+  for (int i = beg; i < end; ++i) { const int x = tc[i]; tc[i] = run; run += x; }
+  if (threadIdx.x == 0) totals[blockIdx.x] = total;
 }
 
 __global__ __launch_bounds__(kBlock) void k_part_scatter(const int *__restrict__ off, int n,
@@ -600,6 +598,13 @@ __global__ __launch_bounds__(kBlock) void k_mark_initial(const int *__restrict__
   }
 }
 
+// markNeighbors (Alg. 5) for one target: a store of 1, skipped when the flag
+// is already set (a read is cheaper than a partial-line write when most
+// targets are already affected). All writers store the same value.
+__device__ __forceinline__ void mark(uint8_t *dV, int v) {
+  if (!dV[v]) dV[v] = 1;
+}
+
 // After the convergence check of iteration `it`: copy the new ranks of the
 // vertices updated in it, with their contributions (the swap of Alg. 2;
 // vertices not updated keep their rank), then, unless it converged, expandAffected (Alg. 5): every u
@@ -649,7 +654,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_expand(
     if (f) { s_e0[off + p] = e0; s_e1[off + p] = e1; }
     __syncthreads();
     for (int k = 0; k < cnt; ++k)
-      for (int e = s_e0[k] + tid; e < s_e1[k]; e += kBlock) dV[out_tgt[e]] = 1;
+      for (int e = s_e0[k] + tid; e < s_e1[k]; e += kBlock) mark(dV, ld_nt(out_tgt + e));
     __syncthreads();
     }
     // wavefront class
@@ -669,7 +674,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_expand(
         mask &= mask - 1;
         const int uu = __shfl(u, j);
         const int a = out_off[uu], b = out_off[uu + 1];
-        for (int e = a + lane; e < b; e += kWave) dV[out_tgt[e]] = 1;
+        for (int e = a + lane; e < b; e += kWave) mark(dV, ld_nt(out_tgt + e));
       }
     }
   }
@@ -687,7 +692,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_expand(
       if (expand && dN[v]) {
         const int e0 = out_off[v], e1 = out_off[v + 1];
         if (e1 - e0 <= t_exp)
-          for (int e = e0; e < e1; ++e) dV[out_tgt[e]] = 1;
+          for (int e = e0; e < e1; ++e) mark(dV, ld_nt(out_tgt + e));
       }
     }
   }
@@ -720,24 +725,20 @@ __global__ __launch_bounds__(kBlock) void k_group_count(const int *__restrict__ 
   if (threadIdx.x < kGroups) counts[(size_t)threadIdx.x * ntiles + blockIdx.x] = c[threadIdx.x];
 }
 
-// In-place exclusive scan of a[0 .. len) by one 1024-thread workgroup.
-__global__ __launch_bounds__(kFinalBlock) void k_scan_flat(int *__restrict__ a, int len) {
-  const int per = (len + kFinalBlock - 1) / kFinalBlock;
-  const int beg = min((int)threadIdx.x * per, len), end = min(beg + per, len);
-  int s = 0;
-  for (int i = beg; i < end; ++i) s += a[i];
-  int total;
-  int run = block_exclusive_scan_1024(s, &total);
-  for (int i = beg; i < end; ++i) { const int x = a[i]; a[i] = run; run += x; }
-}
-
+// base[g][tile]: exclusive prefix of group g's counts over the tiles;
+// totals[g]: group sizes (the group's first position is their prefix sum).
 __global__ __launch_bounds__(kBlock) void k_group_scatter(const int *__restrict__ out_off, int n,
                                                           const int *__restrict__ base,
+                                                          const int *__restrict__ totals,
                                                           int ntiles, int *__restrict__ newid) {
   __shared__ int s_base[kGroups];
   __shared__ int s_cnt[kWavesPerBlock][kGroups];
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-  if (threadIdx.x < kGroups) s_base[threadIdx.x] = base[(size_t)threadIdx.x * ntiles + blockIdx.x];
+  if (threadIdx.x < kGroups) {
+    int gb = 0;
+    for (int g = 0; g < (int)threadIdx.x; ++g) gb += totals[g];
+    s_base[threadIdx.x] = gb + base[(size_t)threadIdx.x * ntiles + blockIdx.x];
+  }
   for (int k = 0; k < kPartTile / kBlock; ++k) {
     const int v = blockIdx.x * kPartTile + k * kBlock + threadIdx.x;
     const int key = v < n ? group_key(out_off[v + 1] - out_off[v]) : -1;

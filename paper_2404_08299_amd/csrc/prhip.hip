@@ -66,6 +66,7 @@ struct Workspace {
   int *src_p = nullptr;        // [m] in-CSR sources in that numbering
   int *tile_counts = nullptr;  // [kGroups][ntiles]
   int *counts = nullptr;       // [kNumCounts]
+  int *group_totals = nullptr; // [kGroups]
   double *partials = nullptr;  // [cap_partials]
   Ctrl *ctrl = nullptr;
   Ctrl *host_ctrl = nullptr;  // pinned ring
@@ -116,7 +117,7 @@ void free_arrays(Workspace &w) {
 
 void free_ws(Workspace &w) {
   free_arrays(w);
-  (void)hipFree(w.counts); (void)hipFree(w.ctrl);
+  (void)hipFree(w.counts); (void)hipFree(w.group_totals); (void)hipFree(w.ctrl);
   if (w.host_ctrl) (void)hipHostFree(w.host_ctrl);
   if (w.host_counts) (void)hipHostFree(w.host_counts);
   if (w.events_ready) {
@@ -151,6 +152,7 @@ int get_ws(size_t n, size_t m, int CH, int B, Workspace **out) {
     for (auto &e : w.call_ev) HIP_TRY(hipEventCreate(&e));
     HIP_TRY(hipMalloc(&w.ctrl, sizeof(Ctrl)));
     HIP_TRY(hipMalloc(&w.counts, kNumCounts * sizeof(int)));
+    HIP_TRY(hipMalloc(&w.group_totals, kGroups * sizeof(int)));
     HIP_TRY(hipHostMalloc(&w.host_ctrl, kRing * sizeof(Ctrl), hipHostMallocDefault));
     HIP_TRY(hipHostMalloc(&w.host_counts, kNumCounts * sizeof(int), hipHostMallocDefault));
     HIP_TRY(hipDeviceGetAttribute(&w.num_cus, hipDeviceAttributeMultiprocessorCount, dev));
@@ -233,7 +235,7 @@ int partition(Workspace &w, const int *off, int n, int t1, int t2, int CH, int *
   const int nt = (int)ntiles_for(n);
   hipLaunchKernelGGL(k_part_count, dim3(nt), dim3(kBlock), 0, s, off, n, t1, t2, w.tile_counts,
                      nt);
-  hipLaunchKernelGGL(k_part_scan, dim3(1), dim3(kFinalBlock), 0, s, w.tile_counts, nt,
+  hipLaunchKernelGGL(k_scan_rows, dim3(2), dim3(kFinalBlock), 0, s, w.tile_counts, nt,
                      w.counts + slot);
   hipLaunchKernelGGL(k_part_scatter, dim3(nt), dim3(kBlock), 0, s, off, n, t1, t2,
                      w.tile_counts, nt, (const int *)(w.counts + slot), hi);
@@ -259,9 +261,10 @@ int locality(Workspace &w, const pr_csr *g, const pr_tuning &tn, hipStream_t s, 
   const int n = g->n, nt = (int)ntiles_for(n);
   hipLaunchKernelGGL(k_group_count, dim3(nt), dim3(kBlock), 0, s, g->out_offsets, n,
                      w.tile_counts, nt);
-  hipLaunchKernelGGL(k_scan_flat, dim3(1), dim3(kFinalBlock), 0, s, w.tile_counts, kGroups * nt);
+  hipLaunchKernelGGL(k_scan_rows, dim3(kGroups), dim3(kFinalBlock), 0, s, w.tile_counts, nt,
+                     w.group_totals);
   hipLaunchKernelGGL(k_group_scatter, dim3(nt), dim3(kBlock), 0, s, g->out_offsets, n,
-                     (const int *)w.tile_counts, nt, w.newid);
+                     (const int *)w.tile_counts, (const int *)w.group_totals, nt, w.newid);
   const int mb = std::min((g->m + kBlock - 1) / kBlock, 8 * std::max(1, w.num_cus) * 4);
   hipLaunchKernelGGL(k_map_sources, dim3(mb), dim3(kBlock), 0, s, g->in_sources, g->m,
                      (const int *)w.newid, w.src_p);
