@@ -121,6 +121,20 @@ int pr_dfp_ex(const pr_csr *csr_old, const pr_csr *csr_new, const pr_edges *dele
               double frontier_tol, double prune_tol, int max_iter, int mode, double *ranks_out);
 
 /*
+ * Personalised PageRank with k teleport vectors (Eq. 1 with the uniform
+ * teleport (1-alpha)/|V| replaced by (1-alpha) * s_j[v]):
+ *   R_j[v] = alpha * sum_{u in in(v)} R_j[u] / |out(u)| + (1 - alpha) * s_j[v].
+ * All vectors start from 1/n and iterate together; vector j stops on its own
+ * when max_v |R_j,new[v] - R_j[v]| <= tol and keeps that iterate.
+ *   teleport   [n][k] device, vertex-major (s_j[v] at teleport[v*k + j])
+ *   ranks_out  [n][k] device, vertex-major, written
+ *   iters_out  [k] HOST array receiving each vector's iteration count, or NULL
+ * PR_NOT_CONVERGED if some vector reached max_iter.
+ */
+int pr_ppr(const pr_csr *csr, const double *teleport, int k, double alpha, double tol,
+           int max_iter, double *ranks_out, int32_t *iters_out);
+
+/*
  * Checks the input contract on the device: offsets start at 0, are
  * non-decreasing and end at m; every ID is in [0, n); rows are strictly
  * ascending (no duplicates); every vertex has its self-loop in both views;

@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "kernels.h"
+#include "ppr.h"
 #include "prhip.h"
 
 using namespace prhip;
@@ -68,6 +69,12 @@ struct Workspace {
   int *counts = nullptr;       // [kNumCounts]
   int *group_totals = nullptr; // [kGroups]
   double *partials = nullptr;  // [cap_partials]
+  // personalised PageRank: 4 [n][K] buffers (R, R', X, X'), chunk partials,
+  // per-workgroup per-vector maxima, per-vector state
+  double *ppr_buf = nullptr, *ppr_part = nullptr, *ppr_pmax = nullptr, *ppr_vdelta = nullptr;
+  int *ppr_vdone = nullptr, *ppr_viters = nullptr;
+  uint8_t *ppr_split = nullptr;
+  size_t cap_ppr_buf = 0, cap_ppr_part = 0, cap_ppr_pmax = 0, cap_ppr_k = 0, cap_ppr_n = 0;
   Ctrl *ctrl = nullptr;
   Ctrl *host_ctrl = nullptr;  // pinned ring
   int *host_counts = nullptr;  // pinned
@@ -115,8 +122,19 @@ void free_arrays(Workspace &w) {
   w.cap_n = w.cap_chunks = w.cap_partials = w.cap_m = 0;
 }
 
+void free_ppr(Workspace &w) {
+  (void)hipFree(w.ppr_buf); (void)hipFree(w.ppr_part); (void)hipFree(w.ppr_pmax);
+  (void)hipFree(w.ppr_vdelta); (void)hipFree(w.ppr_vdone); (void)hipFree(w.ppr_viters);
+  (void)hipFree(w.ppr_split);
+  w.ppr_buf = w.ppr_part = w.ppr_pmax = w.ppr_vdelta = nullptr;
+  w.ppr_vdone = w.ppr_viters = nullptr;
+  w.ppr_split = nullptr;
+  w.cap_ppr_buf = w.cap_ppr_part = w.cap_ppr_pmax = w.cap_ppr_k = w.cap_ppr_n = 0;
+}
+
 void free_ws(Workspace &w) {
   free_arrays(w);
+  free_ppr(w);
   (void)hipFree(w.counts); (void)hipFree(w.group_totals); (void)hipFree(w.ctrl);
   if (w.host_ctrl) (void)hipHostFree(w.host_ctrl);
   if (w.host_counts) (void)hipHostFree(w.host_counts);
@@ -506,6 +524,107 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
   return t_stats.converged ? PR_OK : PR_NOT_CONVERGED;
 }
 
+constexpr int kPprChunk = 256;  // in-edges per wavefront before a row is split
+
+int ppr_ws(Workspace &w, size_t n, size_t m, size_t K, size_t B) {
+  const size_t nbuf = 4 * n * K;
+  const size_t npart = (m / kPprChunk + n + 1) * K;
+  const size_t npmax = (B + kHubFinalizeBlocks + 16) * K;
+  if (nbuf > w.cap_ppr_buf || npart > w.cap_ppr_part || npmax > w.cap_ppr_pmax ||
+      K > w.cap_ppr_k || n > w.cap_ppr_n) {
+    const size_t a = std::max(nbuf, w.cap_ppr_buf), b = std::max(npart, w.cap_ppr_part);
+    const size_t c = std::max(npmax, w.cap_ppr_pmax), kk = std::max(K, w.cap_ppr_k);
+    const size_t nn = std::max(n, w.cap_ppr_n);
+    free_ppr(w);
+    hipError_t e = hipSuccess;
+    if ((e = hipMalloc(&w.ppr_buf, a * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&w.ppr_part, b * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&w.ppr_pmax, c * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&w.ppr_vdelta, kk * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&w.ppr_vdone, kk * sizeof(int))) != hipSuccess ||
+        (e = hipMalloc(&w.ppr_viters, kk * sizeof(int))) != hipSuccess ||
+        (e = hipMalloc(&w.ppr_split, nn)) != hipSuccess) {
+      (void)hipGetLastError();
+      free_ppr(w);
+      return fail(e == hipErrorOutOfMemory ? PR_ENOMEM : PR_EHIP,
+                  std::string("PPR workspace allocation: ") + hipGetErrorString(e));
+    }
+    w.cap_ppr_buf = a;
+    w.cap_ppr_part = b;
+    w.cap_ppr_pmax = c;
+    w.cap_ppr_k = kk;
+    w.cap_ppr_n = nn;
+  }
+  return PR_OK;
+}
+
+int run_ppr(const pr_csr *g, const double *teleport, int K, double alpha, double tol,
+            int max_iter, double *ranks_out, int32_t *iters_out) {
+  hipStream_t s = t_stream;
+  const int n = g->n;
+  const pr_tuning tn = g_tuning;
+  Workspace *wp = nullptr;
+  int rc = get_ws((size_t)n, (size_t)g->m, kPprChunk, tn.grid_blocks, &wp);
+  if (rc) return rc;
+  Workspace &w = *wp;
+  const int B = grid_blocks(w, tn, k_ppr_rank);
+  const int F = kHubFinalizeBlocks;
+  if ((rc = ppr_ws(w, (size_t)n, (size_t)g->m, (size_t)K, (size_t)B))) return rc;
+  CallTimer timer(w, s);
+  const size_t nk = (size_t)n * K;
+  double *Rb[2] = {w.ppr_buf, w.ppr_buf + nk};
+  double *Xb[2] = {w.ppr_buf + 2 * nk, w.ppr_buf + 3 * nk};
+  hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, s, w.ctrl);
+  // rows longer than kPprChunk form the split class (class 1 of Alg. 4 empty)
+  rc = partition(w, g->in_offsets, n, kPprChunk, kPprChunk, kPprChunk, w.hi_in, kInWave,
+                 kInChunks, w.hub_start_in, w.chunk_hub_in, s);
+  if (rc) return rc;
+  Locality loc;
+  if ((rc = locality(w, g, tn, s, &loc))) return rc;
+  const int ib = (int)std::min<size_t>((nk + kBlock - 1) / kBlock, (size_t)B * 4);
+  hipLaunchKernelGGL(k_ppr_init, dim3(ib), dim3(kBlock), 0, s, n, K, g->out_offsets, loc.pos,
+                     Rb[0], Xb[0], w.ppr_vdone, w.ppr_viters);
+  hipLaunchKernelGGL(k_split_flags, dim3(std::min(B, (n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                     s, g->in_offsets, n, kPprChunk, w.ppr_split);
+  LAUNCH_TRY();
+  const size_t shm = (size_t)kWavesPerBlock * K * sizeof(double);
+  auto launch = [&](int it, bool prof, hipEvent_t after) -> int {
+    const int a = it & 1, b = a ^ 1;
+    hipLaunchKernelGGL(k_ppr_rank, dim3(B), dim3(kBlock), shm, s, g->in_offsets, loc.src,
+                       g->out_offsets, loc.pos, (const int *)w.hi_in, (const int *)w.counts,
+                       (const int *)w.hub_start_in, (const int *)w.chunk_hub_in,
+                       (const uint8_t *)w.ppr_split, kPprChunk, n, K, (const double *)Xb[a],
+                       (const double *)Rb[a], Rb[b], Xb[b], teleport, w.ppr_part,
+                       (const int *)w.ppr_vdone, alpha, w.ppr_pmax, (const Ctrl *)w.ctrl);
+    if (prof) HIP_TRY(hipEventRecord(after, s));
+    hipLaunchKernelGGL(k_ppr_finalize, dim3(F), dim3(kBlock), shm, s, g->out_offsets, loc.pos,
+                       (const int *)w.hi_in, (const int *)w.counts, (const int *)w.hub_start_in,
+                       K, (const double *)w.ppr_part, (const double *)Rb[a], Rb[b], Xb[b],
+                       teleport, (const int *)w.ppr_vdone, alpha, w.ppr_pmax + (size_t)B * K,
+                       (const Ctrl *)w.ctrl);
+    hipLaunchKernelGGL(k_ppr_linf, dim3(1), dim3(kBlock), 0, s, (const double *)w.ppr_pmax,
+                       B + F, K, w.ppr_vdone, w.ppr_viters, w.ppr_vdelta, w.ctrl, tol, it,
+                       max_iter);
+    LAUNCH_TRY();
+    return PR_OK;
+  };
+  int iters = 0, launched = 0;
+  rc = iterate(w, s, max_iter, launch, &iters, &launched);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_ppr_gather_out, dim3(ib), dim3(kBlock), 0, s, n, K,
+                     (const double *)Rb[0], (const double *)Rb[1], (const int *)w.ppr_viters,
+                     ranks_out);
+  LAUNCH_TRY();
+  if (iters_out)
+    HIP_TRY(hipMemcpyAsync(iters_out, w.ppr_viters, (size_t)K * sizeof(int),
+                           hipMemcpyDeviceToHost, s));
+  timer.stop();
+  HIP_TRY(hipStreamSynchronize(s));
+  t_stats.total_ms = timer.ms();
+  collect_profile(w, iters);
+  return t_stats.converged ? PR_OK : PR_NOT_CONVERGED;
+}
+
 int check_edges(const pr_edges *e, const char *name) {
   if (!e) return PR_OK;
   if (e->count < 0) return fail(PR_EINVAL, std::string(name) + ".count < 0");
@@ -555,6 +674,20 @@ int pr_dfp(const pr_csr *csr_old, const pr_csr *csr_new, const pr_edges *deletio
            double frontier_tol, double prune_tol, double *ranks_out) {
   return pr_dfp_ex(csr_old, csr_new, deletions, insertions, ranks_prev, alpha, tol, frontier_tol,
                    prune_tol, PR_MAX_ITERATIONS, PR_MODE_DFP, ranks_out);
+}
+
+int pr_ppr(const pr_csr *csr, const double *teleport, int k, double alpha, double tol,
+           int max_iter, double *ranks_out, int32_t *iters_out) {
+  reset_stats();
+  int rc = check_csr(csr, false);
+  if (rc) return rc;
+  if ((rc = check_params(alpha, tol, max_iter))) return rc;
+  if (k <= 0) return fail(PR_EINVAL, "k must be > 0");
+  if (!teleport || !ranks_out) return fail(PR_EINVAL, "teleport and ranks_out are required");
+  if ((size_t)csr->n * (size_t)k > ((size_t)1 << 40))
+    return fail(PR_EINVAL, "n * k too large");
+  std::lock_guard<std::mutex> lock(g_mu);
+  return run_ppr(csr, teleport, k, alpha, tol, max_iter, ranks_out, iters_out);
 }
 
 int pr_validate_csr(const pr_csr *g) {
