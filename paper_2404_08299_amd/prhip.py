@@ -58,7 +58,7 @@ class PrStats(ctypes.Structure):
                 ("reserved", ctypes.c_double * 4)]
 
 
-EXPORTED = ["pr_static", "pr_dfp", "pr_dfp_ex", "pr_validate_csr", "pr_set_tuning",
+EXPORTED = ["pr_static", "pr_dfp", "pr_dfp_ex", "pr_ppr", "pr_validate_csr", "pr_set_tuning",
             "pr_get_tuning", "pr_last_stats", "pr_set_profiling", "pr_set_stream",
             "pr_last_error", "pr_release"]
 
@@ -81,6 +81,7 @@ def load_library(path: str = SO_PATH):
     lib.pr_dfp.argtypes = [P(PrCsr), P(PrCsr), P(PrEdges), P(PrEdges), vp, d, d, d, d, vp]
     lib.pr_dfp_ex.argtypes = [P(PrCsr), P(PrCsr), P(PrEdges), P(PrEdges), vp, d, d, d, d, i, i,
                               vp]
+    lib.pr_ppr.argtypes = [P(PrCsr), vp, i, d, d, i, vp, P(ctypes.c_int32)]
     lib.pr_validate_csr.argtypes = [P(PrCsr)]
     lib.pr_set_tuning.argtypes = [P(PrTuning)]
     lib.pr_get_tuning.argtypes = [P(PrTuning)]
@@ -92,7 +93,7 @@ def load_library(path: str = SO_PATH):
     lib.pr_last_error.restype = ctypes.c_char_p
     lib.pr_release.argtypes = []
     lib.pr_release.restype = None
-    for f in ("pr_static", "pr_dfp", "pr_dfp_ex", "pr_validate_csr", "pr_set_tuning",
+    for f in ("pr_static", "pr_dfp", "pr_dfp_ex", "pr_ppr", "pr_validate_csr", "pr_set_tuning",
               "pr_get_tuning", "pr_last_stats", "pr_set_profiling"):
         getattr(lib, f).restype = ctypes.c_int
     if path == SO_PATH:
@@ -230,6 +231,29 @@ def dfp(g_new: DeviceGraph, batch: DeviceBatch, ranks_prev, alpha=ALPHA, tol=TOL
                            frontier_tol, prune_tol, max_iter, MODES[mode], out.data_ptr())
     _check(rc, lib)
     return _result(rc, out)
+
+
+def ppr(g: DeviceGraph, teleport, alpha=ALPHA, tol=TOL, max_iter=MAX_ITERATIONS, out=None):
+    """Personalised PageRank through pr_ppr. teleport: [n][k] float64 device
+    tensor (vertex-major). Returns (Result with ranks [n][k], iterations per
+    vector as a numpy array)."""
+    torch = _torch()
+    lib = load_library()
+    assert teleport.dtype == torch.float64 and teleport.is_contiguous()
+    if teleport.dim() == 1:
+        teleport = teleport.view(-1, 1)
+    n, k = teleport.shape
+    assert n == g.n
+    if out is None:
+        out = torch.empty((n, k), dtype=torch.float64, device=teleport.device)
+    assert out.dtype == torch.float64 and out.is_contiguous() and out.shape == (n, k)
+    its = np.zeros(k, np.int32)
+    _bind_stream(lib, torch)
+    csr = g.csr()
+    rc = _check(lib.pr_ppr(ctypes.byref(csr), teleport.data_ptr(), k, alpha, tol, max_iter,
+                           out.data_ptr(), its.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))),
+                lib)
+    return _result(rc, out), its
 
 
 def validate(g: DeviceGraph) -> None:

@@ -100,3 +100,13 @@ def test_binding_has_no_cpu_fallback():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "liboracle" not in text, f
+
+
+def test_ppr_argument_errors(lib):
+    csr = prhip.PrCsr(4, 4, 8, 8, 8, None)
+    assert lib.pr_ppr(ctypes.byref(csr), ctypes.c_void_p(8), 0, 0.85, 1e-10, 10,
+                      ctypes.c_void_p(8), None) == prhip.PR_EINVAL
+    assert lib.pr_ppr(ctypes.byref(csr), None, 4, 0.85, 1e-10, 10, ctypes.c_void_p(8),
+                      None) == prhip.PR_EINVAL
+    assert lib.pr_ppr(ctypes.byref(csr), ctypes.c_void_p(8), 4, 1.5, 1e-10, 10,
+                      ctypes.c_void_p(8), None) == prhip.PR_EINVAL
