@@ -135,6 +135,39 @@ int pr_ppr(const pr_csr *csr, const double *teleport, int k, double alpha, doubl
            int max_iter, double *ranks_out, int32_t *iters_out);
 
 /*
+ * Weighted forward (PageRank with given transition weights and teleport):
+ *   r_v = alpha * sum_{u in in(v)} P_uv * r_u + (1 - alpha) * s_v,
+ * from r = 1/n, L-infinity stop as in pr_static. The weights are used as
+ * given (no normalisation); with P_uv = 1/|out(u)| and s = 1/n this is Eq. 1.
+ *   in_weights  [m] device, P_uv aligned with in_sources (in-CSR order)
+ *   teleport    [n] device, s; NULL means s_v = 1/n with the term (1-alpha)/n
+ *   ranks_out   [n] device, written
+ */
+int pr_weighted(const pr_csr *csr, const double *in_weights, const double *teleport,
+                double alpha, double tol, int max_iter, double *ranks_out);
+
+/*
+ * Adjoint of pr_weighted. For a loss L(r) with g = dL/dr at the forward
+ * solution r, the adjoint lambda solves lambda = g + alpha * A^T lambda
+ * (A[v][u] = P_uv), i.e. lambda_u = g_u + alpha * sum_{v in out(u)} P_uv *
+ * lambda_v, iterated from 0 with the same L-infinity stop (a pull over the
+ * out-CSR; the weights are transposed into out-CSR order on the device).
+ * Then
+ *   grad_weights[e] = alpha * r_u * lambda_v   for in-edge e = (u -> v),
+ *   grad_teleport[v] = (1 - alpha) * lambda_v.
+ *   csr            both views (out_targets required; rows ascending)
+ *   in_weights     [m] device, P_uv in in-CSR order (as for pr_weighted)
+ *   ranks          [n] device, the forward solution r
+ *   grad_ranks     [n] device, g
+ *   grad_weights   [m] device, in-CSR order, or NULL
+ *   grad_teleport  [n] device, or NULL
+ *   lambda_out     [n] device, or NULL
+ */
+int pr_adjoint(const pr_csr *csr, const double *in_weights, const double *ranks,
+               const double *grad_ranks, double alpha, double tol, int max_iter,
+               double *grad_weights, double *grad_teleport, double *lambda_out);
+
+/*
  * Checks the input contract on the device: offsets start at 0, are
  * non-decreasing and end at m; every ID is in [0, n); rows are strictly
  * ascending (no duplicates); every vertex has its self-loop in both views;

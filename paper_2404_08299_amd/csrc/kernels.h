@@ -252,75 +252,100 @@ __global__ __launch_bounds__(kFinalBlock) void k_hub_plan(const int *__restrict_
 }
 
 // ------------------------------------------------------------ Static init
-// R = 1/n, X = R / |out(v)| (Alg. 1 initialisation). With `init` the start
-// vector is given (Naive-dynamic, Sec. 3.4.1); it may alias R.
+// R = r0 (1/n in Alg. 1), X = R / |out(v)| (or R when weighted). With
+// `init` the start vector is given (Naive-dynamic, Sec. 3.4.1); it may alias R.
 __global__ __launch_bounds__(kBlock) void k_static_init(int n, const int *__restrict__ out_off,
                                                         const int *__restrict__ pos,
-                                                        const double *init, double *R,
+                                                        const double *init, double r0,
+                                                        int weighted, double *R,
                                                         double *__restrict__ X) {
   const int v = blockIdx.x * kBlock + threadIdx.x;
   if (v < n) {
-    const double r = init ? init[v] : 1.0 / (double)n;
+    const double r = init ? init[v] : r0;
     R[v] = r;
-    X[xpos(pos, v)] = r / (double)(out_off[v + 1] - out_off[v]);
+    X[xpos(pos, v)] = weighted ? r : r / (double)(out_off[v + 1] - out_off[v]);
   }
 }
 
 // ------------------------------------------------------------ row sums
-// Sequential in-row sum of X over sources, ascending (four loads in flight,
-// additions in row order, so the result equals a plain sequential sum).
+// Sequential in-row sum of the contributions, ascending (four gathers in
+// flight, additions in row order, so the result equals a plain sequential
+// sum). Unweighted: X[src[e]]; weighted: wt[e] * X[src[e]].
+template <bool WEIGHTED>
 __device__ __forceinline__ double row_sum_seq(const int *__restrict__ src,
+                                              const double *__restrict__ wt,
                                               const double *__restrict__ X, int e0, int e1) {
   double c = 0.0;
   int e = e0;
   for (; e + 4 <= e1; e += 4) {
     const int u0 = ld_nt(src + e), u1 = ld_nt(src + e + 1), u2 = ld_nt(src + e + 2),
               u3 = ld_nt(src + e + 3);
-    const double x0 = X[u0], x1 = X[u1], x2 = X[u2], x3 = X[u3];
+    double x0 = X[u0], x1 = X[u1], x2 = X[u2], x3 = X[u3];
+    if (WEIGHTED) {
+      x0 = ld_nt(wt + e) * x0;
+      x1 = ld_nt(wt + e + 1) * x1;
+      x2 = ld_nt(wt + e + 2) * x2;
+      x3 = ld_nt(wt + e + 3) * x3;
+    }
     c = c + x0;
     c = c + x1;
     c = c + x2;
     c = c + x3;
   }
-  for (; e < e1; ++e) c = c + X[ld_nt(src + e)];
+  for (; e < e1; ++e) {
+    const double x = X[ld_nt(src + e)];
+    c = c + (WEIGHTED ? ld_nt(wt + e) * x : x);
+  }
   return c;
 }
 
-// Contribution of in-edge e: X[src[e]].
+// Contribution of in-edge e.
+template <bool WEIGHTED>
 __device__ __forceinline__ double contrib(int e, const int *__restrict__ src,
+                                          const double *__restrict__ wt,
                                           const double *__restrict__ X) {
-  return X[ld_nt(src + e)];
+  const double x = X[ld_nt(src + e)];
+  return WEIGHTED ? ld_nt(wt + e) * x : x;
 }
 
 // Strided partial sum over [e0, e1) with stride S starting at e0 + t, four
 // independent accumulators combined in a fixed order.
-template <int S>
+template <int S, bool WEIGHTED>
 __device__ __forceinline__ double strided_sum(int e0, int e1, int t, const int *__restrict__ src,
+                                              const double *__restrict__ wt,
                                               const double *__restrict__ X) {
   double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
   int e = e0 + t;
   for (; e + 3 * S < e1; e += 4 * S) {
-    c0 += contrib(e, src, X);
-    c1 += contrib(e + S, src, X);
-    c2 += contrib(e + 2 * S, src, X);
-    c3 += contrib(e + 3 * S, src, X);
+    c0 += contrib<WEIGHTED>(e, src, wt, X);
+    c1 += contrib<WEIGHTED>(e + S, src, wt, X);
+    c2 += contrib<WEIGHTED>(e + 2 * S, src, wt, X);
+    c3 += contrib<WEIGHTED>(e + 3 * S, src, wt, X);
   }
-  for (; e < e1; e += S) c0 += contrib(e, src, X);
+  for (; e < e1; e += S) c0 += contrib<WEIGHTED>(e, src, wt, X);
   return (c0 + c1) + (c2 + c3);
 }
 
 // ------------------------------------------------------------ finishing
+// Finishing of a full pull for one vertex:
+//   r = C0 + alpha * c                    (Eq. 1, uniform teleport), or
+//   r = tscale * tele[v] + alpha * c      (given teleport term),
+// then R_new[v] = r, the gather-side value X[pos(v)] = r / |out(v)|
+// (unweighted) or r (weighted), and |r - R[v]| is returned.
 struct StaticOut {
   const int *out_off;
   const int *pos;
   const double *R;
   double *Rn, *Xn;
   double C0, alpha;
-  // Eq. 1 for one vertex: R_new, its contribution, and |R_new - R|.
+  const double *tele;
+  double tscale;
+  bool weighted;
   __device__ __forceinline__ double finish(int v, double c) const {
-    const double r = C0 + alpha * c;
+    const double r = tele ? tscale * ld_nt(tele + v) + alpha * c : C0 + alpha * c;
     st_nt(Rn + v, r);
-    Xn[xpos(pos, v)] = r / (double)(ld_nt(out_off + v + 1) - ld_nt(out_off + v));
+    Xn[xpos(pos, v)] =
+        weighted ? r : r / (double)(ld_nt(out_off + v + 1) - ld_nt(out_off + v));
     return fabs(r - ld_nt(R + v));
   }
 };
@@ -356,10 +381,10 @@ struct DynOut {
 // only vertices with dV set are updated, and every vertex processed here
 // rewrites its dN flag (cleared when unaffected), which is the clearing of
 // delta_N at the start of the iteration in Alg. 2.
-template <bool DYN, class Out>
+template <bool DYN, bool WEIGHTED, class Out>
 __device__ __forceinline__ void rank_update(
     const int *__restrict__ in_off, const int *__restrict__ in_src,
-    const double *__restrict__ X, const uint8_t *dV,
+    const double *__restrict__ wt, const double *__restrict__ X, const uint8_t *dV,
     uint8_t *dN, const int *__restrict__ hi, const int *__restrict__ counts,
     const int *__restrict__ hub_start, const int *__restrict__ chunk_hub,
     double *__restrict__ hub_part, int CH, int n, int t1, const Out &out,
@@ -388,9 +413,9 @@ __device__ __forceinline__ void rank_update(
       e0 = r0 + (c - hub_start[i]) * CH;
       e1 = min(e0 + CH, r1);
     }
-    int wt;
-    const int p = wave_prefix_count(f, &wt);
-    if (lane == 0) s_wcnt[wid] = wt;
+    int wtot;
+    const int p = wave_prefix_count(f, &wtot);
+    if (lane == 0) s_wcnt[wid] = wtot;
     __syncthreads();
     int off = 0, cnt = 0;
 #pragma unroll
@@ -401,7 +426,7 @@ __device__ __forceinline__ void rank_update(
     if (f) { s_c[off + p] = c; s_v[off + p] = v; s_e0[off + p] = e0; s_e1[off + p] = e1; }
     __syncthreads();
     for (int k = 0; k < cnt; ++k) {
-      double s = strided_sum<kBlock>(s_e0[k], s_e1[k], tid, in_src, X);
+      double s = strided_sum<kBlock, WEIGHTED>(s_e0[k], s_e1[k], tid, in_src, wt, X);
       s = block_sum<kBlock>(s, lds);
       if (tid == 0) hub_part[s_c[k]] = s;
     }
@@ -427,7 +452,7 @@ __device__ __forceinline__ void rank_update(
         mask &= mask - 1;
         const int vv = __shfl(v, j);
         const int e0 = in_off[vv], e1 = in_off[vv + 1];
-        double c = strided_sum<kWave>(e0, e1, lane, in_src, X);
+        double c = strided_sum<kWave, WEIGHTED>(e0, e1, lane, in_src, wt, X);
         c = wave_sum(c);
         if (lane == 0) dmax = fmax(dmax, out.finish(vv, c));
       }
@@ -443,7 +468,7 @@ __device__ __forceinline__ void rank_update(
         const int e0 = ld_nt(in_off + v), e1 = ld_nt(in_off + v + 1);
         if (e1 - e0 <= t1) {
           if (!DYN || dV[v]) {
-            const double c = row_sum_seq(in_src, X, e0, e1);
+            const double c = row_sum_seq<WEIGHTED>(in_src, wt, X, e0, e1);
             dmax = fmax(dmax, out.finish(v, c));
           } else {
             dN[v] = 0;
@@ -456,20 +481,24 @@ __device__ __forceinline__ void rank_update(
   if (tid == 0) partials[blockIdx.x] = dmax;
 }
 
-// in_src: the sources of the in-CSR in the gather-side numbering (pos);
-// X, Xn: contributions in that numbering; R, Rn: ranks in vertex order.
+// One full pull (Static, Naive-dynamic, the weighted forward and the
+// adjoint iteration). in_src: the row indices in the gather-side numbering
+// (pos); wt: per-edge weights aligned with them (WEIGHTED); X, Xn: gathered
+// values in that numbering; R, Rn: the iterate in vertex order.
+template <bool WEIGHTED>
 __global__ __launch_bounds__(kBlock) void k_rank_static(
     const int *__restrict__ in_off, const int *__restrict__ in_src,
-    const int *__restrict__ out_off, const int *__restrict__ pos, const double *__restrict__ X,
-    const double *__restrict__ R, double *__restrict__ Rn, double *__restrict__ Xn,
-    const int *__restrict__ hi, const int *__restrict__ counts,
-    const int *__restrict__ hub_start, const int *__restrict__ chunk_hub,
-    double *__restrict__ hub_part, int CH, int n, int t1, double C0, double alpha,
+    const double *__restrict__ wt, const int *__restrict__ out_off,
+    const int *__restrict__ pos, const double *__restrict__ X, const double *__restrict__ R,
+    double *__restrict__ Rn, double *__restrict__ Xn, const int *__restrict__ hi,
+    const int *__restrict__ counts, const int *__restrict__ hub_start,
+    const int *__restrict__ chunk_hub, double *__restrict__ hub_part, int CH, int n, int t1,
+    double C0, double alpha, const double *__restrict__ tele, double tscale,
     double *__restrict__ partials, const Ctrl *__restrict__ ctrl) {
   if (ctrl->done) return;
-  const StaticOut out{out_off, pos, R, Rn, Xn, C0, alpha};
-  rank_update<false>(in_off, in_src, X, nullptr, nullptr, hi, counts, hub_start, chunk_hub,
-                     hub_part, CH, n, t1, out, partials);
+  const StaticOut out{out_off, pos, R, Rn, Xn, C0, alpha, tele, tscale, WEIGHTED};
+  rank_update<false, WEIGHTED>(in_off, in_src, wt, X, nullptr, nullptr, hi, counts, hub_start,
+                               chunk_hub, hub_part, CH, n, t1, out, partials);
 }
 
 template <bool PRUNE>
@@ -483,8 +512,8 @@ __global__ __launch_bounds__(kBlock) void k_rank_dfp(
     const Ctrl *__restrict__ ctrl) {
   if (ctrl->done) return;
   const DynOut<PRUNE> out{out_off, R, T, dV, dN, cv, C0, alpha, tau_f, tau_p};
-  rank_update<true>(in_off, in_src, X, dV, dN, hi, counts, hub_start, chunk_hub, hub_part, CH, n,
-                    t1, out, partials);
+  rank_update<true, false>(in_off, in_src, nullptr, X, dV, dN, hi, counts, hub_start, chunk_hub,
+                           hub_part, CH, n, t1, out, partials);
 }
 
 // Split-class vertices: add the chunk partials in chunk order and finish.
@@ -516,10 +545,10 @@ __global__ __launch_bounds__(kBlock) void k_hub_finalize_static(
     const int *__restrict__ hi, const int *__restrict__ counts, const int *__restrict__ hub_start,
     const double *__restrict__ hub_part, const int *__restrict__ out_off,
     const int *__restrict__ pos, const double *__restrict__ R, double *__restrict__ Rn,
-    double *__restrict__ Xn, double C0, double alpha, double *__restrict__ partials,
-    const Ctrl *__restrict__ ctrl) {
+    double *__restrict__ Xn, double C0, double alpha, const double *__restrict__ tele,
+    double tscale, int weighted, double *__restrict__ partials, const Ctrl *__restrict__ ctrl) {
   if (ctrl->done) return;
-  const StaticOut out{out_off, pos, R, Rn, Xn, C0, alpha};
+  const StaticOut out{out_off, pos, R, Rn, Xn, C0, alpha, tele, tscale, weighted != 0};
   hub_finalize<false>(hi, counts, hub_start, hub_part, nullptr, nullptr, out, partials);
 }
 
@@ -641,9 +670,9 @@ __global__ __launch_bounds__(kBlock) void k_apply_expand(
       e0 = out_off[u] + (c - hub_start[i]) * CH;
       e1 = min(e0 + CH, out_off[u + 1]);
     }
-    int wt;
-    const int p = wave_prefix_count(f, &wt);
-    if (lane == 0) s_wcnt[wid] = wt;
+    int wtot;
+    const int p = wave_prefix_count(f, &wtot);
+    if (lane == 0) s_wcnt[wid] = wtot;
     __syncthreads();
     int off = 0, cnt = 0;
 #pragma unroll
@@ -696,6 +725,61 @@ __global__ __launch_bounds__(kBlock) void k_apply_expand(
       }
     }
   }
+}
+
+// ------------------------------------------------------------ adjoint
+// Row of edge e in a CSR (offsets[row] <= e < offsets[row + 1]).
+__device__ __forceinline__ int row_of_edge(const int *__restrict__ off, int n, int e) {
+  int lo = 0, hi = n;  // invariant: off[lo] <= e < off[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= e) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Weights in out-CSR order: for in-edge e = (u -> v), P_out at the position
+// of v in u's (ascending) out-row gets in_w[e]. Entries of an out-row whose
+// in-edge is missing (views inconsistent) keep 0.
+__global__ __launch_bounds__(kBlock) void k_transpose_weights(
+    const int *__restrict__ in_off, const int *__restrict__ in_src, const double *__restrict__ in_w,
+    const int *__restrict__ out_off, const int *__restrict__ out_tgt, int n, int m,
+    double *__restrict__ out_w) {
+  for (int e = blockIdx.x * kBlock + threadIdx.x; e < m; e += gridDim.x * kBlock) {
+    const int v = row_of_edge(in_off, n, e);
+    const int u = in_src[e];
+    int lo = out_off[u], hi = out_off[u + 1];
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (out_tgt[mid] < v) lo = mid + 1;
+      else hi = mid;
+    }
+    if (lo < out_off[u + 1] && out_tgt[lo] == v) out_w[lo] = in_w[e];
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill(double *__restrict__ a, size_t len, double x) {
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < len;
+       i += (size_t)gridDim.x * kBlock)
+    a[i] = x;
+}
+
+// Gradients from the adjoint solution lambda: d/dP_uv = alpha * r_u * lambda_v
+// for every in-edge (in-CSR order), d/ds_v = (1 - alpha) * lambda_v.
+__global__ __launch_bounds__(kBlock) void k_adjoint_grads(
+    const int *__restrict__ in_off, const int *__restrict__ in_src, int n, int m,
+    const double *__restrict__ r, const double *__restrict__ lam, double alpha,
+    double *__restrict__ grad_w, double *__restrict__ grad_s) {
+  const int stride = gridDim.x * kBlock;
+  if (grad_w)
+    for (int e = blockIdx.x * kBlock + threadIdx.x; e < m; e += stride) {
+      const int v = row_of_edge(in_off, n, e);
+      grad_w[e] = alpha * r[in_src[e]] * lam[v];
+    }
+  if (grad_s)
+    for (int v = blockIdx.x * kBlock + threadIdx.x; v < n; v += stride)
+      grad_s[v] = (1.0 - alpha) * lam[v];
 }
 
 // ------------------------------------------------------------ locality

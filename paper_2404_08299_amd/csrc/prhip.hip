@@ -63,6 +63,8 @@ struct Workspace {
   int *hub_start_in = nullptr, *hub_start_out = nullptr;  // [n + 1]
   int *chunk_hub_in = nullptr, *chunk_hub_out = nullptr;  // [cap_chunks]
   double *hub_part = nullptr;                             // [cap_chunks]
+  double *w_out = nullptr;     // [m] edge weights in out-CSR order (adjoint)
+  size_t cap_w_out = 0;
   int *newid = nullptr;        // [n] gather-side numbering
   int *src_p = nullptr;        // [m] in-CSR sources in that numbering
   int *tile_counts = nullptr;  // [kGroups][ntiles]
@@ -135,6 +137,9 @@ void free_ppr(Workspace &w) {
 void free_ws(Workspace &w) {
   free_arrays(w);
   free_ppr(w);
+  (void)hipFree(w.w_out);
+  w.w_out = nullptr;
+  w.cap_w_out = 0;
   (void)hipFree(w.counts); (void)hipFree(w.group_totals); (void)hipFree(w.ctrl);
   if (w.host_ctrl) (void)hipHostFree(w.host_ctrl);
   if (w.host_counts) (void)hipHostFree(w.host_counts);
@@ -263,29 +268,31 @@ int partition(Workspace &w, const int *off, int n, int t1, int t2, int CH, int *
   return PR_OK;
 }
 
-// Gather-side numbering (degree-based grouping) and the in-CSR sources
-// mapped into it. Returns the numbering to use (nullptr = identity) and the
-// source array the rank kernels gather through.
+// Gather-side numbering (degree-based grouping by the degrees of
+// `group_off`) and the row indices `idx` mapped into it. Returns the
+// numbering to use (nullptr = identity) and the index array the pull kernels
+// gather through.
 struct Locality {
   const int *pos;
   const int *src;
 };
-int locality(Workspace &w, const pr_csr *g, const pr_tuning &tn, hipStream_t s, Locality *out) {
-  const bool on = tn.relabel > 0 || (tn.relabel < 0 && g->n >= (1 << 20));
+int locality(Workspace &w, int n, int m, const int *group_off, const int *idx,
+             const pr_tuning &tn, bool allowed, hipStream_t s, Locality *out) {
+  const bool on = allowed && (tn.relabel > 0 || (tn.relabel < 0 && n >= (1 << 20)));
   if (!on) {
-    *out = Locality{nullptr, g->in_sources};
+    *out = Locality{nullptr, idx};
     return PR_OK;
   }
-  const int n = g->n, nt = (int)ntiles_for(n);
-  hipLaunchKernelGGL(k_group_count, dim3(nt), dim3(kBlock), 0, s, g->out_offsets, n,
-                     w.tile_counts, nt);
+  const int nt = (int)ntiles_for(n);
+  hipLaunchKernelGGL(k_group_count, dim3(nt), dim3(kBlock), 0, s, group_off, n, w.tile_counts,
+                     nt);
   hipLaunchKernelGGL(k_scan_rows, dim3(kGroups), dim3(kFinalBlock), 0, s, w.tile_counts, nt,
                      w.group_totals);
-  hipLaunchKernelGGL(k_group_scatter, dim3(nt), dim3(kBlock), 0, s, g->out_offsets, n,
+  hipLaunchKernelGGL(k_group_scatter, dim3(nt), dim3(kBlock), 0, s, group_off, n,
                      (const int *)w.tile_counts, (const int *)w.group_totals, nt, w.newid);
-  const int mb = std::min((g->m + kBlock - 1) / kBlock, 8 * std::max(1, w.num_cus) * 4);
-  hipLaunchKernelGGL(k_map_sources, dim3(mb), dim3(kBlock), 0, s, g->in_sources, g->m,
-                     (const int *)w.newid, w.src_p);
+  const int mb = std::min((m + kBlock - 1) / kBlock, 8 * std::max(1, w.num_cus) * 4);
+  hipLaunchKernelGGL(k_map_sources, dim3(mb), dim3(kBlock), 0, s, idx, m, (const int *)w.newid,
+                     w.src_p);
   LAUNCH_TRY();
   *out = Locality{w.newid, w.src_p};
   return PR_OK;
@@ -364,48 +371,72 @@ void reset_stats() {
   t_err.clear();
 }
 
-// Static iteration (Alg. 1), from 1/n or from `init` (Naive-dynamic).
-int run_static(const pr_csr *g, double alpha, double tol, int max_iter, const double *init,
-               double *ranks_out) {
+// One full-pull iteration problem:
+//   x_new[v] = tele ? tscale * tele[v] + alpha * S(v) : (1 - alpha)/n + alpha * S(v)
+//   S(v) = sum over row v of (w ? w[e] * x[idx[e]] : x[idx[e]] / |out(idx[e])|)
+// Static (Alg. 1, Eq. 1), Naive-dynamic (init = R^{t-1}), the weighted
+// forward and the adjoint iteration are instances.
+struct PullProblem {
+  int n, m;
+  const int *row_off, *row_idx;  // CSR pulled over (rows = updated vertices)
+  const int *deg_off;            // offsets giving |out(u)| (unweighted only)
+  const int *group_off;          // degrees that group the gather side
+  const double *w;               // per-edge weights aligned with row_idx, or null
+  const double *tele;            // teleport term or null
+  double tscale;
+  const double *init;            // start vector or null (then r0)
+  double r0;
+  bool relabel;                  // gather-side renumbering allowed
+};
+
+int run_pull(const PullProblem &P, double alpha, double tol, int max_iter, double *ranks_out) {
   hipStream_t s = t_stream;
-  const int n = g->n;
+  const int n = P.n;
   const pr_tuning tn = g_tuning;
   Workspace *wp = nullptr;
-  int rc = get_ws((size_t)n, (size_t)g->m, tn.hub_chunk_edges, tn.grid_blocks, &wp);
+  int rc = get_ws((size_t)n, (size_t)P.m, tn.hub_chunk_edges, tn.grid_blocks, &wp);
   if (rc) return rc;
   Workspace &w = *wp;
-  const int B = grid_blocks(w, tn, k_rank_static);
+  const bool weighted = P.w != nullptr;
+  const int B = weighted ? grid_blocks(w, tn, k_rank_static<true>)
+                         : grid_blocks(w, tn, k_rank_static<false>);
   const int np = B + kHubFinalizeBlocks;
   CallTimer timer(w, s);
   hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, s, w.ctrl);
-  rc = partition(w, g->in_offsets, n, tn.lane_max_degree, tn.wave_max_degree,
-                 tn.hub_chunk_edges, w.hi_in, kInWave, kInChunks, w.hub_start_in, w.chunk_hub_in,
-                 s);
+  rc = partition(w, P.row_off, n, tn.lane_max_degree, tn.wave_max_degree, tn.hub_chunk_edges,
+                 w.hi_in, kInWave, kInChunks, w.hub_start_in, w.chunk_hub_in, s);
   if (rc) return rc;
   Locality loc;
-  if ((rc = locality(w, g, tn, s, &loc))) return rc;
+  if ((rc = locality(w, n, P.m, P.group_off, P.row_idx, tn, P.relabel, s, &loc))) return rc;
   // R[0] is the caller's output vector; with `init` (which may alias it) the
   // start vector is copied into it.
   double *R[2] = {ranks_out, w.R1};
   double *X[2] = {w.X0, w.X1};
   hipLaunchKernelGGL(k_static_init, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n,
-                     g->out_offsets, loc.pos, init, R[0], X[0]);
+                     P.deg_off, loc.pos, P.init, P.r0, (int)weighted, R[0], X[0]);
   LAUNCH_TRY();
   const double C0 = (1.0 - alpha) / (double)n;
   const int t1 = tn.lane_max_degree, CH = tn.hub_chunk_edges;
   auto launch = [&](int it, bool prof, hipEvent_t after) -> int {
     const int a = it & 1, b = a ^ 1;
-    hipLaunchKernelGGL(k_rank_static, dim3(B), dim3(kBlock), 0, s, g->in_offsets, loc.src,
-                       g->out_offsets, loc.pos, (const double *)X[a], (const double *)R[a], R[b],
-                       X[b],
-                       (const int *)w.hi_in, (const int *)w.counts, (const int *)w.hub_start_in,
-                       (const int *)w.chunk_hub_in, w.hub_part, CH, n, t1, C0, alpha, w.partials,
-                       (const Ctrl *)w.ctrl);
+    if (weighted)
+      hipLaunchKernelGGL(k_rank_static<true>, dim3(B), dim3(kBlock), 0, s, P.row_off, loc.src,
+                         P.w, P.deg_off, loc.pos, (const double *)X[a], (const double *)R[a],
+                         R[b], X[b], (const int *)w.hi_in, (const int *)w.counts,
+                         (const int *)w.hub_start_in, (const int *)w.chunk_hub_in, w.hub_part, CH,
+                         n, t1, C0, alpha, P.tele, P.tscale, w.partials, (const Ctrl *)w.ctrl);
+    else
+      hipLaunchKernelGGL(k_rank_static<false>, dim3(B), dim3(kBlock), 0, s, P.row_off, loc.src,
+                         (const double *)nullptr, P.deg_off, loc.pos, (const double *)X[a],
+                         (const double *)R[a], R[b], X[b], (const int *)w.hi_in,
+                         (const int *)w.counts, (const int *)w.hub_start_in,
+                         (const int *)w.chunk_hub_in, w.hub_part, CH, n, t1, C0, alpha, P.tele,
+                         P.tscale, w.partials, (const Ctrl *)w.ctrl);
     if (prof) HIP_TRY(hipEventRecord(after, s));
     hipLaunchKernelGGL(k_hub_finalize_static, dim3(kHubFinalizeBlocks), dim3(kBlock), 0, s,
                        (const int *)w.hi_in, (const int *)w.counts, (const int *)w.hub_start_in,
-                       (const double *)w.hub_part, g->out_offsets, loc.pos,
-                       (const double *)R[a], R[b], X[b], C0, alpha, w.partials + B,
+                       (const double *)w.hub_part, P.deg_off, loc.pos, (const double *)R[a], R[b],
+                       X[b], C0, alpha, P.tele, P.tscale, (int)weighted, w.partials + B,
                        (const Ctrl *)w.ctrl);
     hipLaunchKernelGGL(k_linf_final, dim3(1), dim3(kFinalBlock), 0, s,
                        (const double *)w.partials, np, w.ctrl, tol, it);
@@ -426,6 +457,22 @@ int run_static(const pr_csr *g, double alpha, double tol, int max_iter, const do
   return t_stats.converged ? PR_OK : PR_NOT_CONVERGED;
 }
 
+// Static iteration (Alg. 1), from 1/n or from `init` (Naive-dynamic).
+int run_static(const pr_csr *g, double alpha, double tol, int max_iter, const double *init,
+               double *ranks_out) {
+  PullProblem P{};
+  P.n = g->n;
+  P.m = g->m;
+  P.row_off = g->in_offsets;
+  P.row_idx = g->in_sources;
+  P.deg_off = g->out_offsets;
+  P.group_off = g->out_offsets;
+  P.init = init;
+  P.r0 = 1.0 / (double)g->n;
+  P.relabel = true;
+  return run_pull(P, alpha, tol, max_iter, ranks_out);
+}
+
 int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *ins,
                          const double *prev, double alpha, double tol, double tau_f,
                          double tau_p, int max_iter, bool prune, double *ranks_out) {
@@ -444,7 +491,7 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
   const int t1 = tn.lane_max_degree, t_exp = tn.expand_lane_max_degree, CH = tn.hub_chunk_edges;
   hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, s, w.ctrl);
   Locality loc;
-  if ((rc = locality(w, g, tn, s, &loc))) return rc;
+  if ((rc = locality(w, n, g->m, g->out_offsets, g->in_sources, tn, true, s, &loc))) return rc;
   double *X = w.X0;
   hipLaunchKernelGGL(k_dfp_init, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n,
                      g->out_offsets, loc.pos, prev, R, X, dV, dN, cv);
@@ -580,7 +627,7 @@ int run_ppr(const pr_csr *g, const double *teleport, int K, double alpha, double
                  kInChunks, w.hub_start_in, w.chunk_hub_in, s);
   if (rc) return rc;
   Locality loc;
-  if ((rc = locality(w, g, tn, s, &loc))) return rc;
+  if ((rc = locality(w, n, g->m, g->out_offsets, g->in_sources, tn, true, s, &loc))) return rc;
   const int ib = (int)std::min<size_t>((nk + kBlock - 1) / kBlock, (size_t)B * 4);
   hipLaunchKernelGGL(k_ppr_init, dim3(ib), dim3(kBlock), 0, s, n, K, g->out_offsets, loc.pos,
                      Rb[0], Xb[0], w.ppr_vdone, w.ppr_viters);
@@ -623,6 +670,78 @@ int run_ppr(const pr_csr *g, const double *teleport, int K, double alpha, double
   t_stats.total_ms = timer.ms();
   collect_profile(w, iters);
   return t_stats.converged ? PR_OK : PR_NOT_CONVERGED;
+}
+
+// Weighted forward: r = alpha * A r + (1 - alpha) s with A[v][u] = w(u -> v).
+int run_weighted(const pr_csr *g, const double *in_w, const double *tele, double alpha,
+                 double tol, int max_iter, double *ranks_out) {
+  PullProblem P{};
+  P.n = g->n;
+  P.m = g->m;
+  P.row_off = g->in_offsets;
+  P.row_idx = g->in_sources;
+  P.deg_off = g->out_offsets;
+  P.group_off = g->out_offsets;
+  P.w = in_w;
+  P.tele = tele;
+  P.tscale = 1.0 - alpha;
+  P.r0 = 1.0 / (double)g->n;
+  P.relabel = true;
+  return run_pull(P, alpha, tol, max_iter, ranks_out);
+}
+
+// Adjoint of the weighted forward: lambda = g + alpha * A^T lambda, pulled
+// over the out-CSR with the weights transposed into out-CSR order, from
+// lambda = 0; then the edge and teleport gradients.
+int run_adjoint(const pr_csr *g, const double *in_w, const double *r, const double *grad_r,
+                double alpha, double tol, int max_iter, double *grad_w, double *grad_s,
+                double *lambda_out, double *lambda_tmp_owner) {
+  hipStream_t s = t_stream;
+  const int n = g->n, m = g->m;
+  Workspace *wp = nullptr;
+  const pr_tuning tn = g_tuning;
+  int rc = get_ws((size_t)n, (size_t)m, tn.hub_chunk_edges, tn.grid_blocks, &wp);
+  if (rc) return rc;
+  Workspace &w = *wp;
+  if ((size_t)m > w.cap_w_out) {
+    (void)hipFree(w.w_out);
+    w.w_out = nullptr;
+    w.cap_w_out = 0;
+    hipError_t e = hipMalloc(&w.w_out, (size_t)m * sizeof(double));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(e == hipErrorOutOfMemory ? PR_ENOMEM : PR_EHIP,
+                  std::string("adjoint workspace: ") + hipGetErrorString(e));
+    }
+    w.cap_w_out = (size_t)m;
+  }
+  const int gb = std::min((m + kBlock - 1) / kBlock, 8 * std::max(1, w.num_cus) * 4);
+  hipLaunchKernelGGL(k_fill, dim3(gb), dim3(kBlock), 0, s, w.w_out, (size_t)m, 0.0);
+  hipLaunchKernelGGL(k_transpose_weights, dim3(gb), dim3(kBlock), 0, s, g->in_offsets,
+                     g->in_sources, in_w, g->out_offsets, g->out_targets, n, m, w.w_out);
+  LAUNCH_TRY();
+  PullProblem P{};
+  P.n = n;
+  P.m = m;
+  P.row_off = g->out_offsets;
+  P.row_idx = g->out_targets;
+  P.deg_off = g->out_offsets;
+  P.group_off = g->in_offsets;
+  P.w = w.w_out;
+  P.tele = grad_r;
+  P.tscale = 1.0;
+  P.r0 = 0.0;
+  P.relabel = true;
+  double *lam = lambda_out ? lambda_out : lambda_tmp_owner;
+  rc = run_pull(P, alpha, tol, max_iter, lam);
+  if (rc < 0) return rc;
+  const pr_stats keep = t_stats;
+  hipLaunchKernelGGL(k_adjoint_grads, dim3(gb), dim3(kBlock), 0, s, g->in_offsets, g->in_sources,
+                     n, m, r, (const double *)lam, alpha, grad_w, grad_s);
+  LAUNCH_TRY();
+  HIP_TRY(hipStreamSynchronize(s));
+  t_stats = keep;
+  return rc;
 }
 
 int check_edges(const pr_edges *e, const char *name) {
@@ -688,6 +807,46 @@ int pr_ppr(const pr_csr *csr, const double *teleport, int k, double alpha, doubl
     return fail(PR_EINVAL, "n * k too large");
   std::lock_guard<std::mutex> lock(g_mu);
   return run_ppr(csr, teleport, k, alpha, tol, max_iter, ranks_out, iters_out);
+}
+
+int pr_weighted(const pr_csr *csr, const double *in_weights, const double *teleport,
+                double alpha, double tol, int max_iter, double *ranks_out) {
+  reset_stats();
+  int rc = check_csr(csr, false);
+  if (rc) return rc;
+  if ((rc = check_params(alpha, tol, max_iter))) return rc;
+  if (!in_weights || !ranks_out) return fail(PR_EINVAL, "in_weights and ranks_out are required");
+  std::lock_guard<std::mutex> lock(g_mu);
+  return run_weighted(csr, in_weights, teleport, alpha, tol, max_iter, ranks_out);
+}
+
+int pr_adjoint(const pr_csr *csr, const double *in_weights, const double *ranks,
+               const double *grad_ranks, double alpha, double tol, int max_iter,
+               double *grad_weights, double *grad_teleport, double *lambda_out) {
+  reset_stats();
+  int rc = check_csr(csr, true);
+  if (rc) return rc;
+  if ((rc = check_params(alpha, tol, max_iter))) return rc;
+  if (!in_weights || !ranks || !grad_ranks)
+    return fail(PR_EINVAL, "in_weights, ranks and grad_ranks are required");
+  if (!grad_weights && !grad_teleport && !lambda_out)
+    return fail(PR_EINVAL, "no output requested");
+  std::lock_guard<std::mutex> lock(g_mu);
+  double *tmp = nullptr;
+  if (!lambda_out) {
+    hipError_t e = hipMallocAsync((void **)&tmp, (size_t)csr->n * sizeof(double), t_stream);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(PR_ENOMEM, "lambda buffer");
+    }
+  }
+  rc = run_adjoint(csr, in_weights, ranks, grad_ranks, alpha, tol, max_iter, grad_weights,
+                   grad_teleport, lambda_out, tmp);
+  if (tmp) {
+    (void)hipFreeAsync(tmp, t_stream);
+    (void)hipStreamSynchronize(t_stream);
+  }
+  return rc;
 }
 
 int pr_validate_csr(const pr_csr *g) {

@@ -58,7 +58,8 @@ class PrStats(ctypes.Structure):
                 ("reserved", ctypes.c_double * 4)]
 
 
-EXPORTED = ["pr_static", "pr_dfp", "pr_dfp_ex", "pr_ppr", "pr_validate_csr", "pr_set_tuning",
+EXPORTED = ["pr_static", "pr_dfp", "pr_dfp_ex", "pr_ppr", "pr_weighted", "pr_adjoint",
+            "pr_validate_csr", "pr_set_tuning",
             "pr_get_tuning", "pr_last_stats", "pr_set_profiling", "pr_set_stream",
             "pr_last_error", "pr_release"]
 
@@ -82,6 +83,8 @@ def load_library(path: str = SO_PATH):
     lib.pr_dfp_ex.argtypes = [P(PrCsr), P(PrCsr), P(PrEdges), P(PrEdges), vp, d, d, d, d, i, i,
                               vp]
     lib.pr_ppr.argtypes = [P(PrCsr), vp, i, d, d, i, vp, P(ctypes.c_int32)]
+    lib.pr_weighted.argtypes = [P(PrCsr), vp, vp, d, d, i, vp]
+    lib.pr_adjoint.argtypes = [P(PrCsr), vp, vp, vp, d, d, i, vp, vp, vp]
     lib.pr_validate_csr.argtypes = [P(PrCsr)]
     lib.pr_set_tuning.argtypes = [P(PrTuning)]
     lib.pr_get_tuning.argtypes = [P(PrTuning)]
@@ -93,7 +96,8 @@ def load_library(path: str = SO_PATH):
     lib.pr_last_error.restype = ctypes.c_char_p
     lib.pr_release.argtypes = []
     lib.pr_release.restype = None
-    for f in ("pr_static", "pr_dfp", "pr_dfp_ex", "pr_ppr", "pr_validate_csr", "pr_set_tuning",
+    for f in ("pr_static", "pr_dfp", "pr_dfp_ex", "pr_ppr", "pr_weighted", "pr_adjoint",
+              "pr_validate_csr", "pr_set_tuning",
               "pr_get_tuning", "pr_last_stats", "pr_set_profiling"):
         getattr(lib, f).restype = ctypes.c_int
     if path == SO_PATH:
@@ -254,6 +258,50 @@ def ppr(g: DeviceGraph, teleport, alpha=ALPHA, tol=TOL, max_iter=MAX_ITERATIONS,
                            out.data_ptr(), its.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))),
                 lib)
     return _result(rc, out), its
+
+
+def _ptr(x):
+    return None if x is None else x.data_ptr()
+
+
+def weighted(g: DeviceGraph, in_weights, teleport=None, alpha=ALPHA, tol=TOL,
+             max_iter=MAX_ITERATIONS, out=None) -> Result:
+    """Weighted forward r = alpha*A r + (1-alpha) s through pr_weighted.
+    in_weights: [m] float64 in in-CSR order; teleport: [n] or None (1/n)."""
+    torch = _torch()
+    lib = load_library()
+    assert in_weights.dtype == torch.float64 and in_weights.is_contiguous()
+    assert in_weights.numel() == g.m
+    if teleport is not None:
+        assert teleport.dtype == torch.float64 and teleport.is_contiguous()
+        assert teleport.numel() == g.n
+    if out is None:
+        out = torch.empty(g.n, dtype=torch.float64, device=in_weights.device)
+    _bind_stream(lib, torch)
+    csr = g.csr()
+    rc = _check(lib.pr_weighted(ctypes.byref(csr), in_weights.data_ptr(), _ptr(teleport), alpha,
+                                tol, max_iter, out.data_ptr()), lib)
+    return _result(rc, out)
+
+
+def adjoint(g: DeviceGraph, in_weights, ranks, grad_ranks, alpha=ALPHA, tol=TOL,
+            max_iter=MAX_ITERATIONS, want_weights=True, want_teleport=True, want_lambda=False):
+    """Adjoint of pr_weighted through pr_adjoint. Returns (grad_weights [m] in
+    in-CSR order or None, grad_teleport [n] or None, lambda [n] or None)."""
+    torch = _torch()
+    lib = load_library()
+    for x in (in_weights, ranks, grad_ranks):
+        assert x.dtype == torch.float64 and x.is_contiguous()
+    dev = ranks.device
+    gw = torch.empty(g.m, dtype=torch.float64, device=dev) if want_weights else None
+    gs = torch.empty(g.n, dtype=torch.float64, device=dev) if want_teleport else None
+    lam = torch.empty(g.n, dtype=torch.float64, device=dev) if want_lambda else None
+    _bind_stream(lib, torch)
+    csr = g.csr()
+    _check(lib.pr_adjoint(ctypes.byref(csr), in_weights.data_ptr(), ranks.data_ptr(),
+                          grad_ranks.data_ptr(), alpha, tol, max_iter, _ptr(gw), _ptr(gs),
+                          _ptr(lam)), lib)
+    return gw, gs, lam
 
 
 def validate(g: DeviceGraph) -> None:

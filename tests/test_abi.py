@@ -110,3 +110,17 @@ def test_ppr_argument_errors(lib):
                       None) == prhip.PR_EINVAL
     assert lib.pr_ppr(ctypes.byref(csr), ctypes.c_void_p(8), 4, 1.5, 1e-10, 10,
                       ctypes.c_void_p(8), None) == prhip.PR_EINVAL
+
+
+def test_weighted_adjoint_argument_errors(lib):
+    csr = prhip.PrCsr(4, 4, 8, 8, 8, None)
+    assert lib.pr_weighted(ctypes.byref(csr), None, None, 0.85, 1e-10, 10,
+                           ctypes.c_void_p(8)) == prhip.PR_EINVAL
+    # the adjoint needs out_targets and at least one output
+    assert lib.pr_adjoint(ctypes.byref(csr), ctypes.c_void_p(8), ctypes.c_void_p(8),
+                          ctypes.c_void_p(8), 0.85, 1e-10, 10, ctypes.c_void_p(8), None,
+                          None) == prhip.PR_EINVAL
+    csr2 = prhip.PrCsr(4, 4, 8, 8, 8, 8)
+    assert lib.pr_adjoint(ctypes.byref(csr2), ctypes.c_void_p(8), ctypes.c_void_p(8),
+                          ctypes.c_void_p(8), 0.85, 1e-10, 10, None, None,
+                          None) == prhip.PR_EINVAL
