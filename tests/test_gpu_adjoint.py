@@ -43,6 +43,7 @@ def cu(a):
 @pytest.mark.parametrize("scale,relabel,tuning", [(11, 0, {}), (12, 1, {}),
                                                   (11, 1, dict(lane_max_degree=2,
                                                                wave_max_degree=16,
+                                                               expand_lane_max_degree=2,
                                                                hub_chunk_edges=32))])
 def test_weighted_forward_vs_oracle(scale, relabel, tuning):
     prhip.set_tuning(relabel=relabel, **tuning)
