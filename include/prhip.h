@@ -135,6 +135,22 @@ int pr_ppr(const pr_csr *csr, const double *teleport, int k, double alpha, doubl
            int max_iter, double *ranks_out, int32_t *iters_out);
 
 /*
+ * Static PageRank (as pr_static) on num_graphs independent graphs in one
+ * batched computation: the graphs are joined into one block-diagonal union,
+ * every graph keeps its own teleport term (1 - alpha)/n_g and its own
+ * L-infinity stop (a converged graph is no longer updated), and the
+ * iterations run as replays of one captured hipGraph. Each graph's result
+ * equals pr_static on that graph with the same tuning.
+ *   graphs       [num_graphs] host array of graphs (device pointers inside;
+ *                out_targets not read); total vertices and edges < 2^31
+ *   num_graphs   1 .. 4096
+ *   ranks_out    [num_graphs] host array of device pointers, [n_g] each
+ *   iters_out    [num_graphs] host array for the iteration counts, or NULL
+ */
+int pr_static_batched(const pr_csr *graphs, int num_graphs, double alpha, double tol,
+                      int max_iter, double *const *ranks_out, int32_t *iters_out);
+
+/*
  * Weighted forward (PageRank with given transition weights and teleport):
  *   r_v = alpha * sum_{u in in(v)} P_uv * r_u + (1 - alpha) * s_v,
  * from r = 1/n, L-infinity stop as in pr_static. The weights are used as

@@ -348,6 +348,9 @@ struct StaticOut {
         weighted ? r : r / (double)(ld_nt(out_off + v + 1) - ld_nt(out_off + v));
     return fabs(r - ld_nt(R + v));
   }
+  __device__ __forceinline__ bool active(int) const { return true; }
+  __device__ __forceinline__ void inactive(int) const {}
+  __device__ __forceinline__ void note(int, double) const {}
 };
 
 template <bool PRUNE>
@@ -373,19 +376,25 @@ struct DynOut {
     cv[v] = 1;
     return dr;
   }
+  // only affected vertices are updated; the others clear their dN flag
+  __device__ __forceinline__ bool active(int v) const { return dV[v] != 0; }
+  __device__ __forceinline__ void inactive(int v) const { dN[v] = 0; }
+  __device__ __forceinline__ void note(int, double) const {}
 };
 
 // ------------------------------------------------------------ rank update
 // One rank update (Alg. 3 / Eq. 1 for Static, Eq. 2 for DF-P) over all three
-// classes; see the file comment for the launch shape. DYN = DF/DF-P mode:
-// only vertices with dV set are updated, and every vertex processed here
-// rewrites its dN flag (cleared when unaffected), which is the clearing of
-// delta_N at the start of the iteration in Alg. 2.
-template <bool DYN, bool WEIGHTED, class Out>
+// classes; see the file comment for the launch shape. The output policy
+// `out` decides which vertices are updated (active: all for Static; those
+// with dV set for DF/DF-P), what an inactive vertex does (DF/DF-P clears its
+// dN flag, which is the clearing of delta_N at the start of the iteration in
+// Alg. 2), computes the new value (finish) and may record its |change|
+// elsewhere (note). partials may be null (no per-workgroup maximum).
+template <bool WEIGHTED, class Out>
 __device__ __forceinline__ void rank_update(
     const int *__restrict__ in_off, const int *__restrict__ in_src,
-    const double *__restrict__ wt, const double *__restrict__ X, const uint8_t *dV,
-    uint8_t *dN, const int *__restrict__ hi, const int *__restrict__ counts,
+    const double *__restrict__ wt, const double *__restrict__ X, const int *__restrict__ hi,
+    const int *__restrict__ counts,
     const int *__restrict__ hub_start, const int *__restrict__ chunk_hub,
     double *__restrict__ hub_part, int CH, int n, int t1, const Out &out,
     double *__restrict__ partials) {
@@ -408,7 +417,7 @@ __device__ __forceinline__ void rank_update(
     if (cl < nch) {
       const int i = chunk_hub[c];
       v = hi[n1 + i];
-      f = DYN ? (dV[v] != 0) : true;
+      f = out.active(v);
       const int r0 = in_off[v], r1 = in_off[v + 1];
       e0 = r0 + (c - hub_start[i]) * CH;
       e1 = min(e0 + CH, r1);
@@ -443,8 +452,8 @@ __device__ __forceinline__ void rank_update(
       bool f = false;
       if (ii < n1) {
         v = hi[ii];
-        f = DYN ? (dV[v] != 0) : true;
-        if (DYN && !f) dN[v] = 0;
+        f = out.active(v);
+        if (!f) out.inactive(v);
       }
       unsigned long long mask = __ballot(f);
       while (mask) {
@@ -454,7 +463,11 @@ __device__ __forceinline__ void rank_update(
         const int e0 = in_off[vv], e1 = in_off[vv + 1];
         double c = strided_sum<kWave, WEIGHTED>(e0, e1, lane, in_src, wt, X);
         c = wave_sum(c);
-        if (lane == 0) dmax = fmax(dmax, out.finish(vv, c));
+        if (lane == 0) {
+          const double d = out.finish(vv, c);
+          dmax = fmax(dmax, d);
+          out.note(vv, d);
+        }
       }
     }
   }
@@ -467,18 +480,22 @@ __device__ __forceinline__ void rank_update(
       if (v < n) {
         const int e0 = ld_nt(in_off + v), e1 = ld_nt(in_off + v + 1);
         if (e1 - e0 <= t1) {
-          if (!DYN || dV[v]) {
+          if (out.active(v)) {
             const double c = row_sum_seq<WEIGHTED>(in_src, wt, X, e0, e1);
-            dmax = fmax(dmax, out.finish(v, c));
+            const double d = out.finish(v, c);
+            dmax = fmax(dmax, d);
+            out.note(v, d);
           } else {
-            dN[v] = 0;
+            out.inactive(v);
           }
         }
       }
     }
   }
-  dmax = block_max<kBlock>(dmax, lds);
-  if (tid == 0) partials[blockIdx.x] = dmax;
+  if (partials) {
+    dmax = block_max<kBlock>(dmax, lds);
+    if (tid == 0) partials[blockIdx.x] = dmax;
+  }
 }
 
 // One full pull (Static, Naive-dynamic, the weighted forward and the
@@ -497,8 +514,8 @@ __global__ __launch_bounds__(kBlock) void k_rank_static(
     double *__restrict__ partials, const Ctrl *__restrict__ ctrl) {
   if (ctrl->done) return;
   const StaticOut out{out_off, pos, R, Rn, Xn, C0, alpha, tele, tscale, WEIGHTED};
-  rank_update<false, WEIGHTED>(in_off, in_src, wt, X, nullptr, nullptr, hi, counts, hub_start,
-                               chunk_hub, hub_part, CH, n, t1, out, partials);
+  rank_update<WEIGHTED>(in_off, in_src, wt, X, hi, counts, hub_start, chunk_hub, hub_part, CH, n,
+                        t1, out, partials);
 }
 
 template <bool PRUNE>
@@ -512,33 +529,36 @@ __global__ __launch_bounds__(kBlock) void k_rank_dfp(
     const Ctrl *__restrict__ ctrl) {
   if (ctrl->done) return;
   const DynOut<PRUNE> out{out_off, R, T, dV, dN, cv, C0, alpha, tau_f, tau_p};
-  rank_update<true, false>(in_off, in_src, nullptr, X, dV, dN, hi, counts, hub_start, chunk_hub,
-                           hub_part, CH, n, t1, out, partials);
+  rank_update<false>(in_off, in_src, nullptr, X, hi, counts, hub_start, chunk_hub, hub_part, CH, n,
+                     t1, out, partials);
 }
 
 // Split-class vertices: add the chunk partials in chunk order and finish.
-template <bool DYN, class Out>
+template <class Out>
 __device__ __forceinline__ void hub_finalize(const int *__restrict__ hi,
                                              const int *__restrict__ counts,
                                              const int *__restrict__ hub_start,
-                                             const double *__restrict__ hub_part,
-                                             const uint8_t *dV, uint8_t *dN, const Out &out,
+                                             const double *__restrict__ hub_part, const Out &out,
                                              double *__restrict__ partials) {
   __shared__ double lds[kWavesPerBlock];
   const int n1 = counts[kInWave], n2 = counts[kInSplit];
   double dmax = 0.0;
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < n2; i += gridDim.x * kBlock) {
     const int v = hi[n1 + i];
-    if (DYN && !dV[v]) {
-      dN[v] = 0;
+    if (!out.active(v)) {
+      out.inactive(v);
       continue;
     }
     double c = 0.0;
     for (int k = hub_start[i]; k < hub_start[i + 1]; ++k) c = c + hub_part[k];
-    dmax = fmax(dmax, out.finish(v, c));
+    const double d = out.finish(v, c);
+    dmax = fmax(dmax, d);
+    out.note(v, d);
   }
-  dmax = block_max<kBlock>(dmax, lds);
-  if (threadIdx.x == 0) partials[blockIdx.x] = dmax;
+  if (partials) {
+    dmax = block_max<kBlock>(dmax, lds);
+    if (threadIdx.x == 0) partials[blockIdx.x] = dmax;
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_hub_finalize_static(
@@ -549,7 +569,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_finalize_static(
     double tscale, int weighted, double *__restrict__ partials, const Ctrl *__restrict__ ctrl) {
   if (ctrl->done) return;
   const StaticOut out{out_off, pos, R, Rn, Xn, C0, alpha, tele, tscale, weighted != 0};
-  hub_finalize<false>(hi, counts, hub_start, hub_part, nullptr, nullptr, out, partials);
+  hub_finalize(hi, counts, hub_start, hub_part, out, partials);
 }
 
 template <bool PRUNE>
@@ -561,7 +581,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_finalize_dfp(
     const Ctrl *__restrict__ ctrl) {
   if (ctrl->done) return;
   const DynOut<PRUNE> out{out_off, R, T, dV, dN, cv, C0, alpha, tau_f, tau_p};
-  hub_finalize<true>(hi, counts, hub_start, hub_part, dV, dN, out, partials);
+  hub_finalize(hi, counts, hub_start, hub_part, out, partials);
 }
 
 // Second stage of the L-infinity norm; records the iteration's outcome.

@@ -23,6 +23,7 @@
 #include <string>
 #include <vector>
 
+#include "batched.h"
 #include "kernels.h"
 #include "ppr.h"
 #include "prhip.h"
@@ -77,6 +78,16 @@ struct Workspace {
   int *ppr_vdone = nullptr, *ppr_viters = nullptr;
   uint8_t *ppr_split = nullptr;
   size_t cap_ppr_buf = 0, cap_ppr_part = 0, cap_ppr_pmax = 0, cap_ppr_k = 0, cap_ppr_n = 0;
+  // batched Static: union CSR, graph ids, per-graph state
+  int *u_in_off = nullptr, *u_in_src = nullptr, *u_out_off = nullptr, *u_gid = nullptr;
+  size_t cap_u_n = 0, cap_u_m = 0;
+  int *b_vbase = nullptr, *b_ebase = nullptr, *b_gdone = nullptr, *b_giters = nullptr;
+  double *b_c0 = nullptr, *b_gdelta = nullptr, *b_gpart = nullptr;
+  BatchDesc *b_desc = nullptr;
+  double **b_outs = nullptr;
+  size_t cap_b_g = 0, cap_b_part = 0;
+  hipStream_t cap_stream = nullptr;
+  hipEvent_t cap_ev[2] = {};
   Ctrl *ctrl = nullptr;
   Ctrl *host_ctrl = nullptr;  // pinned ring
   int *host_counts = nullptr;  // pinned
@@ -134,9 +145,27 @@ void free_ppr(Workspace &w) {
   w.cap_ppr_buf = w.cap_ppr_part = w.cap_ppr_pmax = w.cap_ppr_k = w.cap_ppr_n = 0;
 }
 
+void free_batch(Workspace &w) {
+  (void)hipFree(w.u_in_off); (void)hipFree(w.u_in_src); (void)hipFree(w.u_out_off);
+  (void)hipFree(w.u_gid); (void)hipFree(w.b_vbase); (void)hipFree(w.b_ebase);
+  (void)hipFree(w.b_gdone); (void)hipFree(w.b_giters); (void)hipFree(w.b_c0);
+  (void)hipFree(w.b_gdelta); (void)hipFree(w.b_gpart); (void)hipFree(w.b_desc);
+  (void)hipFree(w.b_outs);
+  w.u_in_off = w.u_in_src = w.u_out_off = w.u_gid = nullptr;
+  w.b_vbase = w.b_ebase = w.b_gdone = w.b_giters = nullptr;
+  w.b_c0 = w.b_gdelta = w.b_gpart = nullptr;
+  w.b_desc = nullptr;
+  w.b_outs = nullptr;
+  w.cap_u_n = w.cap_u_m = w.cap_b_g = w.cap_b_part = 0;
+}
+
 void free_ws(Workspace &w) {
   free_arrays(w);
   free_ppr(w);
+  free_batch(w);
+  if (w.cap_stream) (void)hipStreamDestroy(w.cap_stream);
+  for (auto &e : w.cap_ev)
+    if (e) (void)hipEventDestroy(e);
   (void)hipFree(w.w_out);
   w.w_out = nullptr;
   w.cap_w_out = 0;
@@ -744,6 +773,185 @@ int run_adjoint(const pr_csr *g, const double *in_w, const double *r, const doub
   return rc;
 }
 
+constexpr int kMaxBatchGraphs = 4096;  // per-graph maxima live in LDS (8 bytes each)
+
+int batch_ws(Workspace &w, size_t N, size_t M, size_t G, size_t part_rows) {
+  const size_t npart = part_rows * G;
+  if (N > w.cap_u_n || M > w.cap_u_m || G > w.cap_b_g || npart > w.cap_b_part) {
+    const size_t nn = std::max(N, w.cap_u_n), mm = std::max(M, w.cap_u_m);
+    const size_t gg = std::max(G, w.cap_b_g), pp = std::max(npart, w.cap_b_part);
+    free_batch(w);
+    hipError_t e = hipSuccess;
+    if ((e = hipMalloc(&w.u_in_off, (nn + 1) * sizeof(int))) != hipSuccess ||
+        (e = hipMalloc(&w.u_out_off, (nn + 1) * sizeof(int))) != hipSuccess ||
+        (e = hipMalloc(&w.u_in_src, mm * sizeof(int))) != hipSuccess ||
+        (e = hipMalloc(&w.u_gid, nn * sizeof(int))) != hipSuccess ||
+        (e = hipMalloc(&w.b_vbase, (gg + 1) * sizeof(int))) != hipSuccess ||
+        (e = hipMalloc(&w.b_ebase, (gg + 1) * sizeof(int))) != hipSuccess ||
+        (e = hipMalloc(&w.b_gdone, gg * sizeof(int))) != hipSuccess ||
+        (e = hipMalloc(&w.b_giters, gg * sizeof(int))) != hipSuccess ||
+        (e = hipMalloc(&w.b_c0, gg * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&w.b_gdelta, gg * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&w.b_gpart, pp * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&w.b_desc, gg * sizeof(BatchDesc))) != hipSuccess ||
+        (e = hipMalloc(&w.b_outs, gg * sizeof(double *))) != hipSuccess) {
+      (void)hipGetLastError();
+      free_batch(w);
+      return fail(e == hipErrorOutOfMemory ? PR_ENOMEM : PR_EHIP,
+                  std::string("batch workspace allocation: ") + hipGetErrorString(e));
+    }
+    w.cap_u_n = nn;
+    w.cap_u_m = mm;
+    w.cap_b_g = gg;
+    w.cap_b_part = pp;
+  }
+  if (!w.cap_stream) {
+    HIP_TRY(hipStreamCreateWithFlags(&w.cap_stream, hipStreamNonBlocking));
+    for (auto &e : w.cap_ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
+  return PR_OK;
+}
+
+// Static PageRank (Alg. 1) on G graphs at once: union CSR, one partition and
+// renumbering, per-graph teleport and convergence; the iterations run as
+// replays of one captured hipGraph holding an even and an odd iteration.
+int run_batched(const pr_csr *graphs, int G, double alpha, double tol, int max_iter,
+                double *const *outs, int32_t *iters_out) {
+  hipStream_t s = t_stream;
+  const pr_tuning tn = g_tuning;
+  std::vector<int> vbase(G + 1), ebase(G + 1);
+  std::vector<BatchDesc> desc(G);
+  std::vector<double> c0(G);
+  long long N = 0, M = 0;
+  for (int g = 0; g < G; ++g) {
+    vbase[g] = (int)N;
+    ebase[g] = (int)M;
+    desc[g] = BatchDesc{graphs[g].in_offsets, graphs[g].in_sources, graphs[g].out_offsets,
+                        (int)N, (int)M, graphs[g].n, graphs[g].m};
+    c0[g] = (1.0 - alpha) / (double)graphs[g].n;
+    N += graphs[g].n;
+    M += graphs[g].m;
+    if (N > INT_MAX - 1 || M > INT_MAX - 1)
+      return fail(PR_EINVAL, "batch too large for int32 vertex/edge indices");
+  }
+  vbase[G] = (int)N;
+  ebase[G] = (int)M;
+  const int n = (int)N, m = (int)M;
+  Workspace *wp = nullptr;
+  int rc = get_ws((size_t)n, (size_t)m, tn.hub_chunk_edges, tn.grid_blocks, &wp);
+  if (rc) return rc;
+  Workspace &w = *wp;
+  const int B = grid_blocks(w, tn, k_rank_batched);
+  const int F = kHubFinalizeBlocks;
+  if ((rc = batch_ws(w, (size_t)n, (size_t)m, (size_t)G, (size_t)(B + F)))) return rc;
+  CallTimer timer(w, s);
+  HIP_TRY(hipMemcpyAsync(w.b_desc, desc.data(), G * sizeof(BatchDesc), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(w.b_vbase, vbase.data(), (G + 1) * sizeof(int), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(w.b_ebase, ebase.data(), (G + 1) * sizeof(int), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(w.b_c0, c0.data(), G * sizeof(double), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(w.b_outs, outs, G * sizeof(double *), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, s, w.ctrl);
+  const int ub = std::min((std::max(n, m) + kBlock - 1) / kBlock, 32 * std::max(1, w.num_cus));
+  hipLaunchKernelGGL(k_union_build, dim3(ub), dim3(kBlock), 0, s, (const BatchDesc *)w.b_desc,
+                     (const int *)w.b_vbase, (const int *)w.b_ebase, G, n, m, w.u_in_off,
+                     w.u_in_src, w.u_out_off, w.u_gid);
+  LAUNCH_TRY();
+  rc = partition(w, w.u_in_off, n, tn.lane_max_degree, tn.wave_max_degree, tn.hub_chunk_edges,
+                 w.hi_in, kInWave, kInChunks, w.hub_start_in, w.chunk_hub_in, s);
+  if (rc) return rc;
+  Locality loc;
+  if ((rc = locality(w, n, m, w.u_out_off, w.u_in_src, tn, true, s, &loc))) return rc;
+  double *R[2] = {w.T, w.R1};
+  double *X[2] = {w.X0, w.X1};
+  hipLaunchKernelGGL(k_batched_init, dim3(ub), dim3(kBlock), 0, s, n, G, (const int *)w.u_gid,
+                     (const int *)w.b_vbase, (const int *)w.u_out_off, loc.pos, R[0], X[0],
+                     w.b_gdone, w.b_giters);
+  LAUNCH_TRY();
+  // iteration pair captured on the library stream, after the work above
+  hipStream_t cs = w.cap_stream;
+  HIP_TRY(hipEventRecord(w.cap_ev[0], s));
+  HIP_TRY(hipStreamWaitEvent(cs, w.cap_ev[0], 0));
+  const size_t shm = (size_t)G * sizeof(unsigned long long);
+  const int t1 = tn.lane_max_degree, CH = tn.hub_chunk_edges;
+  HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  for (int it = 0; it < 2; ++it) {
+    const int a = it & 1, b = a ^ 1;
+    hipLaunchKernelGGL(k_rank_batched, dim3(B), dim3(kBlock), shm, cs, (const int *)w.u_in_off,
+                       loc.src, (const int *)w.u_out_off, loc.pos, (const double *)X[a],
+                       (const double *)R[a], R[b], X[b], (const int *)w.hi_in,
+                       (const int *)w.counts, (const int *)w.hub_start_in,
+                       (const int *)w.chunk_hub_in, w.hub_part, CH, n, t1, (const int *)w.u_gid,
+                       (const double *)w.b_c0, (const int *)w.b_gdone, G, alpha, w.b_gpart,
+                       (const Ctrl *)w.ctrl);
+    hipLaunchKernelGGL(k_hub_finalize_batched, dim3(F), dim3(kBlock), shm, cs,
+                       (const int *)w.hi_in, (const int *)w.counts, (const int *)w.hub_start_in,
+                       (const double *)w.hub_part, (const int *)w.u_out_off, loc.pos,
+                       (const double *)R[a], R[b], X[b], (const int *)w.u_gid,
+                       (const double *)w.b_c0, (const int *)w.b_gdone, G, alpha,
+                       w.b_gpart + (size_t)B * G, (const Ctrl *)w.ctrl);
+    hipLaunchKernelGGL(k_batched_final, dim3(G), dim3(kBlock), 0, cs, (const double *)w.b_gpart,
+                       B + F, G, w.b_gdone, w.b_giters, w.b_gdelta, (const Ctrl *)w.ctrl, tol);
+    hipLaunchKernelGGL(k_batched_done, dim3(1), dim3(kBlock), 0, cs, (const int *)w.b_gdone, G,
+                       w.ctrl, max_iter);
+  }
+  hipGraph_t graph = nullptr;
+  hipError_t ce = hipStreamEndCapture(cs, &graph);
+  if (ce != hipSuccess) return fail(PR_EHIP, std::string("graph capture: ") + hipGetErrorString(ce));
+  hipGraphExec_t exec = nullptr;
+  ce = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ce != hipSuccess)
+    return fail(PR_EHIP, std::string("graph instantiate: ") + hipGetErrorString(ce));
+  const int K = std::max(1, std::min(g_tuning.iters_per_sync, kRing - 1));
+  const int replays = (max_iter + 1) / 2;
+  int r = 0;
+  bool done = false;
+  int err = PR_OK;
+  while (r < replays && !done) {
+    hipError_t e1 = hipGraphLaunch(exec, cs);
+    hipError_t e2 = hipMemcpyAsync(&w.host_ctrl[r % kRing], w.ctrl, sizeof(Ctrl),
+                                   hipMemcpyDeviceToHost, cs);
+    hipError_t e3 = hipEventRecord(w.sync_ev[r % kRing], cs);
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+      err = fail(PR_EHIP, "graph replay failed");
+      break;
+    }
+    ++r;
+    const int j = r - K;
+    if (j >= 0) {
+      if (hipEventSynchronize(w.sync_ev[j % kRing]) != hipSuccess) {
+        err = fail(PR_EHIP, "hipEventSynchronize failed");
+        break;
+      }
+      if (w.host_ctrl[j % kRing].done) done = true;
+    }
+  }
+  (void)hipStreamSynchronize(cs);
+  (void)hipGraphExecDestroy(exec);
+  if (err) return err;
+  HIP_TRY(hipEventRecord(w.cap_ev[1], cs));
+  HIP_TRY(hipStreamWaitEvent(s, w.cap_ev[1], 0));
+  const Ctrl &last = w.host_ctrl[(r - 1) % kRing];
+  hipLaunchKernelGGL(k_batched_out, dim3(ub), dim3(kBlock), 0, s, n, (const int *)w.u_gid,
+                     (const int *)w.b_vbase, (const int *)w.b_giters, (const double *)R[0],
+                     (const double *)R[1], (double *const *)w.b_outs);
+  LAUNCH_TRY();
+  std::vector<int> gi(G), gd(G);
+  HIP_TRY(hipMemcpyAsync(gi.data(), w.b_giters, G * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(gd.data(), w.b_gdone, G * sizeof(int), hipMemcpyDeviceToHost, s));
+  timer.stop();
+  HIP_TRY(hipStreamSynchronize(s));
+  bool all = true;
+  for (int g = 0; g < G; ++g) {
+    all = all && gd[g];
+    if (iters_out) iters_out[g] = gi[g];
+  }
+  t_stats.iterations = last.iters;
+  t_stats.converged = all;
+  t_stats.total_ms = timer.ms();
+  return all ? PR_OK : PR_NOT_CONVERGED;
+}
+
 int check_edges(const pr_edges *e, const char *name) {
   if (!e) return PR_OK;
   if (e->count < 0) return fail(PR_EINVAL, std::string(name) + ".count < 0");
@@ -807,6 +1015,22 @@ int pr_ppr(const pr_csr *csr, const double *teleport, int k, double alpha, doubl
     return fail(PR_EINVAL, "n * k too large");
   std::lock_guard<std::mutex> lock(g_mu);
   return run_ppr(csr, teleport, k, alpha, tol, max_iter, ranks_out, iters_out);
+}
+
+int pr_static_batched(const pr_csr *graphs, int num_graphs, double alpha, double tol,
+                      int max_iter, double *const *ranks_out, int32_t *iters_out) {
+  reset_stats();
+  if (!graphs || !ranks_out) return fail(PR_EINVAL, "graphs and ranks_out are required");
+  if (num_graphs <= 0 || num_graphs > kMaxBatchGraphs)
+    return fail(PR_EINVAL, "num_graphs must be in [1, 4096]");
+  int rc;
+  for (int g = 0; g < num_graphs; ++g) {
+    if ((rc = check_csr(&graphs[g], false))) return rc;
+    if (!ranks_out[g]) return fail(PR_EINVAL, "ranks_out[g] is NULL");
+  }
+  if ((rc = check_params(alpha, tol, max_iter))) return rc;
+  std::lock_guard<std::mutex> lock(g_mu);
+  return run_batched(graphs, num_graphs, alpha, tol, max_iter, ranks_out, iters_out);
 }
 
 int pr_weighted(const pr_csr *csr, const double *in_weights, const double *teleport,

@@ -58,7 +58,8 @@ class PrStats(ctypes.Structure):
                 ("reserved", ctypes.c_double * 4)]
 
 
-EXPORTED = ["pr_static", "pr_dfp", "pr_dfp_ex", "pr_ppr", "pr_weighted", "pr_adjoint",
+EXPORTED = ["pr_static", "pr_dfp", "pr_dfp_ex", "pr_ppr", "pr_static_batched", "pr_weighted",
+            "pr_adjoint",
             "pr_validate_csr", "pr_set_tuning",
             "pr_get_tuning", "pr_last_stats", "pr_set_profiling", "pr_set_stream",
             "pr_last_error", "pr_release"]
@@ -83,6 +84,7 @@ def load_library(path: str = SO_PATH):
     lib.pr_dfp_ex.argtypes = [P(PrCsr), P(PrCsr), P(PrEdges), P(PrEdges), vp, d, d, d, d, i, i,
                               vp]
     lib.pr_ppr.argtypes = [P(PrCsr), vp, i, d, d, i, vp, P(ctypes.c_int32)]
+    lib.pr_static_batched.argtypes = [P(PrCsr), i, d, d, i, P(vp), P(ctypes.c_int32)]
     lib.pr_weighted.argtypes = [P(PrCsr), vp, vp, d, d, i, vp]
     lib.pr_adjoint.argtypes = [P(PrCsr), vp, vp, vp, d, d, i, vp, vp, vp]
     lib.pr_validate_csr.argtypes = [P(PrCsr)]
@@ -96,7 +98,8 @@ def load_library(path: str = SO_PATH):
     lib.pr_last_error.restype = ctypes.c_char_p
     lib.pr_release.argtypes = []
     lib.pr_release.restype = None
-    for f in ("pr_static", "pr_dfp", "pr_dfp_ex", "pr_ppr", "pr_weighted", "pr_adjoint",
+    for f in ("pr_static", "pr_dfp", "pr_dfp_ex", "pr_ppr", "pr_static_batched", "pr_weighted",
+              "pr_adjoint",
               "pr_validate_csr", "pr_set_tuning",
               "pr_get_tuning", "pr_last_stats", "pr_set_profiling"):
         getattr(lib, f).restype = ctypes.c_int
@@ -262,6 +265,23 @@ def ppr(g: DeviceGraph, teleport, alpha=ALPHA, tol=TOL, max_iter=MAX_ITERATIONS,
 
 def _ptr(x):
     return None if x is None else x.data_ptr()
+
+
+def static_batched(graphs, alpha=ALPHA, tol=TOL, max_iter=MAX_ITERATIONS, outs=None):
+    """Static PageRank on many graphs in one batched call (pr_static_batched).
+    Returns (Result with ranks = list of [n_g] tensors, iterations per graph)."""
+    torch = _torch()
+    lib = load_library()
+    G = len(graphs)
+    if outs is None:
+        outs = [torch.empty(g.n, dtype=torch.float64, device=g.in_offsets.device) for g in graphs]
+    csrs = (PrCsr * G)(*[g.csr() for g in graphs])
+    ptrs = (ctypes.c_void_p * G)(*[o.data_ptr() for o in outs])
+    its = np.zeros(G, np.int32)
+    _bind_stream(lib, torch)
+    rc = _check(lib.pr_static_batched(csrs, G, alpha, tol, max_iter, ptrs,
+                                      its.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))), lib)
+    return _result(rc, outs), its
 
 
 def weighted(g: DeviceGraph, in_weights, teleport=None, alpha=ALPHA, tol=TOL,

@@ -124,3 +124,11 @@ def test_weighted_adjoint_argument_errors(lib):
     assert lib.pr_adjoint(ctypes.byref(csr2), ctypes.c_void_p(8), ctypes.c_void_p(8),
                           ctypes.c_void_p(8), 0.85, 1e-10, 10, None, None,
                           None) == prhip.PR_EINVAL
+
+
+def test_batched_argument_errors(lib):
+    csr = (prhip.PrCsr * 2)(prhip.PrCsr(4, 4, 8, 8, 8, None), prhip.PrCsr(0, 4, 8, 8, 8, None))
+    outs = (ctypes.c_void_p * 2)(8, 8)
+    assert lib.pr_static_batched(csr, 0, 0.85, 1e-10, 10, outs, None) == prhip.PR_EINVAL
+    assert lib.pr_static_batched(csr, 5000, 0.85, 1e-10, 10, outs, None) == prhip.PR_EINVAL
+    assert lib.pr_static_batched(csr, 2, 0.85, 1e-10, 10, outs, None) == prhip.PR_EINVAL  # n = 0

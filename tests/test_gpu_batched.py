@@ -1,0 +1,76 @@
+"""GPU batched Static PageRank (pr_static_batched): every graph's result is
+bit-identical to pr_static on that graph alone (same tuning), and within
+1e-9 of the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2404_08299_amd import graphgen as gg
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+from paper_2404_08299_amd import prhip  # noqa: E402
+
+
+@pytest.fixture(autouse=True)
+def default_tuning():
+    prhip.set_tuning()
+    yield
+    prhip.set_tuning()
+
+
+def make_batch(count, seed):
+    rng = np.random.default_rng(seed)
+    gs = []
+    for i in range(count):
+        n = int(2 ** rng.uniform(4, 14))
+        ef = float(rng.uniform(2, 16))
+        scale = max(1, int(np.ceil(np.log2(n))))
+        gs.append(gg.rmat_graph(scale, ef, seed=1000 + i, n=n))
+    return gs
+
+
+@pytest.mark.parametrize("tuning", [dict(), dict(relabel=1),
+                                    dict(lane_max_degree=2, wave_max_degree=16,
+                                         expand_lane_max_degree=2, hub_chunk_edges=32,
+                                         relabel=1)])
+def test_batched_equals_per_graph(tuning):
+    prhip.set_tuning(**tuning)
+    gs = make_batch(24, seed=1)
+    dgs = [prhip.DeviceGraph.from_host(g) for g in gs]
+    res, its = prhip.static_batched(dgs)
+    assert res.converged
+    for g, dg, r, it in zip(gs, dgs, res.ranks, its):
+        single = prhip.static(dg)
+        assert single.iterations == it
+        assert torch.equal(single.ranks, r)
+    for g, r in zip(gs[:6], res.ranks[:6]):
+        o = oracle.static(g.n, *g.edges())
+        assert np.abs(r.cpu().numpy() - o.ranks).max() <= 1e-9
+
+
+def test_batched_with_hubs_and_single():
+    k = 5000
+    star = gg.from_edges(k + 1, np.arange(1, k + 1, dtype=np.int32), np.zeros(k, np.int32))
+    gs = [star, gg.rmat_graph(12, 8, seed=3), gg.from_edges(1, [], [])]
+    dgs = [prhip.DeviceGraph.from_host(g) for g in gs]
+    res, its = prhip.static_batched(dgs)
+    for dg, r, it in zip(dgs, res.ranks, its):
+        single = prhip.static(dg)
+        assert single.iterations == it and torch.equal(single.ranks, r)
+    one, its1 = prhip.static_batched(dgs[1:2])
+    assert torch.equal(one.ranks[0], prhip.static(dgs[1]).ranks)
+
+
+@pytest.mark.parametrize("max_iter", [1, 4, 7])
+def test_batched_iteration_cap(max_iter):
+    gs = make_batch(5, seed=2)
+    dgs = [prhip.DeviceGraph.from_host(g) for g in gs]
+    with pytest.warns(RuntimeWarning):
+        res, its = prhip.static_batched(dgs, tol=0.0, max_iter=max_iter)
+    assert res.status == prhip.PR_NOT_CONVERGED and list(its) == [max_iter] * 5
+    for g, r in zip(gs, res.ranks):
+        o = oracle.static(g.n, *g.edges(), tol=0.0, max_iter=max_iter)
+        assert np.abs(r.cpu().numpy() - o.ranks).max() <= 1e-15
