@@ -1,17 +1,25 @@
 #!/usr/bin/env python3
-"""Benchmark: Static vs DF-P PageRank on one MI355X.
+"""Benchmark of the PageRank hot path on one MI355X.
 
-Workload (synthetic, seeded): R-MAT scale 24 (a, b, c, d = 0.57, 0.19, 0.19,
-0.05), edge factor 16, seed 1, duplicates removed, one self-loop per vertex,
-int32 CSR, FP64 ranks, alpha 0.85, tol 1e-10 (L-infinity), at most 500
-iterations. Random batch updates of 1e-7 .. 1e-3 |E| (one per decade, batch
-seed = decade index + 1), 80 % insertions of absent pairs, 20 % deletions of
-existing non-self-loop edges. R^{t-1} is the Static result on G^{t-1}.
+Headline workload (synthetic, seeded): R-MAT scale 24 (a, b, c, d = 0.57,
+0.19, 0.19, 0.05), edge factor 16, seed 1, Graph500-style scrambled IDs,
+duplicates removed, one self-loop per vertex, int32 CSR, FP64 ranks,
+alpha 0.85, tol 1e-10 (L-infinity), at most 500 iterations. Random batch
+updates of 1e-7 .. 1e-3 |E| (one per decade, batch seed = decade index + 1),
+80 % insertions of absent pairs, 20 % deletions of existing non-self-loop
+edges; R^{t-1} is the Static result on G^{t-1}.
 
-One step = pr_static on G^t plus pr_dfp(G^t, batch, R^{t-1}) for the batch
-of that step; consecutive steps cycle through the decades. Inputs are resident
-in HBM before the timed region. Prints one JSON line on stdout; progress goes
-to stderr.
+One step runs every part of the path once:
+  static   pr_static on G^t                         (scale 24)
+  dfp      pr_dfp(G^t, batch, R^{t-1})               (scale 24; decades cycle over steps)
+  ppr      pr_ppr, 64 teleport vectors of 16 seeds   (R-MAT scale 20, edge factor 16)
+  batched  pr_static_batched on 256 R-MAT graphs, n log-uniform in [2^10, 2^20],
+           edge factor uniform in [4, 32], seeds 1000 + i
+  adjoint  pr_weighted + pr_adjoint, weights U(0.1, 1] row-normalised, loss = sum of
+           squared ranks of 1024 random targets      (R-MAT scale 20, edge factor 16)
+Inputs are resident in HBM before the timed region. `value` is the Static
+GTEPS per iteration (m * iterations / call time). Prints one JSON line on
+stdout; progress goes to stderr.
 """
 import argparse
 import hashlib
@@ -19,6 +27,7 @@ import json
 import os
 import sys
 import time
+import warnings
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -28,6 +37,7 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_rank_static_rmat24.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2404_08299_amd", "csrc", f)
                   for f in ("kernels.h", "wave.h")]
+ALL_LEGS = ("static", "dfp", "ppr", "batched", "adjoint")
 
 
 def log(msg):
@@ -85,6 +95,15 @@ def copy_probe(gib=1.0, reps=5):
     return gbs
 
 
+def timed(fn):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = fn()
+    torch.cuda.synchronize()
+    return r, (time.perf_counter() - t0) * 1e3
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,8 +113,15 @@ def main():
     ap.add_argument("--edge-factor", type=float, default=16)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--fractions", default="1e-7,1e-6,1e-5,1e-4,1e-3")
+    ap.add_argument("--legs", default=",".join(ALL_LEGS),
+                    help="comma-separated subset of " + ",".join(ALL_LEGS))
+    ap.add_argument("--aux-scale", type=int, default=20, help="scale of the PPR/adjoint graph")
+    ap.add_argument("--ppr-k", type=int, default=64)
+    ap.add_argument("--batch-graphs", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the untimed comparison runs (single calls vs batched)")
     ap.add_argument("--cpu-iters", type=int, default=2)
     ap.add_argument("--order", default="scrambled", choices=["scrambled", "natural", "degree"],
                     help="vertex numbering of the input: Graph500 scrambled IDs, R-MAT's own "
@@ -123,7 +149,14 @@ def main():
     if args.copy_probe:
         copy_probe()
         return
+    legs = [x for x in args.legs.split(",") if x]
+    for x in legs:
+        if x not in ALL_LEGS:
+            raise SystemExit(f"unknown leg {x}")
+    if "dfp" in legs and "static" not in legs:
+        legs.insert(0, "static")
 
+    # ------------------------------------------------------------ inputs
     fracs = [float(x) for x in args.fractions.split(",")]
     t = time.time()
     g0 = gg.rmat_graph(args.scale, args.edge_factor, seed=args.seed,
@@ -145,6 +178,45 @@ def main():
         del g1
         log(f"batch {f:g}|E|: {b.size} updates ({b.ins_src.size} ins, {b.del_src.size} del), "
             f"m={ms[-1]} ({time.time() - t:.1f} s)")
+
+    aux = {}
+    if "ppr" in legs or "adjoint" in legs:
+        t = time.time()
+        ga = gg.rmat_graph(args.aux_scale, 16, seed=1)
+        aux["g"] = ga
+        aux["dg"] = prhip.DeviceGraph.from_host(ga)
+        if "ppr" in legs:
+            sets = gg.distinct_vertices(ga.n, args.ppr_k, 16, seed=2)
+            T = np.zeros((ga.n, args.ppr_k))
+            for j in range(args.ppr_k):
+                T[sets[j], j] = 1.0 / 16
+            aux["tele"] = torch.from_numpy(T).cuda()
+            aux["ppr_out"] = torch.empty((ga.n, args.ppr_k), dtype=torch.float64, device="cuda")
+        if "adjoint" in legs:
+            dst = np.repeat(np.arange(ga.n, dtype=np.int32), ga.in_degree())
+            src = ga.in_sources
+            w = gg.edge_weights(src, dst, seed=1)
+            W = np.bincount(src, weights=w, minlength=ga.n)
+            aux["P"] = torch.from_numpy(w / W[src]).cuda()
+            aux["s"] = torch.full((ga.n,), 1.0 / ga.n, dtype=torch.float64, device="cuda")
+            tg = np.random.default_rng(2).choice(ga.n, 1024, replace=False)
+            aux["targets"] = torch.from_numpy(tg).cuda()
+            aux["fw_out"] = torch.empty(ga.n, dtype=torch.float64, device="cuda")
+        log(f"R-MAT scale {args.aux_scale}: n={ga.n} m={ga.m} ({time.time() - t:.1f} s)")
+    if "batched" in legs:
+        t = time.time()
+        rng = np.random.default_rng(7)
+        bgs = []
+        for i in range(args.batch_graphs):
+            nb = int(2 ** rng.uniform(10, 20))
+            ef = float(rng.uniform(4, 32))
+            sc = int(np.ceil(np.log2(nb)))
+            bgs.append(prhip.DeviceGraph.from_host(
+                gg.rmat_graph(sc, ef * nb / (1 << sc), seed=1000 + i, n=nb)))
+        aux["bgs"] = bgs
+        aux["bouts"] = [torch.empty(g.n, dtype=torch.float64, device="cuda") for g in bgs]
+        log(f"{len(bgs)} batched graphs: N={sum(g.n for g in bgs)} M={sum(g.m for g in bgs)} "
+            f"({time.time() - t:.1f} s)")
     torch.cuda.synchronize()
 
     # R^{t-1}: Static on G^{t-1} (untimed)
@@ -154,24 +226,57 @@ def main():
     dfp_out = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in fracs]
     rec = {j: {"static_ms": [], "dfp_ms": [], "static_iters": [], "dfp_iters": [],
                "rank_ms": [], "rank_launches": []} for j in range(len(fracs))}
+    other = {"ppr_ms": [], "ppr_iters": [], "batched_ms": [], "batched_iters": [],
+             "fw_ms": [], "fw_iters": [], "adj_ms": [], "adj_iters": []}
 
     def step(s, record):
         j = s % len(fracs)
-        t0 = time.perf_counter()
-        prhip.static(dgs[j], out=static_out[j])
-        t1 = time.perf_counter()
-        st = prhip.last_stats()
-        prhip.dfp(dgs[j], dbs[j], prev, out=dfp_out[j])
-        t2 = time.perf_counter()
-        sd = prhip.last_stats()
-        if record:
-            r = rec[j]
-            r["static_ms"].append((t1 - t0) * 1e3)
-            r["dfp_ms"].append((t2 - t1) * 1e3)
-            r["static_iters"].append(st["iterations"])
-            r["dfp_iters"].append(sd["iterations"])
-            r["rank_ms"].append(st["rank_kernel_ms"])
-            r["rank_launches"].append(st["rank_kernel_launches"])
+        if "static" in legs:
+            t0 = time.perf_counter()
+            prhip.static(dgs[j], out=static_out[j])
+            t1 = time.perf_counter()
+            st = prhip.last_stats()
+            if record:
+                r = rec[j]
+                r["static_ms"].append((t1 - t0) * 1e3)
+                r["static_iters"].append(st["iterations"])
+                r["rank_ms"].append(st["rank_kernel_ms"])
+                r["rank_launches"].append(st["rank_kernel_launches"])
+        if "dfp" in legs:
+            t1 = time.perf_counter()
+            prhip.dfp(dgs[j], dbs[j], prev, out=dfp_out[j])
+            t2 = time.perf_counter()
+            if record:
+                rec[j]["dfp_ms"].append((t2 - t1) * 1e3)
+                rec[j]["dfp_iters"].append(prhip.last_stats()["iterations"])
+        if "ppr" in legs:
+            t0 = time.perf_counter()
+            _, its = prhip.ppr(aux["dg"], aux["tele"], out=aux["ppr_out"])
+            t1 = time.perf_counter()
+            if record:
+                other["ppr_ms"].append((t1 - t0) * 1e3)
+                other["ppr_iters"].append(int(its.max()))
+        if "batched" in legs:
+            t0 = time.perf_counter()
+            _, its = prhip.static_batched(aux["bgs"], outs=aux["bouts"])
+            t1 = time.perf_counter()
+            if record:
+                other["batched_ms"].append((t1 - t0) * 1e3)
+                other["batched_iters"].append(int(its.max()))
+        if "adjoint" in legs:
+            t0 = time.perf_counter()
+            fr = prhip.weighted(aux["dg"], aux["P"], aux["s"], out=aux["fw_out"])
+            t1 = time.perf_counter()
+            grad = torch.zeros_like(fr.ranks)
+            grad[aux["targets"]] = 2 * fr.ranks[aux["targets"]]
+            t2 = time.perf_counter()
+            prhip.adjoint(aux["dg"], aux["P"], fr.ranks, grad)
+            t3 = time.perf_counter()
+            if record:
+                other["fw_ms"].append((t1 - t0) * 1e3)
+                other["fw_iters"].append(fr.iterations)
+                other["adj_ms"].append((t3 - t2) * 1e3)
+                other["adj_iters"].append(prhip.last_stats()["iterations"])
 
     for s in range(args.warmup):
         step(s, False)
@@ -187,56 +292,109 @@ def main():
     ms_per_step = (T1 - T0) / args.steps * 1e3
     log(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step")
 
-    edges_iter = 0.0
-    bytes_iter = 0.0
-    t_static = 0.0
-    rank_ms = 0.0
-    rank_bytes = 0.0
-    per_batch = []
-    for j, f in enumerate(fracs):
-        r = rec[j]
-        if not r["static_ms"]:
-            continue
-        for k in range(len(r["static_ms"])):
-            edges_iter += ms[j] * r["static_iters"][k]
-            bytes_iter += algorithmic_bytes(n, ms[j]) * r["static_iters"][k]
-            t_static += r["static_ms"][k] / 1e3
-            rank_ms += r["rank_ms"][k]
-            rank_bytes += algorithmic_bytes(n, ms[j]) * r["rank_launches"][k]
-        sm = float(np.mean(r["static_ms"]))
-        dm = float(np.mean(r["dfp_ms"]))
-        per_batch.append({"fraction": f, "batch_size": sizes[j], "static_ms": round(sm, 3),
-                          "dfp_ms": round(dm, 3), "dfp_speedup": round(sm / dm, 2),
-                          "static_iters": r["static_iters"][0], "dfp_iters": r["dfp_iters"][0]})
-    gteps = edges_iter / t_static / 1e9
-    gbs = bytes_iter / t_static / 1e9
-    launches = sum(sum(rec[j]["rank_launches"]) for j in rec)
-    avg_rank_ms = rank_ms / max(1, launches)
-    achieved = rank_bytes / (rank_ms / 1e3) / 1e9 if rank_ms > 0 else None
-    traffic = read_traffic()
-    log(f"Static {gteps:.2f} GTEPS, {gbs:.0f} GB/s algorithmic (whole call); rank kernel "
-        f"{avg_rank_ms * 1e3:.1f} us avg over {launches} launches, {achieved:.0f} GB/s")
+    out = {"metric": METRIC, "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "value": None}
+    out["config"] = {"workload": f"rmat{args.scale}_ef{int(args.edge_factor)}_static_and_dfp",
+                     "vertex_order": args.order, "n": n, "m": g0.m, "scale": args.scale,
+                     "edge_factor": args.edge_factor, "seed": args.seed,
+                     "batch_fractions": fracs, "alpha": 0.85, "tol": 1e-10,
+                     "frontier_tol": 1e-6, "prune_tol": 1e-6, "max_iter": 500, "legs": legs,
+                     "tuning": prhip.get_tuning()}
 
-    accuracy = None
-    if not args.no_accuracy:
-        accuracy = []
+    if "static" in legs:
+        edges_iter = bytes_iter = t_static = rank_ms = rank_bytes = 0.0
+        launches = 0
+        per_batch = []
+        for j, f in enumerate(fracs):
+            r = rec[j]
+            if not r["static_ms"]:
+                continue
+            for k in range(len(r["static_ms"])):
+                edges_iter += ms[j] * r["static_iters"][k]
+                bytes_iter += algorithmic_bytes(n, ms[j]) * r["static_iters"][k]
+                t_static += r["static_ms"][k] / 1e3
+                rank_ms += r["rank_ms"][k]
+                rank_bytes += algorithmic_bytes(n, ms[j]) * r["rank_launches"][k]
+                launches += r["rank_launches"][k]
+            item = {"fraction": f, "batch_size": sizes[j],
+                    "static_ms": round(float(np.mean(r["static_ms"])), 3),
+                    "static_iters": r["static_iters"][0]}
+            if r["dfp_ms"]:
+                dm = float(np.mean(r["dfp_ms"]))
+                item.update(dfp_ms=round(dm, 3), dfp_iters=r["dfp_iters"][0],
+                            dfp_speedup=round(item["static_ms"] / dm, 2))
+            per_batch.append(item)
+        gteps = edges_iter / t_static / 1e9
+        gbs = bytes_iter / t_static / 1e9
+        avg_rank_ms = rank_ms / max(1, launches)
+        achieved = rank_bytes / (rank_ms / 1e3) / 1e9 if rank_ms > 0 else None
+        log(f"Static {gteps:.2f} GTEPS, {gbs:.0f} GB/s algorithmic (whole call); rank kernel "
+            f"{avg_rank_ms * 1e3:.1f} us avg over {launches} launches, {achieved:.0f} GB/s")
+        out["value"] = round(gteps, 3)
+        out["static_gbs_per_iteration"] = round(gbs, 1)
+        out["batches"] = per_batch
+        out["roofline"] = {"bound": "hbm", "kernel": "k_rank_static",
+                           "achieved": round(achieved, 1) if achieved else None,
+                           "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+                           "traffic": read_traffic(),
+                           "avg_launch_us": round(avg_rank_ms * 1e3, 2),
+                           "algorithmic_bytes_per_launch": algorithmic_bytes(n, g0.m)}
+
+    if "ppr" in legs:
+        ga = aux["g"]
+        pm = float(np.mean(other["ppr_ms"]))
+        out["ppr"] = {"workload": f"rmat{args.aux_scale}_ef16_k{args.ppr_k}", "n": ga.n,
+                      "m": ga.m, "k": args.ppr_k, "ms": round(pm, 3),
+                      "iters": other["ppr_iters"][0],
+                      "vector_gteps": round(ga.m * args.ppr_k * other["ppr_iters"][0] / pm / 1e6, 2)}
+    if "batched" in legs:
+        bm = float(np.mean(other["batched_ms"]))
+        out["batched"] = {"graphs": len(aux["bgs"]), "n": sum(g.n for g in aux["bgs"]),
+                          "m": sum(g.m for g in aux["bgs"]), "ms": round(bm, 3),
+                          "max_iters": other["batched_iters"][0]}
+    if "adjoint" in legs:
+        out["adjoint"] = {"workload": f"weighted_rmat{args.aux_scale}_ef16_1024_targets",
+                          "forward_ms": round(float(np.mean(other["fw_ms"])), 3),
+                          "forward_iters": other["fw_iters"][0],
+                          "adjoint_ms": round(float(np.mean(other["adj_ms"])), 3),
+                          "adjoint_iters": other["adj_iters"][0]}
+
+    # ------------------------------------------------------------ untimed comparisons
+    if not args.no_compare:
+        if "batched" in legs:
+            _, t_single = timed(lambda: [prhip.static(g) for g in aux["bgs"]])
+            ref, _ = prhip.static_batched(aux["bgs"], outs=aux["bouts"])
+            same = all(torch.equal(prhip.static(g).ranks, r)
+                       for g, r in zip(aux["bgs"][:8], ref.ranks[:8]))
+            out["batched"].update(sum_of_single_calls_ms=round(t_single, 3),
+                                  speedup=round(t_single / out["batched"]["ms"], 2),
+                                  bitwise_equal_to_single_calls=same)
+        if "ppr" in legs:
+            _, t_single = timed(lambda: [prhip.static(aux["dg"]) for _ in range(args.ppr_k)])
+            out["ppr"].update(k_static_solves_ms=round(t_single, 3),
+                              speedup_vs_k_static=round(t_single / out["ppr"]["ms"], 2))
+        log(f"comparisons: batched {out.get('batched')}, ppr {out.get('ppr')}")
+
+    if not args.no_accuracy and "dfp" in legs:
+        acc = []
         ref = torch.empty(n, dtype=torch.float64, device="cuda")
         for j, f in enumerate(fracs):
             # reference Static run at a vanishing tolerance, capped at 500 iterations
-            with np.errstate(all="ignore"):
-                import warnings
-                with warnings.catch_warnings():
-                    warnings.simplefilter("ignore")
-                    prhip.static(dgs[j], tol=0.0, max_iter=500, out=ref)
+            with warnings.catch_warnings():
+                warnings.simplefilter("ignore")
+                prhip.static(dgs[j], tol=0.0, max_iter=500, out=ref)
             d_dfp = (dfp_out[j] - ref).abs()
             d_st = (static_out[j] - ref).abs()
-            accuracy.append({
-                "fraction": f,
-                "dfp_vs_static_linf": float((dfp_out[j] - static_out[j]).abs().max()),
-                "dfp_linf": float(d_dfp.max()), "dfp_l1": float(d_dfp.sum()),
-                "static_linf": float(d_st.max()), "static_l1": float(d_st.sum()),
-                "max_rank": float(ref.max())})
-            log(f"accuracy {f:g}: {accuracy[-1]}")
+            acc.append({"fraction": f,
+                        "dfp_vs_static_linf": float((dfp_out[j] - static_out[j]).abs().max()),
+                        "dfp_linf": float(d_dfp.max()), "dfp_l1": float(d_dfp.sum()),
+                        "static_linf": float(d_st.max()), "static_l1": float(d_st.sum()),
+                        "max_rank": float(ref.max())})
+        out["accuracy"] = acc
+        log(f"accuracy: max DF-P vs Static L-inf {max(a['dfp_vs_static_linf'] for a in acc):.3e}")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -250,38 +408,7 @@ def main():
                          f"the scale-{args.scale} graph G^(t-1), iteration loop only "
                          f"({sec:.1f} s)"}
         log(f"cpu baseline {cpu}")
-
-    out = {
-        "metric": METRIC,
-        "value": round(gteps, 3),
-        "unit": "GTEPS",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": f"rmat{args.scale}_ef{int(args.edge_factor)}_static_and_dfp",
-                   "vertex_order": args.order,
-                   "n": n, "m": g0.m, "scale": args.scale, "edge_factor": args.edge_factor,
-                   "seed": args.seed, "batch_fractions": fracs, "alpha": 0.85, "tol": 1e-10,
-                   "frontier_tol": 1e-6, "prune_tol": 1e-6, "max_iter": 500,
-                   "tuning": prhip.get_tuning()},
-        "static_gbs_per_iteration": round(gbs, 1),
-        "batches": per_batch,
-        "roofline": {"bound": "hbm", "kernel": "k_rank_static",
-                     "achieved": round(achieved, 1) if achieved else None,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-                     "traffic": traffic,
-                     "avg_launch_us": round(avg_rank_ms * 1e3, 2),
-                     "algorithmic_bytes_per_launch": algorithmic_bytes(n, g0.m)},
-        "accuracy": accuracy,
-        "cpu_baseline": cpu,
-    }
+    out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 
