@@ -17,6 +17,10 @@ One step runs every part of the path once:
            edge factor uniform in [4, 32], seeds 1000 + i
   adjoint  pr_weighted + pr_adjoint, weights U(0.1, 1] row-normalised, loss = sum of
            squared ranks of 1024 random targets      (R-MAT scale 20, edge factor 16)
+After the timed steps (a chain, so not part of a step), unless --temporal-batches 0:
+  temporal preferential-attachment stream, 2M vertices, 40M events: 90 % loaded, the
+           rest in 100 batches (10 % deletions); DF-P chained batch to batch, beside
+           pr_static on every G^t, errors against a tight Static every 10th batch.
 Inputs are resident in HBM before the timed region. `value` is the Static
 GTEPS per iteration (m * iterations / call time). Prints one JSON line on
 stdout; progress goes to stderr.
@@ -104,6 +108,56 @@ def timed(fn):
     return r, (time.perf_counter() - t0) * 1e3
 
 
+def temporal_leg(args, gg, prhip, torch, np):
+    """DF-P chained over the batches of a preferential-attachment temporal
+    stream, beside Static on every G^t (each call timed alone, inputs resident
+    in HBM). Errors against a Static run at tol 0 every 10th batch."""
+    t = time.time()
+    g0, steps = gg.temporal_stream(args.temporal_n, args.temporal_events, seed=1,
+                                   batches=args.temporal_batches)
+    dgs, dbs, sizes = [], [], []
+    for b, g in steps:
+        dgs.append(prhip.DeviceGraph.from_host(g))
+        dbs.append(prhip.DeviceBatch.from_host(b))
+        sizes.append((int(b.ins_src.size), int(b.del_src.size)))
+    log(f"temporal: n={g0.n} m0={g0.m} m_end={dgs[-1].m}, {len(dgs)} batches "
+        f"({time.time() - t:.1f} s)")
+    prev = prhip.static(prhip.DeviceGraph.from_host(g0)).ranks
+    outs = [torch.empty(g0.n, dtype=torch.float64, device="cuda") for _ in range(2)]
+    st_out = torch.empty(g0.n, dtype=torch.float64, device="cuda")
+    ref = torch.empty(g0.n, dtype=torch.float64, device="cuda")
+    dfp_ms, st_ms, dfp_it, errs = [], [], [], []
+    for k, (dg, db) in enumerate(zip(dgs, dbs)):
+        out = outs[k & 1]
+        _, ms_d = timed(lambda: prhip.dfp(dg, db, prev, out=out))
+        dfp_it.append(prhip.last_stats()["iterations"])
+        _, ms_s = timed(lambda: prhip.static(dg, out=st_out))
+        dfp_ms.append(ms_d)
+        st_ms.append(ms_s)
+        prev = out
+        if k % 10 == 9 or k == len(dgs) - 1:
+            with warnings.catch_warnings():
+                warnings.simplefilter("ignore")
+                prhip.static(dg, tol=0.0, max_iter=500, out=ref)
+            d = (out - ref).abs()
+            errs.append({"batch": k + 1, "dfp_linf": float(d.max()), "dfp_l1": float(d.sum()),
+                         "static_linf": float((st_out - ref).abs().max()),
+                         "max_rank": float(ref.max())})
+    gm = lambda a: float(np.exp(np.mean(np.log(a))))
+    res = {"workload": f"pa_temporal_n{args.temporal_n}_ev{args.temporal_events}"
+                       f"_b{args.temporal_batches}",
+           "n": g0.n, "m0": g0.m, "m_end": dgs[-1].m,
+           "mean_insertions": round(float(np.mean([a for a, _ in sizes])), 1),
+           "deletions_per_batch": sizes[0][1],
+           "dfp_ms_geomean": round(gm(dfp_ms), 3), "static_ms_geomean": round(gm(st_ms), 3),
+           "dfp_speedup_geomean": round(gm(np.array(st_ms) / np.array(dfp_ms)), 2),
+           "dfp_iters_mean": round(float(np.mean(dfp_it)), 2),
+           "max_dfp_linf": max(e["dfp_linf"] for e in errs), "errors": errs}
+    log(f"temporal: DF-P {res['dfp_ms_geomean']} ms vs Static {res['static_ms_geomean']} ms "
+        f"per batch (geomean), max DF-P L-inf {res['max_dfp_linf']:.2e}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,7 +176,10 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the untimed comparison runs (single calls vs batched)")
-    ap.add_argument("--cpu-iters", type=int, default=2)
+    ap.add_argument("--cpu-iters", type=int, default=8)
+    ap.add_argument("--temporal-batches", type=int, default=100)
+    ap.add_argument("--temporal-n", type=int, default=2_000_000)
+    ap.add_argument("--temporal-events", type=int, default=40_000_000)
     ap.add_argument("--order", default="scrambled", choices=["scrambled", "natural", "degree"],
                     help="vertex numbering of the input: Graph500 scrambled IDs, R-MAT's own "
                          "IDs, or relabelled by descending out-degree")
@@ -395,6 +452,9 @@ def main():
                         "max_rank": float(ref.max())})
         out["accuracy"] = acc
         log(f"accuracy: max DF-P vs Static L-inf {max(a['dfp_vs_static_linf'] for a in acc):.3e}")
+
+    if args.temporal_batches > 0:
+        out["temporal"] = temporal_leg(args, gg, prhip, torch, np)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -72,6 +72,9 @@ def _load():
                                              ctypes.c_uint64, _I32P]
         lib.gg_distinct_vertices.restype = None
         lib.gg_uniform.argtypes = [ctypes.c_int64, ctypes.c_uint64, _F64P]
+        lib.gg_new_pairs.argtypes = [ctypes.c_int32, _I32P, _I32P, ctypes.c_int64, _I32P, _I32P,
+                                     _I32P, _I32P]
+        lib.gg_new_pairs.restype = ctypes.c_int64
         lib.gg_uniform.restype = None
         _lib = lib
     return _lib
@@ -223,6 +226,51 @@ def pa_temporal_events(n: int, n_events: int, seed: int, gamma: float = 2.1,
     if k != n_events:
         raise ValueError("gg_pa_temporal failed")
     return src, dst
+
+
+def temporal_batch(g: Graph, ev_src, ev_dst, n_del: int, seed: int) -> Batch:
+    """One batch of a temporal stream against the current graph g, as set
+    differences: the events' unique non-self-loop pairs absent from g are the
+    insertions; n_del existing non-self-loop edges of g, drawn uniformly without
+    replacement, are the deletions."""
+    ev_src = np.ascontiguousarray(ev_src, dtype=np.int32)
+    ev_dst = np.ascontiguousarray(ev_dst, dtype=np.int32)
+    is_ = np.empty(ev_src.size, np.int32)
+    id_ = np.empty(ev_src.size, np.int32)
+    k = _load().gg_new_pairs(g.n, _p32(g.out_offsets), _p32(g.out_targets), ev_src.size,
+                             _p32(ev_src), _p32(ev_dst), _p32(is_), _p32(id_))
+    ds = np.empty(n_del, np.int32)
+    dd = np.empty(n_del, np.int32)
+    z = np.empty(0, np.int32)
+    rc = _load().gg_random_batch(g.n, _p32(g.out_offsets), _p32(g.out_targets), n_del, 0, seed,
+                                 _p32(ds), _p32(dd), _p32(z), _p32(z))
+    if rc != 0:
+        raise ValueError("graph too small for the requested deletions")
+    return Batch(ds, dd, is_[:k].copy(), id_[:k].copy())
+
+
+def temporal_stream(n: int, n_events: int, seed: int, load_frac: float = 0.9,
+                    batches: int = 100, del_frac: float = 0.1):
+    """Preferential-attachment temporal graph: the first load_frac of the
+    events form G^0; the rest are cut into `batches` consecutive insertion
+    batches, each with round(del_frac * its event count) deletions of random
+    existing edges. Returns (G^0, generator of (batch, G^t)); each batch is
+    normalised against the graph it updates (batch seed = seed * 1000 + t)."""
+    src, dst = pa_temporal_events(n, n_events, seed)
+    n0 = int(round(load_frac * n_events))
+    g0 = from_edges(n, src[:n0], dst[:n0])
+    cuts = np.linspace(n0, n_events, batches + 1).round().astype(np.int64)
+
+    def steps():
+        g = g0
+        for t in range(batches):
+            a, b = cuts[t], cuts[t + 1]
+            bt = temporal_batch(g, src[a:b], dst[a:b], int(round(del_frac * (b - a))),
+                                seed=seed * 1000 + t)
+            g = apply_batch(g, bt)
+            yield bt, g
+
+    return g0, steps()
 
 
 def edge_weights(src, dst, seed: int, lo: float = 0.1, hi: float = 1.0) -> np.ndarray:

@@ -326,6 +326,27 @@ int gg_random_batch(int32_t n, const int32_t *out_offsets, const int32_t *out_ta
   return 0;
 }
 
+// Insertions of a temporal batch as a set difference: the unique pairs
+// (src[i], dst[i]) with src != dst that are not edges of the graph, in order
+// of first occurrence. Returns their number (written to ins_src/ins_dst).
+int64_t gg_new_pairs(int32_t n, const int32_t *out_offsets, const int32_t *out_targets,
+                     int64_t k, const int32_t *src, const int32_t *dst, int32_t *ins_src,
+                     int32_t *ins_dst) {
+  std::unordered_set<uint64_t> seen;
+  seen.reserve((size_t)k * 2 + 16);
+  int64_t c = 0;
+  for (int64_t i = 0; i < k; ++i) {
+    const int32_t u = src[i], v = dst[i];
+    if (u < 0 || v < 0 || u >= n || v >= n || u == v) continue;
+    if (has_edge(out_offsets, out_targets, u, v)) continue;
+    if (!seen.insert(pack((uint32_t)u, (uint32_t)v)).second) continue;
+    ins_src[c] = u;
+    ins_dst[c] = v;
+    ++c;
+  }
+  return c;
+}
+
 // Apply a batch to one CSR view (rows keyed by `row`, entries `col`): removes
 // each (row, col) deletion and inserts each insertion, keeping rows sorted.
 // The batch must be normalised (deletions present, insertions absent).

@@ -104,6 +104,31 @@ def test_pa_temporal():
     assert indeg.max() > 100 * np.median(indeg)
 
 
+def test_temporal_stream_batches_are_set_differences():
+    n, ev = 5000, 100000
+    src, dst = gg.pa_temporal_events(n, ev, seed=4)
+    g0, steps = gg.temporal_stream(n, ev, seed=4, batches=5)
+    assert np.array_equal(g0.out_offsets, gg.from_edges(n, src[:90000], dst[:90000]).out_offsets)
+    g = g0
+    for t, (b, g1) in enumerate(steps):
+        have = set(zip(*g.edges()))
+        ins = list(zip(b.ins_src.tolist(), b.ins_dst.tolist()))
+        dels = list(zip(b.del_src.tolist(), b.del_dst.tolist()))
+        # insertions: the unique new non-self-loop pairs of the batch's events
+        a, c = 90000 + 2000 * t, 90000 + 2000 * (t + 1)
+        want = []
+        for e in zip(src[a:c].tolist(), dst[a:c].tolist()):
+            if e[0] != e[1] and e not in have and e not in want:
+                want.append(e)
+        assert ins == want
+        assert len(dels) == 200 and len(set(dels)) == 200
+        assert all(e in have and e[0] != e[1] for e in dels)
+        new = set(zip(*g1.edges()))
+        assert new == (have - set(dels)) | set(ins)
+        check_canonical(g1)
+        g = g1
+
+
 def test_edge_weights_and_sets():
     g = gg.rmat_graph(8, 8, seed=1)
     s, d = g.edges()
