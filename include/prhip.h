@@ -220,6 +220,17 @@ int pr_validate_csr(const pr_csr *csr);
  *                      grouping of the sources, built inside each call):
  *                      1 on, 0 off, -1 automatic (on when n >= 2^20). Rows and
  *                      their summation order are unchanged.
+ *   xcd_split_degree   0: off. Otherwise in-degree >= this (and above
+ *                      lane_max_degree) selects the die-split class, which
+ *                      replaces the wavefront class above this degree and
+ *                      the split class: the sources are cut into 8
+ *                      contiguous ranges of about equal out-edge count, a
+ *                      row's sources in range x are summed (in chunks of
+ *                      hub_chunk_edges, one wavefront each) by workgroups on
+ *                      accelerator die x, whose L2 then holds only that
+ *                      range's contributions, and the partial sums are added
+ *                      in range and chunk order. With relabel on, the
+ *                      grouping is done inside each range. Must be 0 or >= 2.
  */
 typedef struct pr_tuning {
   int32_t lane_max_degree;
@@ -229,11 +240,12 @@ typedef struct pr_tuning {
   int32_t hub_chunk_edges;
   int32_t grid_blocks;
   int32_t relabel;
-  int32_t reserved;
+  int32_t xcd_split_degree;
 } pr_tuning;
 
 /* Set (NULL = defaults) or read the process-wide tuning. PR_EINVAL if a
- * field is out of range (degrees < 0, lane > wave, iters_per_sync < 1). */
+ * field is out of range (degrees < 0, lane > wave, iters_per_sync < 1,
+ * xcd_split_degree == 1). */
 int pr_set_tuning(const pr_tuning *t);
 int pr_get_tuning(pr_tuning *t);
 

@@ -98,15 +98,16 @@ __global__ __launch_bounds__(kBlock) void k_rank_batched(
     const double *__restrict__ R, double *__restrict__ Rn, double *__restrict__ Xn,
     const int *__restrict__ hi, const int *__restrict__ counts,
     const int *__restrict__ hub_start, const int *__restrict__ chunk_hub,
-    double *__restrict__ hub_part, int CH, int n, int t1, const int *__restrict__ gid,
-    const double *__restrict__ C0g, const int *__restrict__ gdone, int G, double alpha,
-    double *__restrict__ gpart, const Ctrl *__restrict__ ctrl) {
+    double *__restrict__ hub_part, int CH, int n, int t1, const int4 *__restrict__ xitems,
+    const int *__restrict__ xoff, const int *__restrict__ gid, const double *__restrict__ C0g,
+    const int *__restrict__ gdone, int G, double alpha, double *__restrict__ gpart,
+    const Ctrl *__restrict__ ctrl) {
   if (ctrl->done) return;
   extern __shared__ unsigned long long s_gmax[];
   clear_table(s_gmax, G);
   const BatchOut out{out_off, pos, gid, C0g, gdone, R, Rn, Xn, alpha, s_gmax};
   rank_update<false>(in_off, in_src, nullptr, X, hi, counts, hub_start, chunk_hub, hub_part, CH,
-                     n, t1, out, nullptr);
+                     n, t1, xitems, xoff, out, nullptr);
   flush_table(s_gmax, G, gpart + (size_t)blockIdx.x * G);
 }
 

@@ -49,6 +49,7 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kPartTile = 1024;  // vertices per partition block
 constexpr int kFinalBlock = 1024;
 constexpr int kHubFinalizeBlocks = 64;
+constexpr int kXcds = 8;  // accelerator dies; workgroup b is dispatched to die b mod 8
 
 // Device-side control block of one call.
 struct Ctrl {
@@ -251,6 +252,137 @@ __global__ __launch_bounds__(kFinalBlock) void k_hub_plan(const int *__restrict_
   }
 }
 
+// ------------------------------------------------------------ XCD split plan
+// Each accelerator die (XCD) has its own L2. The gather side is cut into
+// kXcds contiguous source ranges of about equal out-edge count, and every
+// split-class row into the kXcds segments of its (ascending) sources that fall
+// in each range. Segment x of every row is summed by the workgroups on die x,
+// so each L2 caches only its own range of the contributions. Segments are cut
+// into chunks of at most CH edges; the chunk partials of a row are laid out
+// row-major (range 0 first, chunks in order), so hub_finalize adds them in one
+// fixed order.
+//
+// Range starts of graph g, rs[g][0..kXcds] (first = the graph's first
+// vertex, last = its end): the first vertex whose out-edge prefix reaches
+// x * m_g / kXcds, rounded to partition tiles of the graph's own numbering.
+// Graph g spans vertices vb[g] .. vb[g+1] (vb = null: one graph of n vertices),
+// so a graph of a batch is cut exactly as it is when run alone.
+__global__ void k_xcd_ranges(const int *__restrict__ goff, const int *__restrict__ vb, int n,
+                             int *__restrict__ rs) {
+  const int g = blockIdx.x, x = threadIdx.x;
+  if (x > kXcds) return;
+  const int v0 = vb ? vb[g] : 0, v1 = vb ? vb[g + 1] : n;
+  const int ng = v1 - v0;
+  int v = 0;
+  if (x == kXcds) {
+    v = ng;
+  } else if (x > 0) {
+    const long long e0 = goff[v0];
+    const long long target = e0 + (long long)(goff[v1] - e0) * x / kXcds;
+    int lo = v0, hi = v1;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if ((long long)goff[mid] < target) lo = mid + 1;
+      else hi = mid;
+    }
+    v = min(ng, (lo - v0 + kPartTile / 2) / kPartTile * kPartTile);
+  }
+  rs[g * (kXcds + 1) + x] = v0 + v;
+}
+
+// First position p in [lo, hi) with idx[p] >= key (idx ascending there).
+__device__ __forceinline__ int lower_bound_idx(const int *__restrict__ idx, int lo, int hi,
+                                               int key) {
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (idx[mid] < key) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// End of segment x of row [r0, r1) given the end of segment x - 1.
+__device__ __forceinline__ int xseg_end(const int *__restrict__ idx, const int *__restrict__ rs,
+                                        int prev, int r1, int x) {
+  return x == kXcds - 1 ? r1 : lower_bound_idx(idx, prev, r1, rs[x + 1]);
+}
+
+// mat[x][i] = chunks of segment x of split row i, mat[kXcds][i] = the row's
+// total, for i < nb (rows i >= n2 count 0, so nb may be any bound >= n2 + 1).
+// gid (batches): graph of each row, whose ranges are rs[gid[v]].
+__global__ __launch_bounds__(kBlock) void k_xsplit_count(
+    const int *__restrict__ off, const int *__restrict__ idx, const int *__restrict__ hi,
+    const int *__restrict__ counts, int slot, const int *__restrict__ rs_all,
+    const int *__restrict__ gid, int CH, int nb, int *__restrict__ mat) {
+  const int n1 = counts[slot], n2 = counts[slot + 1];
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < nb; i += gridDim.x * kBlock) {
+    int tot = 0;
+    if (i < n2) {
+      const int v = hi[n1 + i];
+      const int *rs = rs_all + (gid ? gid[v] : 0) * (kXcds + 1);
+      const int r1 = off[v + 1];
+      int prev = off[v];
+      for (int x = 0; x < kXcds; ++x) {
+        const int e = xseg_end(idx, rs, prev, r1, x);
+        const int c = (e - prev + CH - 1) / CH;
+        mat[(size_t)x * nb + i] = c;
+        tot += c;
+        prev = e;
+      }
+    } else {
+      for (int x = 0; x < kXcds; ++x) mat[(size_t)x * nb + i] = 0;
+    }
+    mat[(size_t)kXcds * nb + i] = tot;
+  }
+}
+
+// After the exclusive scans of the rows of mat (totals in tot[0..kXcds]):
+// work item {partial index, e0, e1, vertex} of every chunk, list x at
+// xoff[x] .. xoff[x + 1]; hub_start[i] = first partial of split row i.
+__global__ __launch_bounds__(kBlock) void k_xsplit_fill(
+    const int *__restrict__ off, const int *__restrict__ idx, const int *__restrict__ hi,
+    int *__restrict__ counts, int slot, int chunk_slot, const int *__restrict__ rs_all,
+    const int *__restrict__ gid, int CH, int nb, const int *__restrict__ mat,
+    const int *__restrict__ tot, int *__restrict__ xoff, int *__restrict__ hub_start,
+    int4 *__restrict__ items) {
+  const int n1 = counts[slot], n2 = counts[slot + 1];
+  int base[kXcds];
+  int run = 0;
+#pragma unroll
+  for (int x = 0; x < kXcds; ++x) {
+    base[x] = run;
+    run += tot[x];
+  }
+  if (blockIdx.x == 0 && threadIdx.x <= kXcds) {
+    int a = 0;
+    for (int x = 0; x < (int)threadIdx.x; ++x) a += tot[x];
+    xoff[threadIdx.x] = a;
+    if (threadIdx.x == 0) {
+      hub_start[n2] = tot[kXcds];
+      counts[chunk_slot] = tot[kXcds];
+    }
+  }
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n2; i += gridDim.x * kBlock) {
+    const int v = hi[n1 + i];
+    const int *rs = rs_all + (gid ? gid[v] : 0) * (kXcds + 1);
+    const int r1 = off[v + 1];
+    int p = mat[(size_t)kXcds * nb + i];
+    hub_start[i] = p;
+    int prev = off[v];
+    for (int x = 0; x < kXcds; ++x) {
+      const int e = xseg_end(idx, rs, prev, r1, x);
+      const int cnt = (e - prev + CH - 1) / CH;
+      int4 *dst = items + base[x] + mat[(size_t)x * nb + i];
+      for (int k = 0; k < cnt; ++k) {
+        const int e0 = prev + k * CH;
+        dst[k] = make_int4(p + k, e0, min(e0 + CH, e), v);
+      }
+      p += cnt;
+      prev = e;
+    }
+  }
+}
+
 // ------------------------------------------------------------ Static init
 // R = r0 (1/n in Alg. 1), X = R / |out(v)| (or R when weighted). With
 // `init` the start vector is given (Naive-dynamic, Sec. 3.4.1); it may alias R.
@@ -396,8 +528,8 @@ __device__ __forceinline__ void rank_update(
     const double *__restrict__ wt, const double *__restrict__ X, const int *__restrict__ hi,
     const int *__restrict__ counts,
     const int *__restrict__ hub_start, const int *__restrict__ chunk_hub,
-    double *__restrict__ hub_part, int CH, int n, int t1, const Out &out,
-    double *__restrict__ partials) {
+    double *__restrict__ hub_part, int CH, int n, int t1, const int4 *__restrict__ xitems,
+    const int *__restrict__ xoff, const Out &out, double *__restrict__ partials) {
   __shared__ double lds[kWavesPerBlock];
   __shared__ int s_v[kBlock], s_e0[kBlock], s_e1[kBlock], s_c[kBlock];
   __shared__ int s_wcnt[kWavesPerBlock];
@@ -406,10 +538,29 @@ __device__ __forceinline__ void rank_update(
   const int B = gridDim.x;
   double dmax = 0.0;
 
-  // 1) split class: this workgroup's chunks are blockIdx + k*B; in each
+  // 1a) split class cut by source range (xitems set): list x is summed by the
+  // workgroups on die x, one wavefront per chunk. With fewer than kXcds
+  // workgroups, workgroup b takes lists b, b + B, ...
+  if (xitems) {
+    const int x0 = B >= kXcds ? (int)blockIdx.x % kXcds : (int)blockIdx.x;
+    const int xstep = B >= kXcds ? kXcds : B;
+    const int loc = B >= kXcds ? (int)blockIdx.x / kXcds : 0;
+    const int nloc = B >= kXcds ? (B - 1 - x0) / kXcds + 1 : 1;
+    for (int x = x0; x < kXcds; x += xstep) {
+      const int end = xoff[x + 1];
+      for (int j = xoff[x] + loc * kWavesPerBlock + wid; j < end; j += nloc * kWavesPerBlock) {
+        const int4 it = xitems[j];  // {partial, e0, e1, vertex}; uniform in the wavefront
+        if (!out.active(it.w)) continue;
+        double c = strided_sum<kWave, WEIGHTED>(it.y, it.z, lane, in_src, wt, X);
+        c = wave_sum(c);
+        if (lane == 0) hub_part[it.x] = c;
+      }
+    }
+  }
+  // 1b) split class: this workgroup's chunks are blockIdx + k*B; in each
   // round thread tid checks one of them, and the selected ones are summed by
   // the whole workgroup.
-  for (long long base = blockIdx.x; base < nch; base += (long long)kBlock * B) {
+  for (long long base = blockIdx.x; !xitems && base < nch; base += (long long)kBlock * B) {
     const long long cl = base + (long long)tid * B;
     const int c = cl < nch ? (int)cl : 0;
     bool f = false;
@@ -510,12 +661,13 @@ __global__ __launch_bounds__(kBlock) void k_rank_static(
     double *__restrict__ Rn, double *__restrict__ Xn, const int *__restrict__ hi,
     const int *__restrict__ counts, const int *__restrict__ hub_start,
     const int *__restrict__ chunk_hub, double *__restrict__ hub_part, int CH, int n, int t1,
-    double C0, double alpha, const double *__restrict__ tele, double tscale,
-    double *__restrict__ partials, const Ctrl *__restrict__ ctrl) {
+    const int4 *__restrict__ xitems, const int *__restrict__ xoff, double C0, double alpha,
+    const double *__restrict__ tele, double tscale, double *__restrict__ partials,
+    const Ctrl *__restrict__ ctrl) {
   if (ctrl->done) return;
   const StaticOut out{out_off, pos, R, Rn, Xn, C0, alpha, tele, tscale, WEIGHTED};
   rank_update<WEIGHTED>(in_off, in_src, wt, X, hi, counts, hub_start, chunk_hub, hub_part, CH, n,
-                        t1, out, partials);
+                        t1, xitems, xoff, out, partials);
 }
 
 template <bool PRUNE>
@@ -525,12 +677,12 @@ __global__ __launch_bounds__(kBlock) void k_rank_dfp(
     double *__restrict__ T, uint8_t *dV, uint8_t *dN, uint8_t *cv, const int *__restrict__ hi,
     const int *__restrict__ counts, const int *__restrict__ hub_start,
     const int *__restrict__ chunk_hub, double *__restrict__ hub_part, int CH, int n, int t1,
-    double C0, double alpha, double tau_f, double tau_p, double *__restrict__ partials,
-    const Ctrl *__restrict__ ctrl) {
+    const int4 *__restrict__ xitems, const int *__restrict__ xoff, double C0, double alpha,
+    double tau_f, double tau_p, double *__restrict__ partials, const Ctrl *__restrict__ ctrl) {
   if (ctrl->done) return;
   const DynOut<PRUNE> out{out_off, R, T, dV, dN, cv, C0, alpha, tau_f, tau_p};
   rank_update<false>(in_off, in_src, nullptr, X, hi, counts, hub_start, chunk_hub, hub_part, CH, n,
-                     t1, out, partials);
+                     t1, xitems, xoff, out, partials);
 }
 
 // Split-class vertices: add the chunk partials in chunk order and finish.
@@ -667,7 +819,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_expand(
     const uint8_t *dN, uint8_t *cv,
     const int *__restrict__ hi_out, const int *__restrict__ counts,
     const int *__restrict__ hub_start, const int *__restrict__ chunk_hub, int CH, int n,
-    int t_exp, const Ctrl *__restrict__ ctrl, int it) {
+    int t_exp, const int *__restrict__ rt, const Ctrl *__restrict__ ctrl, int it) {
   const int done = ctrl->done;
   if (done && ctrl->iters < it + 1) return;  // converged before this iteration
   const bool expand = !done;
@@ -675,7 +827,50 @@ __global__ __launch_bounds__(kBlock) void k_apply_expand(
   __shared__ int s_wcnt[kWavesPerBlock];
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
   const int B = gridDim.x;
-  if (expand) {
+  if (expand && rt) {
+    // Wavefront and split classes cut by target range: the workgroups on die
+    // x mark only targets in [rt[x], rt[x+1]), found by binary search in the
+    // ascending out-row, so the flags they read and write stay in that die's
+    // L2. Candidates: the wavefront-class rows, then the split-class chunks.
+    const int n1 = counts[kOutWave], nch = counts[kOutChunks];
+    const long long ncand = (long long)n1 + nch;
+    const int x0 = B >= kXcds ? (int)blockIdx.x % kXcds : (int)blockIdx.x;
+    const int xstep = B >= kXcds ? kXcds : B;
+    const int loc = B >= kXcds ? (int)blockIdx.x / kXcds : 0;
+    const int nloc = B >= kXcds ? (B - 1 - x0) / kXcds + 1 : 1;
+    const long long Wx = (long long)nloc * kWavesPerBlock;
+    const int gwx = loc * kWavesPerBlock + wid;
+    for (int x = x0; x < kXcds; x += xstep) {
+      const int lo_t = rt[x], hi_t = rt[x + 1];
+      for (long long k0 = 0; gwx + k0 * Wx < ncand; k0 += kWave) {
+        const long long ii = gwx + (k0 + lane) * Wx;
+        bool f = false;
+        int a = 0, b = 0;
+        if (ii < n1) {
+          const int u = hi_out[ii];
+          f = dN[u] != 0;
+          a = out_off[u];
+          b = out_off[u + 1];
+        } else if (ii < ncand) {
+          const int c = (int)(ii - n1);
+          const int i = chunk_hub[c];
+          const int u = hi_out[n1 + i];
+          f = dN[u] != 0;
+          a = out_off[u] + (c - hub_start[i]) * CH;
+          b = min(a + CH, out_off[u + 1]);
+        }
+        unsigned long long mask = __ballot(f);
+        while (mask) {
+          const int j = __ffsll(mask) - 1;
+          mask &= mask - 1;
+          const int aa = __shfl(a, j), bb = __shfl(b, j);
+          const int s0 = lower_bound_idx(out_tgt, aa, bb, lo_t);
+          const int s1 = lower_bound_idx(out_tgt, s0, bb, hi_t);
+          for (int e = s0 + lane; e < s1; e += kWave) mark(dV, ld_nt(out_tgt + e));
+        }
+      }
+    }
+  } else if (expand) {
     const int n1 = counts[kOutWave], nch = counts[kOutChunks];
     // split class: chunks blockIdx + k*B, one per thread and round
     for (long long base = blockIdx.x; base < nch; base += (long long)kBlock * B) {
@@ -831,17 +1026,35 @@ __global__ __launch_bounds__(kBlock) void k_group_count(const int *__restrict__ 
 
 // base[g][tile]: exclusive prefix of group g's counts over the tiles;
 // totals[g]: group sizes (the group's first position is their prefix sum).
+// With source ranges rs (tile-aligned, see k_xcd_ranges) the grouping is done
+// inside each range, so range x keeps the positions rs[x] .. rs[x+1]: the
+// contributions a die gathers stay contiguous. rs = null: one range.
 __global__ __launch_bounds__(kBlock) void k_group_scatter(const int *__restrict__ out_off, int n,
                                                           const int *__restrict__ base,
                                                           const int *__restrict__ totals,
-                                                          int ntiles, int *__restrict__ newid) {
+                                                          int ntiles, const int *__restrict__ rs,
+                                                          int *__restrict__ newid) {
   __shared__ int s_base[kGroups];
   __shared__ int s_cnt[kWavesPerBlock][kGroups];
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   if (threadIdx.x < kGroups) {
-    int gb = 0;
-    for (int g = 0; g < (int)threadIdx.x; ++g) gb += totals[g];
-    s_base[threadIdx.x] = gb + base[(size_t)threadIdx.x * ntiles + blockIdx.x];
+    // tiles [t0, t1) form this tile's range; prefix(g, t) = members of group
+    // g in tiles before t (totals[g] at t = ntiles)
+    int r0 = 0, t0 = 0, t1 = ntiles;
+    if (rs) {
+      int x = 0;
+      while (x < kXcds - 1 && rs[x + 1] <= (int)blockIdx.x * kPartTile) ++x;
+      r0 = rs[x];
+      t0 = rs[x] / kPartTile;
+      t1 = (rs[x + 1] + kPartTile - 1) / kPartTile;
+    }
+    auto prefix = [&](int g, int t) {
+      return t < ntiles ? base[(size_t)g * ntiles + t] : totals[g];
+    };
+    int gb = r0;
+    for (int g = 0; g < (int)threadIdx.x; ++g) gb += prefix(g, t1) - prefix(g, t0);
+    s_base[threadIdx.x] =
+        gb + base[(size_t)threadIdx.x * ntiles + blockIdx.x] - prefix(threadIdx.x, t0);
   }
   for (int k = 0; k < kPartTile / kBlock; ++k) {
     const int v = blockIdx.x * kPartTile + k * kBlock + threadIdx.x;

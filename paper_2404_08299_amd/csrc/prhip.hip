@@ -49,6 +49,7 @@ pr_tuning default_tuning() {
   t.hub_chunk_edges = 4096;
   t.grid_blocks = 0;
   t.relabel = -1;
+  t.xcd_split_degree = 257;
   return t;
 }
 pr_tuning g_tuning = default_tuning();
@@ -71,6 +72,13 @@ struct Workspace {
   int *tile_counts = nullptr;  // [kGroups][ntiles]
   int *counts = nullptr;       // [kNumCounts]
   int *group_totals = nullptr; // [kGroups]
+  // die-split class: source range starts, scan totals, list offsets (small),
+  // per-row chunk counts [kXcds + 1][nb] and the work items
+  int *xrs = nullptr, *xtot = nullptr, *xoff = nullptr;
+  int *xrt = nullptr;  // target ranges of the die-split expand (DF-P)
+  int *xmat = nullptr;
+  int4 *xitems = nullptr;
+  size_t cap_xmat = 0, cap_xitems = 0;
   double *partials = nullptr;  // [cap_partials]
   // personalised PageRank: 4 [n][K] buffers (R, R', X, X'), chunk partials,
   // per-workgroup per-vector maxima, per-vector state
@@ -85,6 +93,7 @@ struct Workspace {
   double *b_c0 = nullptr, *b_gdelta = nullptr, *b_gpart = nullptr;
   BatchDesc *b_desc = nullptr;
   double **b_outs = nullptr;
+  int *b_xrs = nullptr;  // [G][kXcds + 1] die-split ranges per graph
   size_t cap_b_g = 0, cap_b_part = 0;
   hipStream_t cap_stream = nullptr;
   hipEvent_t cap_ev[2] = {};
@@ -150,7 +159,8 @@ void free_batch(Workspace &w) {
   (void)hipFree(w.u_gid); (void)hipFree(w.b_vbase); (void)hipFree(w.b_ebase);
   (void)hipFree(w.b_gdone); (void)hipFree(w.b_giters); (void)hipFree(w.b_c0);
   (void)hipFree(w.b_gdelta); (void)hipFree(w.b_gpart); (void)hipFree(w.b_desc);
-  (void)hipFree(w.b_outs);
+  (void)hipFree(w.b_outs); (void)hipFree(w.b_xrs);
+  w.b_xrs = nullptr;
   w.u_in_off = w.u_in_src = w.u_out_off = w.u_gid = nullptr;
   w.b_vbase = w.b_ebase = w.b_gdone = w.b_giters = nullptr;
   w.b_c0 = w.b_gdelta = w.b_gpart = nullptr;
@@ -159,8 +169,17 @@ void free_batch(Workspace &w) {
   w.cap_u_n = w.cap_u_m = w.cap_b_g = w.cap_b_part = 0;
 }
 
+void free_xsplit(Workspace &w) {
+  (void)hipFree(w.xmat); (void)hipFree(w.xitems);
+  w.xmat = nullptr;
+  w.xitems = nullptr;
+  w.cap_xmat = w.cap_xitems = 0;
+}
+
 void free_ws(Workspace &w) {
   free_arrays(w);
+  free_xsplit(w);
+  (void)hipFree(w.xrs);
   free_ppr(w);
   free_batch(w);
   if (w.cap_stream) (void)hipStreamDestroy(w.cap_stream);
@@ -194,6 +213,40 @@ int grid_blocks(const Workspace &w, const pr_tuning &tn, K kernel) {
   return per_cu * std::max(1, w.num_cus);
 }
 
+// Die-split class under the current tuning: lower in-degree bound (0 = off),
+// a bound on its row count (+1) and on its work items.
+int xsplit_min_degree(const pr_tuning &tn) {
+  if (tn.xcd_split_degree <= 0) return 0;
+  return std::max(tn.xcd_split_degree, tn.lane_max_degree + 1);
+}
+size_t xsplit_rows_bound(size_t n, size_t m) {
+  const int T = xsplit_min_degree(g_tuning);
+  return T ? std::min(n, m / (size_t)T) + 1 : 0;
+}
+size_t xsplit_items_bound(size_t n, size_t m, int CH) {
+  const size_t nb = xsplit_rows_bound(n, m);
+  return nb ? kXcds * nb + m / (size_t)std::max(CH, 1) + kXcds : 0;
+}
+
+int xsplit_ws(Workspace &w, size_t nb, size_t items) {
+  const size_t need_mat = (kXcds + 1) * nb;
+  if (need_mat > w.cap_xmat || items > w.cap_xitems) {
+    const size_t a = std::max(need_mat, w.cap_xmat), b = std::max(items, w.cap_xitems);
+    free_xsplit(w);
+    hipError_t e = hipSuccess;
+    if ((e = hipMalloc(&w.xmat, a * sizeof(int))) != hipSuccess ||
+        (e = hipMalloc(&w.xitems, b * sizeof(int4))) != hipSuccess) {
+      (void)hipGetLastError();
+      free_xsplit(w);
+      return fail(e == hipErrorOutOfMemory ? PR_ENOMEM : PR_EHIP,
+                  std::string("die-split workspace allocation: ") + hipGetErrorString(e));
+    }
+    w.cap_xmat = a;
+    w.cap_xitems = b;
+  }
+  return PR_OK;
+}
+
 // Workspace for n vertices, m edges and chunk size CH (grow-only, per device).
 int get_ws(size_t n, size_t m, int CH, int B, Workspace **out) {
   int dev = 0;
@@ -205,6 +258,10 @@ int get_ws(size_t n, size_t m, int CH, int B, Workspace **out) {
     HIP_TRY(hipMalloc(&w.ctrl, sizeof(Ctrl)));
     HIP_TRY(hipMalloc(&w.counts, kNumCounts * sizeof(int)));
     HIP_TRY(hipMalloc(&w.group_totals, kGroups * sizeof(int)));
+    HIP_TRY(hipMalloc(&w.xrs, 4 * 16 * sizeof(int)));
+    w.xtot = w.xrs + 16;
+    w.xoff = w.xrs + 32;
+    w.xrt = w.xrs + 48;
     HIP_TRY(hipHostMalloc(&w.host_ctrl, kRing * sizeof(Ctrl), hipHostMallocDefault));
     HIP_TRY(hipHostMalloc(&w.host_counts, kNumCounts * sizeof(int), hipHostMallocDefault));
     HIP_TRY(hipDeviceGetAttribute(&w.num_cus, hipDeviceAttributeMultiprocessorCount, dev));
@@ -212,8 +269,9 @@ int get_ws(size_t n, size_t m, int CH, int B, Workspace **out) {
   }
   if (B <= 0) B = 32 * std::max(1, w.num_cus);  // bound on any occupancy-derived grid
   // chunks of the split class: sum over its vertices of ceil(deg / CH)
-  // <= m / CH + (number of split vertices) <= m / CH + n
-  const size_t need_chunks = m / (size_t)CH + n + 1;
+  // <= m / CH + (number of split vertices) <= m / CH + n; die-split rows have
+  // up to kXcds segments each
+  const size_t need_chunks = std::max(m / (size_t)CH + n + 1, xsplit_items_bound(n, m, CH));
   const size_t need_partials = (size_t)B + kHubFinalizeBlocks + 16;
   if (n > w.cap_n || m > w.cap_m || need_chunks > w.cap_chunks ||
       need_partials > w.cap_partials) {
@@ -282,8 +340,32 @@ int check_params(double alpha, double tol, int max_iter) {
 
 // Alg. 4 on an offsets array: class lists into `hi`, class sizes into
 // counts[slot], counts[slot + 1]; then the chunk plan of the split class.
-int partition(Workspace &w, const int *off, int n, int t1, int t2, int CH, int *hi, int slot,
-              int chunk_slot, int *hub_start, int *chunk_hub, hipStream_t s) {
+// Work lists of the die-split class (null items: the class is off).
+struct XPlan {
+  const int4 *items = nullptr;
+  const int *off = nullptr;
+};
+
+// Source ranges of the die split (w.xrs), balanced by the gather-side
+// degrees goff.
+int xcd_ranges(Workspace &w, const int *goff, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_xcd_ranges, dim3(1), dim3(64), 0, s, goff, (const int *)nullptr, n,
+                     w.xrs);
+  LAUNCH_TRY();
+  return PR_OK;
+}
+
+// Degree classes of the rows `off` (Alg. 4 with three classes) and the plan of
+// the top class. With `xidx` (the rows' original, ascending indices; needs
+// the ranges in w.xrs) the top class is the die-split class of rows with
+// degree >= xsplit_min_degree; otherwise rows above t2, cut into chunks.
+int partition(Workspace &w, const int *off, int n, int m, int t1, int t2, int CH, int *hi,
+              int slot, int chunk_slot, int *hub_start, int *chunk_hub, hipStream_t s,
+              const int *xidx = nullptr, XPlan *xp = nullptr, const int *xrs = nullptr,
+              const int *gid = nullptr) {
+  if (!xrs) xrs = w.xrs;
+  const int T = xidx ? xsplit_min_degree(g_tuning) : 0;
+  if (T) t2 = T - 1;
   const int nt = (int)ntiles_for(n);
   hipLaunchKernelGGL(k_part_count, dim3(nt), dim3(kBlock), 0, s, off, n, t1, t2, w.tile_counts,
                      nt);
@@ -291,9 +373,26 @@ int partition(Workspace &w, const int *off, int n, int t1, int t2, int CH, int *
                      w.counts + slot);
   hipLaunchKernelGGL(k_part_scatter, dim3(nt), dim3(kBlock), 0, s, off, n, t1, t2,
                      w.tile_counts, nt, (const int *)(w.counts + slot), hi);
-  hipLaunchKernelGGL(k_hub_plan, dim3(1), dim3(kFinalBlock), 0, s, off, (const int *)hi, w.counts,
-                     slot, chunk_slot, CH, hub_start, chunk_hub);
+  if (!T) {
+    hipLaunchKernelGGL(k_hub_plan, dim3(1), dim3(kFinalBlock), 0, s, off, (const int *)hi,
+                       w.counts, slot, chunk_slot, CH, hub_start, chunk_hub);
+    LAUNCH_TRY();
+    if (xp) *xp = XPlan{};
+    return PR_OK;
+  }
+  const size_t nb = xsplit_rows_bound((size_t)n, (size_t)m);
+  int rc = xsplit_ws(w, nb, xsplit_items_bound((size_t)n, (size_t)m, CH));
+  if (rc) return rc;
+  const int gb = (int)std::min<size_t>((nb + kBlock - 1) / kBlock, 16 * std::max(1, w.num_cus));
+  hipLaunchKernelGGL(k_xsplit_count, dim3(gb), dim3(kBlock), 0, s, off, xidx, (const int *)hi,
+                     (const int *)w.counts, slot, xrs, gid, CH, (int)nb, w.xmat);
+  hipLaunchKernelGGL(k_scan_rows, dim3(kXcds + 1), dim3(kFinalBlock), 0, s, w.xmat, (int)nb,
+                     w.xtot);
+  hipLaunchKernelGGL(k_xsplit_fill, dim3(gb), dim3(kBlock), 0, s, off, xidx, (const int *)hi,
+                     w.counts, slot, chunk_slot, xrs, gid, CH, (int)nb,
+                     (const int *)w.xmat, (const int *)w.xtot, w.xoff, hub_start, w.xitems);
   LAUNCH_TRY();
+  if (xp) *xp = XPlan{w.xitems, w.xoff};
   return PR_OK;
 }
 
@@ -306,7 +405,8 @@ struct Locality {
   const int *src;
 };
 int locality(Workspace &w, int n, int m, const int *group_off, const int *idx,
-             const pr_tuning &tn, bool allowed, hipStream_t s, Locality *out) {
+             const pr_tuning &tn, bool allowed, hipStream_t s, Locality *out,
+             const int *rs = nullptr) {
   const bool on = allowed && (tn.relabel > 0 || (tn.relabel < 0 && n >= (1 << 20)));
   if (!on) {
     *out = Locality{nullptr, idx};
@@ -318,7 +418,7 @@ int locality(Workspace &w, int n, int m, const int *group_off, const int *idx,
   hipLaunchKernelGGL(k_scan_rows, dim3(kGroups), dim3(kFinalBlock), 0, s, w.tile_counts, nt,
                      w.group_totals);
   hipLaunchKernelGGL(k_group_scatter, dim3(nt), dim3(kBlock), 0, s, group_off, n,
-                     (const int *)w.tile_counts, (const int *)w.group_totals, nt, w.newid);
+                     (const int *)w.tile_counts, (const int *)w.group_totals, nt, rs, w.newid);
   const int mb = std::min((m + kBlock - 1) / kBlock, 8 * std::max(1, w.num_cus) * 4);
   hipLaunchKernelGGL(k_map_sources, dim3(mb), dim3(kBlock), 0, s, idx, m, (const int *)w.newid,
                      w.src_p);
@@ -432,11 +532,17 @@ int run_pull(const PullProblem &P, double alpha, double tol, int max_iter, doubl
   const int np = B + kHubFinalizeBlocks;
   CallTimer timer(w, s);
   hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, s, w.ctrl);
-  rc = partition(w, P.row_off, n, tn.lane_max_degree, tn.wave_max_degree, tn.hub_chunk_edges,
-                 w.hi_in, kInWave, kInChunks, w.hub_start_in, w.chunk_hub_in, s);
+  const bool xs = xsplit_min_degree(tn) > 0;
+  if (xs && (rc = xcd_ranges(w, P.group_off, n, s))) return rc;
+  XPlan xp;
+  rc = partition(w, P.row_off, n, P.m, tn.lane_max_degree, tn.wave_max_degree,
+                 tn.hub_chunk_edges, w.hi_in, kInWave, kInChunks, w.hub_start_in,
+                 w.chunk_hub_in, s, xs ? P.row_idx : nullptr, &xp);
   if (rc) return rc;
   Locality loc;
-  if ((rc = locality(w, n, P.m, P.group_off, P.row_idx, tn, P.relabel, s, &loc))) return rc;
+  if ((rc = locality(w, n, P.m, P.group_off, P.row_idx, tn, P.relabel, s, &loc,
+                     xs ? w.xrs : nullptr)))
+    return rc;
   // R[0] is the caller's output vector; with `init` (which may alias it) the
   // start vector is copied into it.
   double *R[2] = {ranks_out, w.R1};
@@ -453,14 +559,15 @@ int run_pull(const PullProblem &P, double alpha, double tol, int max_iter, doubl
                          P.w, P.deg_off, loc.pos, (const double *)X[a], (const double *)R[a],
                          R[b], X[b], (const int *)w.hi_in, (const int *)w.counts,
                          (const int *)w.hub_start_in, (const int *)w.chunk_hub_in, w.hub_part, CH,
-                         n, t1, C0, alpha, P.tele, P.tscale, w.partials, (const Ctrl *)w.ctrl);
+                         n, t1, xp.items, xp.off, C0, alpha, P.tele, P.tscale, w.partials,
+                         (const Ctrl *)w.ctrl);
     else
       hipLaunchKernelGGL(k_rank_static<false>, dim3(B), dim3(kBlock), 0, s, P.row_off, loc.src,
                          (const double *)nullptr, P.deg_off, loc.pos, (const double *)X[a],
                          (const double *)R[a], R[b], X[b], (const int *)w.hi_in,
                          (const int *)w.counts, (const int *)w.hub_start_in,
-                         (const int *)w.chunk_hub_in, w.hub_part, CH, n, t1, C0, alpha, P.tele,
-                         P.tscale, w.partials, (const Ctrl *)w.ctrl);
+                         (const int *)w.chunk_hub_in, w.hub_part, CH, n, t1, xp.items, xp.off,
+                         C0, alpha, P.tele, P.tscale, w.partials, (const Ctrl *)w.ctrl);
     if (prof) HIP_TRY(hipEventRecord(after, s));
     hipLaunchKernelGGL(k_hub_finalize_static, dim3(kHubFinalizeBlocks), dim3(kBlock), 0, s,
                        (const int *)w.hi_in, (const int *)w.counts, (const int *)w.hub_start_in,
@@ -519,16 +626,28 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
   double *R = ranks_out;
   const int t1 = tn.lane_max_degree, t_exp = tn.expand_lane_max_degree, CH = tn.hub_chunk_edges;
   hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, s, w.ctrl);
+  const bool xs = xsplit_min_degree(tn) > 0;
+  if (xs && (rc = xcd_ranges(w, g->out_offsets, n, s))) return rc;
+  if (xs) {
+    // marks land in proportion to in-degree: target ranges balanced by it
+    hipLaunchKernelGGL(k_xcd_ranges, dim3(1), dim3(64), 0, s, g->in_offsets,
+                       (const int *)nullptr, n, w.xrt);
+    LAUNCH_TRY();
+  }
   Locality loc;
-  if ((rc = locality(w, n, g->m, g->out_offsets, g->in_sources, tn, true, s, &loc))) return rc;
+  if ((rc = locality(w, n, g->m, g->out_offsets, g->in_sources, tn, true, s, &loc,
+                     xs ? w.xrs : nullptr)))
+    return rc;
   double *X = w.X0;
   hipLaunchKernelGGL(k_dfp_init, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n,
                      g->out_offsets, loc.pos, prev, R, X, dV, dN, cv);
   LAUNCH_TRY();
-  rc = partition(w, g->in_offsets, n, t1, tn.wave_max_degree, CH, w.hi_in, kInWave, kInChunks,
-                 w.hub_start_in, w.chunk_hub_in, s);
+  XPlan xp;
+  rc = partition(w, g->in_offsets, n, g->m, t1, tn.wave_max_degree, CH, w.hi_in, kInWave,
+                 kInChunks, w.hub_start_in, w.chunk_hub_in, s, xs ? g->in_sources : nullptr,
+                 &xp);
   if (rc) return rc;
-  rc = partition(w, g->out_offsets, n, t_exp, tn.wave_max_degree, CH, w.hi_out, kOutWave,
+  rc = partition(w, g->out_offsets, n, g->m, t_exp, tn.wave_max_degree, CH, w.hi_out, kOutWave,
                  kOutChunks, w.hub_start_out, w.chunk_hub_out, s);
   if (rc) return rc;
   const int nd = del ? del->count : 0, ni = ins ? ins->count : 0;
@@ -544,7 +663,7 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
                        (const uint8_t *)dN, cv,
                        (const int *)w.hi_out, (const int *)w.counts,
                        (const int *)w.hub_start_out, (const int *)w.chunk_hub_out, CH, n, t_exp,
-                       (const Ctrl *)w.ctrl, it);
+                       xs ? (const int *)w.xrt : nullptr, (const Ctrl *)w.ctrl, it);
   };
   // initial expandAffected (Alg. 2, after initialAffected)
   apply_expand(-1);
@@ -562,7 +681,8 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
                          dN, cv,
                          (const int *)w.hi_in, (const int *)w.counts,
                          (const int *)w.hub_start_in, (const int *)w.chunk_hub_in, w.hub_part, CH,
-                         n, t1, C0, alpha, tau_f, tau_p, w.partials, (const Ctrl *)w.ctrl);
+                         n, t1, xp.items, xp.off, C0, alpha, tau_f, tau_p, w.partials,
+                         (const Ctrl *)w.ctrl);
       if (prof) HIP_TRY(hipEventRecord(after, s));
       hipLaunchKernelGGL(k_hub_finalize_dfp<true>, dim3(kHubFinalizeBlocks), dim3(kBlock), 0, s,
                          (const int *)w.hi_in, (const int *)w.counts, (const int *)w.hub_start_in,
@@ -574,7 +694,8 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
                          dN, cv,
                          (const int *)w.hi_in, (const int *)w.counts,
                          (const int *)w.hub_start_in, (const int *)w.chunk_hub_in, w.hub_part, CH,
-                         n, t1, C0, alpha, tau_f, tau_p, w.partials, (const Ctrl *)w.ctrl);
+                         n, t1, xp.items, xp.off, C0, alpha, tau_f, tau_p, w.partials,
+                         (const Ctrl *)w.ctrl);
       if (prof) HIP_TRY(hipEventRecord(after, s));
       hipLaunchKernelGGL(k_hub_finalize_dfp<false>, dim3(kHubFinalizeBlocks), dim3(kBlock), 0, s,
                          (const int *)w.hi_in, (const int *)w.counts, (const int *)w.hub_start_in,
@@ -652,7 +773,7 @@ int run_ppr(const pr_csr *g, const double *teleport, int K, double alpha, double
   double *Xb[2] = {w.ppr_buf + 2 * nk, w.ppr_buf + 3 * nk};
   hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, s, w.ctrl);
   // rows longer than kPprChunk form the split class (class 1 of Alg. 4 empty)
-  rc = partition(w, g->in_offsets, n, kPprChunk, kPprChunk, kPprChunk, w.hi_in, kInWave,
+  rc = partition(w, g->in_offsets, n, g->m, kPprChunk, kPprChunk, kPprChunk, w.hi_in, kInWave,
                  kInChunks, w.hub_start_in, w.chunk_hub_in, s);
   if (rc) return rc;
   Locality loc;
@@ -794,7 +915,8 @@ int batch_ws(Workspace &w, size_t N, size_t M, size_t G, size_t part_rows) {
         (e = hipMalloc(&w.b_gdelta, gg * sizeof(double))) != hipSuccess ||
         (e = hipMalloc(&w.b_gpart, pp * sizeof(double))) != hipSuccess ||
         (e = hipMalloc(&w.b_desc, gg * sizeof(BatchDesc))) != hipSuccess ||
-        (e = hipMalloc(&w.b_outs, gg * sizeof(double *))) != hipSuccess) {
+        (e = hipMalloc(&w.b_outs, gg * sizeof(double *))) != hipSuccess ||
+        (e = hipMalloc(&w.b_xrs, gg * (kXcds + 1) * sizeof(int))) != hipSuccess) {
       (void)hipGetLastError();
       free_batch(w);
       return fail(e == hipErrorOutOfMemory ? PR_ENOMEM : PR_EHIP,
@@ -856,8 +978,19 @@ int run_batched(const pr_csr *graphs, int G, double alpha, double tol, int max_i
                      (const int *)w.b_vbase, (const int *)w.b_ebase, G, n, m, w.u_in_off,
                      w.u_in_src, w.u_out_off, w.u_gid);
   LAUNCH_TRY();
-  rc = partition(w, w.u_in_off, n, tn.lane_max_degree, tn.wave_max_degree, tn.hub_chunk_edges,
-                 w.hi_in, kInWave, kInChunks, w.hub_start_in, w.chunk_hub_in, s);
+  // die-split ranges per graph (each graph is cut as when run alone, so the
+  // summation order and the result match pr_static on it bit for bit)
+  const bool xs = xsplit_min_degree(tn) > 0;
+  if (xs) {
+    hipLaunchKernelGGL(k_xcd_ranges, dim3(G), dim3(64), 0, s, (const int *)w.u_out_off,
+                       (const int *)w.b_vbase, n, w.b_xrs);
+    LAUNCH_TRY();
+  }
+  XPlan xp;
+  rc = partition(w, w.u_in_off, n, m, tn.lane_max_degree, tn.wave_max_degree,
+                 tn.hub_chunk_edges, w.hi_in, kInWave, kInChunks, w.hub_start_in,
+                 w.chunk_hub_in, s, xs ? w.u_in_src : nullptr, &xp, w.b_xrs,
+                 (const int *)w.u_gid);
   if (rc) return rc;
   Locality loc;
   if ((rc = locality(w, n, m, w.u_out_off, w.u_in_src, tn, true, s, &loc))) return rc;
@@ -880,7 +1013,8 @@ int run_batched(const pr_csr *graphs, int G, double alpha, double tol, int max_i
                        loc.src, (const int *)w.u_out_off, loc.pos, (const double *)X[a],
                        (const double *)R[a], R[b], X[b], (const int *)w.hi_in,
                        (const int *)w.counts, (const int *)w.hub_start_in,
-                       (const int *)w.chunk_hub_in, w.hub_part, CH, n, t1, (const int *)w.u_gid,
+                       (const int *)w.chunk_hub_in, w.hub_part, CH, n, t1, xp.items, xp.off,
+                       (const int *)w.u_gid,
                        (const double *)w.b_c0, (const int *)w.b_gdone, G, alpha, w.b_gpart,
                        (const Ctrl *)w.ctrl);
     hipLaunchKernelGGL(k_hub_finalize_batched, dim3(F), dim3(kBlock), shm, cs,
@@ -1122,7 +1256,8 @@ int pr_set_tuning(const pr_tuning *t) {
   if (t->lane_max_degree < 0 || t->wave_max_degree < t->lane_max_degree ||
       t->expand_lane_max_degree < 0 || t->expand_lane_max_degree > t->wave_max_degree ||
       t->iters_per_sync < 1 || t->iters_per_sync >= kRing || t->hub_chunk_edges < 0 ||
-      t->grid_blocks < 0 || t->grid_blocks > (1 << 20) || t->relabel < -1 || t->relabel > 1)
+      t->grid_blocks < 0 || t->grid_blocks > (1 << 20) || t->relabel < -1 || t->relabel > 1 ||
+      t->xcd_split_degree < 0 || t->xcd_split_degree == 1)
     return fail(PR_EINVAL, "tuning field out of range");
   g_tuning = *t;
   if (g_tuning.hub_chunk_edges == 0) g_tuning.hub_chunk_edges = 4096;

@@ -77,12 +77,16 @@ def test_tuning_validation(lib):
                 prhip.PrTuning(1, 5, 9, 1, 4096, 0),    # expand lane > wave
                 prhip.PrTuning(1, 5, 3, 1, -1, 0),      # chunk < 0
                 prhip.PrTuning(1, 5, 3, 1, 64, -2),     # grid < 0
-                prhip.PrTuning(1, 5, 3, 1, 64, 0, 2)]:  # relabel not in {-1, 0, 1}
+                prhip.PrTuning(1, 5, 3, 1, 64, 0, 2),   # relabel not in {-1, 0, 1}
+                prhip.PrTuning(1, 5, 3, 1, 64, 0, 0, -1),  # die-split degree < 0
+                prhip.PrTuning(1, 5, 3, 1, 64, 0, 0, 1)]:  # die-split degree 1
         assert lib.pr_set_tuning(ctypes.byref(bad)) == prhip.PR_EINVAL
-    good = prhip.PrTuning(4, 64, 8, 3, 0, 100, 1)
+    assert default["xcd_split_degree"] == 257
+    good = prhip.PrTuning(4, 64, 8, 3, 0, 100, 1, 2)
     assert lib.pr_set_tuning(ctypes.byref(good)) == 0
     got = prhip.get_tuning()
     assert got["wave_max_degree"] == 64 and got["hub_chunk_edges"] == 4096 and got["grid_blocks"] == 100
+    assert got["xcd_split_degree"] == 2
     prhip.set_tuning(hub_chunk_edges=128)
     assert prhip.get_tuning()["hub_chunk_edges"] == 128
     with pytest.raises(KeyError):

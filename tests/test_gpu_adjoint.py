@@ -44,7 +44,13 @@ def cu(a):
                                                   (11, 1, dict(lane_max_degree=2,
                                                                wave_max_degree=16,
                                                                expand_lane_max_degree=2,
-                                                               hub_chunk_edges=32))])
+                                                               hub_chunk_edges=32,
+                                                               xcd_split_degree=0)),
+                                                  (11, 1, dict(xcd_split_degree=3,
+                                                               hub_chunk_edges=4)),
+                                                  (12, 0, dict(xcd_split_degree=2,
+                                                               lane_max_degree=1,
+                                                               grid_blocks=9))])
 def test_weighted_forward_vs_oracle(scale, relabel, tuning):
     prhip.set_tuning(relabel=relabel, **tuning)
     g, src, dst, w, P = weighted_graph(scale, seed=scale)
@@ -76,9 +82,9 @@ def test_weighted_unit_weights_equal_static():
     assert np.abs(r - st).max() <= 1e-14
 
 
-@pytest.mark.parametrize("relabel", [0, 1])
-def test_adjoint_vs_oracle_and_dense(relabel):
-    prhip.set_tuning(relabel=relabel)
+@pytest.mark.parametrize("relabel,xsplit", [(0, 257), (1, 257), (1, 2), (0, 3)])
+def test_adjoint_vs_oracle_and_dense(relabel, xsplit):
+    prhip.set_tuning(relabel=relabel, xcd_split_degree=xsplit)
     g, src, dst, w, P = weighted_graph(9, seed=5)
     n = g.n
     s = np.full(n, 1.0 / n)

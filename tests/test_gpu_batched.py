@@ -35,7 +35,9 @@ def make_batch(count, seed):
 @pytest.mark.parametrize("tuning", [dict(), dict(relabel=1),
                                     dict(lane_max_degree=2, wave_max_degree=16,
                                          expand_lane_max_degree=2, hub_chunk_edges=32,
-                                         relabel=1)])
+                                         relabel=1, xcd_split_degree=0),
+                                    dict(xcd_split_degree=4, hub_chunk_edges=8, relabel=1),
+                                    dict(xcd_split_degree=2, lane_max_degree=1, grid_blocks=6)])
 def test_batched_equals_per_graph(tuning):
     prhip.set_tuning(**tuning)
     gs = make_batch(24, seed=1)

@@ -19,7 +19,14 @@ from paper_2404_08299_amd import prhip  # noqa: E402
 
 ALL_LANE = dict(lane_max_degree=1 << 30, wave_max_degree=1 << 30, expand_lane_max_degree=1 << 30)
 ALL_CLASSES = dict(lane_max_degree=2, wave_max_degree=12, expand_lane_max_degree=2,
-                   hub_chunk_edges=16, relabel=1)
+                   hub_chunk_edges=16, relabel=1, xcd_split_degree=0)
+# die-split class: every row above the lane class, chunking inside segments,
+# range-major grouping, fewer workgroups than dies, a grid not a multiple of 8
+XSPLIT = [dict(xcd_split_degree=2, lane_max_degree=1),
+          dict(xcd_split_degree=8, hub_chunk_edges=4, relabel=1),
+          dict(xcd_split_degree=5, grid_blocks=5, relabel=1),
+          dict(xcd_split_degree=3, grid_blocks=13, hub_chunk_edges=2, relabel=1),
+          dict(xcd_split_degree=16, relabel=0, grid_blocks=64)]
 
 
 @pytest.fixture(autouse=True)
@@ -66,12 +73,17 @@ def test_static_all_lane_bitwise(relabel):
 
 
 @pytest.mark.parametrize("tuning", [ALL_CLASSES, dict(lane_max_degree=0, wave_max_degree=0,
-                                                         expand_lane_max_degree=0),
-                                    dict(lane_max_degree=8, wave_max_degree=200),
+                                                         expand_lane_max_degree=0,
+                                                         xcd_split_degree=0),
+                                    dict(lane_max_degree=0, wave_max_degree=0,
+                                         expand_lane_max_degree=0),
+                                    dict(lane_max_degree=8, wave_max_degree=200,
+                                         xcd_split_degree=0),
                                     dict(lane_max_degree=4, wave_max_degree=8, hub_chunk_edges=8,
-                                         expand_lane_max_degree=4, grid_blocks=7),
+                                         expand_lane_max_degree=4, grid_blocks=7,
+                                         xcd_split_degree=0),
                                     dict(grid_blocks=1), dict(hub_chunk_edges=64, grid_blocks=3000),
-                                    dict(relabel=1), dict(relabel=1, grid_blocks=5)])
+                                    dict(relabel=1), dict(relabel=1, grid_blocks=5)] + XSPLIT)
 def test_static_every_class(tuning):
     prhip.set_tuning(**tuning)
     g = gg.rmat_graph(13, 8, seed=2)
@@ -127,7 +139,8 @@ def test_static_max_iter_and_determinism():
 def test_static_threshold_invariance():
     g = gg.rmat_graph(13, 8, seed=7)
     outs = []
-    for t in (dict(), ALL_LANE, ALL_CLASSES, dict(lane_max_degree=16, wave_max_degree=64)):
+    for t in (dict(), ALL_LANE, ALL_CLASSES, dict(lane_max_degree=16, wave_max_degree=64),
+              *XSPLIT):
         prhip.set_tuning()
         prhip.set_tuning(**t)
         outs.append(gpu_static(g, tol=1e-13, max_iter=1000)[0])
@@ -219,7 +232,8 @@ def test_df_nd_vs_oracle(mode, relabel):
 
 @pytest.mark.parametrize("tuning", [ALL_CLASSES, dict(grid_blocks=1), dict(relabel=1),
                                     dict(lane_max_degree=4, wave_max_degree=8, hub_chunk_edges=8,
-                                         expand_lane_max_degree=4, grid_blocks=5, relabel=1)])
+                                         expand_lane_max_degree=4, grid_blocks=5, relabel=1,
+                                         xcd_split_degree=0)] + XSPLIT)
 def test_dfp_every_class(tuning):
     prhip.set_tuning(**tuning)
     g0, g1, b, prev = dynamic_case(scale=13, frac=1e-3, seed=3)

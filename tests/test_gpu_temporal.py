@@ -6,8 +6,13 @@ result.
 
 Per step, the GPU and the oracle get the same previous ranks (the oracle's
 own chain) and must agree within 1e-9 (tol 1e-10). The GPU's own chain is
-also run to the end and compared with a Static recompute of the last graph:
-DF-P's accepted error (Sec. 5.3) against the 1e-8 bound."""
+also run to the end: it must match the oracle's chain, and its distance to a
+Static recompute of the last graph must stay within DF-P's accepted error
+(Sec. 5.3), 10 * tau_p * max(R). On this hub-heavy graph (max rank ~0.03)
+that distance is ~1e-7 for the oracle as well, from the first batch on: an
+absolute 1e-8 holds on R-MAT, where the ranks are far smaller, not here."""
+import warnings
+
 import numpy as np
 import pytest
 
@@ -48,7 +53,11 @@ def test_temporal_chain_vs_oracle(relabel):
         assert same.converged and err <= 1e-9
         assert abs(same.iterations - o.iters) <= 1
         prev_o, prev_g = o.ranks, chain.ranks
-    ref = prhip.static(dg, tol=0.0, max_iter=500)
+    assert np.abs(prev_g.cpu().numpy() - prev_o).max() <= 1e-9
+    with warnings.catch_warnings():  # tol 0 may or may not reach an exact fixed point
+        warnings.simplefilter("ignore", RuntimeWarning)
+        ref = prhip.static(dg, tol=0.0, max_iter=500)
     d = float((prev_g - ref.ranks).abs().max())
-    print(f"chain end vs Static recompute: linf={d:.2e} max rank={float(ref.ranks.max()):.3e}")
-    assert d <= 1e-8
+    mx = float(ref.ranks.max())
+    print(f"chain end vs Static recompute: linf={d:.2e} max rank={mx:.3e}")
+    assert d <= 10 * 1e-6 * mx
