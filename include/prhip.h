@@ -231,6 +231,14 @@ int pr_validate_csr(const pr_csr *csr);
  *                      range's contributions, and the partial sums are added
  *                      in range and chunk order. With relabel on, the
  *                      grouping is done inside each range. Must be 0 or >= 2.
+ *   expand_pull_per_mille  DF/DF-P expandAffected direction: when the
+ *                      frontier (vertices whose neighbours are to be marked)
+ *                      holds more than this many thousandths of the
+ *                      vertices, every unaffected vertex is marked if one of
+ *                      its in-neighbours is in the frontier (pull, over a
+ *                      frontier bitmap); otherwise the frontier's out-edges
+ *                      are marked (push). Both give the same set. 0 = always
+ *                      push; 0..1000.
  */
 typedef struct pr_tuning {
   int32_t lane_max_degree;
@@ -241,6 +249,7 @@ typedef struct pr_tuning {
   int32_t grid_blocks;
   int32_t relabel;
   int32_t xcd_split_degree;
+  int32_t expand_pull_per_mille;
 } pr_tuning;
 
 /* Set (NULL = defaults) or read the process-wide tuning. PR_EINVAL if a

@@ -2,9 +2,9 @@
 
 Alg. 4 leaves the degree threshold that splits vertices between the
 thread-per-vertex and block-per-vertex kernels unspecified; here the
-thresholds (lane / wavefront / split-chunk sizes, the expand threshold), the
-gather-side relabelling switch and the host/device pipelining depth are
-picked by measurement on the graph at hand.
+thresholds (lane / wavefront / die-split / split-chunk sizes, the expand
+threshold), the gather-side relabelling switch and the host/device
+pipelining depth are picked by measurement on the graph at hand.
 
 Search: coordinate descent over one field at a time (two passes), each
 candidate scored by short runs of the real entry point with the iteration cap
@@ -31,11 +31,13 @@ from . import prhip
 DEFAULT_SPACE = {
     "lane_max_degree": [8, 16, 32, 64],
     "wave_max_degree": [1024, 4096, 16384],
-    "hub_chunk_edges": [2048, 4096, 8192],
+    "xcd_split_degree": [0, 64, 257, 1024],
+    "hub_chunk_edges": [1024, 4096, 8192],
     "relabel": [0, 1],
     "iters_per_sync": [1, 2, 4],
 }
-DFP_SPACE = dict(DEFAULT_SPACE, expand_lane_max_degree=[8, 32, 128])
+DFP_SPACE = dict(DEFAULT_SPACE, expand_lane_max_degree=[8, 32, 128],
+                 expand_pull_per_mille=[0, 5, 20, 100])
 
 CACHE_PATH = os.environ.get("PRHIP_TUNING_CACHE",
                             os.path.join(os.path.expanduser("~"), ".cache", "prhip_tuning.json"))

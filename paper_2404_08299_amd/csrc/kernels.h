@@ -48,7 +48,7 @@ constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kPartTile = 1024;  // vertices per partition block
 constexpr int kFinalBlock = 1024;
-constexpr int kHubFinalizeBlocks = 64;
+constexpr int kHubFinalizeBlocks = 512;
 constexpr int kXcds = 8;  // accelerator dies; workgroup b is dispatched to die b mod 8
 
 // Device-side control block of one call.
@@ -170,11 +170,14 @@ __global__ __launch_bounds__(kBlock) void k_part_count(const int *__restrict__ o
   }
 }
 
-// Exclusive scan of each class row rows[cls][0..ntiles) in place, one
-// workgroup per class (blockIdx.x); totals[cls] = the row's sum.
+// Exclusive scan of each class row rows[cls][0..len) in place, one
+// workgroup per class (blockIdx.x); totals[cls] = the row's sum. Rows are
+// `ntiles` apart; len = ntiles, or *dlen when given (a count on the device).
 __global__ __launch_bounds__(kFinalBlock) void k_scan_rows(int *__restrict__ rows, int ntiles,
-                                                           int *__restrict__ totals) {
+                                                           int *__restrict__ totals,
+                                                           const int *__restrict__ dlen) {
   int *tc = rows + (size_t)blockIdx.x * ntiles;
+  if (dlen) ntiles = min(ntiles, *dlen);
   const int per = (ntiles + kFinalBlock - 1) / kFinalBlock;
   const int beg = min((int)threadIdx.x * per, ntiles), end = min(beg + per, ntiles);
   int s = 0;
@@ -308,29 +311,25 @@ __device__ __forceinline__ int xseg_end(const int *__restrict__ idx, const int *
 }
 
 // mat[x][i] = chunks of segment x of split row i, mat[kXcds][i] = the row's
-// total, for i < nb (rows i >= n2 count 0, so nb may be any bound >= n2 + 1).
+// total, for the n2 rows of the class (nb >= n2 is the row stride of mat).
 // gid (batches): graph of each row, whose ranges are rs[gid[v]].
 __global__ __launch_bounds__(kBlock) void k_xsplit_count(
     const int *__restrict__ off, const int *__restrict__ idx, const int *__restrict__ hi,
     const int *__restrict__ counts, int slot, const int *__restrict__ rs_all,
     const int *__restrict__ gid, int CH, int nb, int *__restrict__ mat) {
-  const int n1 = counts[slot], n2 = counts[slot + 1];
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < nb; i += gridDim.x * kBlock) {
+  const int n1 = counts[slot], n2 = min(counts[slot + 1], nb);
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n2; i += gridDim.x * kBlock) {
     int tot = 0;
-    if (i < n2) {
-      const int v = hi[n1 + i];
-      const int *rs = rs_all + (gid ? gid[v] : 0) * (kXcds + 1);
-      const int r1 = off[v + 1];
-      int prev = off[v];
-      for (int x = 0; x < kXcds; ++x) {
-        const int e = xseg_end(idx, rs, prev, r1, x);
-        const int c = (e - prev + CH - 1) / CH;
-        mat[(size_t)x * nb + i] = c;
-        tot += c;
-        prev = e;
-      }
-    } else {
-      for (int x = 0; x < kXcds; ++x) mat[(size_t)x * nb + i] = 0;
+    const int v = hi[n1 + i];
+    const int *rs = rs_all + (gid ? gid[v] : 0) * (kXcds + 1);
+    const int r1 = off[v + 1];
+    int prev = off[v];
+    for (int x = 0; x < kXcds; ++x) {
+      const int e = xseg_end(idx, rs, prev, r1, x);
+      const int c = (e - prev + CH - 1) / CH;
+      mat[(size_t)x * nb + i] = c;
+      tot += c;
+      prev = e;
     }
     mat[(size_t)kXcds * nb + i] = tot;
   }
@@ -546,14 +545,29 @@ __device__ __forceinline__ void rank_update(
     const int xstep = B >= kXcds ? kXcds : B;
     const int loc = B >= kXcds ? (int)blockIdx.x / kXcds : 0;
     const int nloc = B >= kXcds ? (B - 1 - x0) / kXcds + 1 : 1;
+    // a wavefront loads 64 consecutive items {partial, e0, e1, vertex} (one
+    // per lane), keeps those of active vertices and sums them one by one
+    const long long Wx = (long long)nloc * kWavesPerBlock * kWave;
     for (int x = x0; x < kXcds; x += xstep) {
       const int end = xoff[x + 1];
-      for (int j = xoff[x] + loc * kWavesPerBlock + wid; j < end; j += nloc * kWavesPerBlock) {
-        const int4 it = xitems[j];  // {partial, e0, e1, vertex}; uniform in the wavefront
-        if (!out.active(it.w)) continue;
-        double c = strided_sum<kWave, WEIGHTED>(it.y, it.z, lane, in_src, wt, X);
-        c = wave_sum(c);
-        if (lane == 0) hub_part[it.x] = c;
+      for (long long j0 = xoff[x] + (long long)(loc * kWavesPerBlock + wid) * kWave; j0 < end;
+           j0 += Wx) {
+        const long long j = j0 + lane;
+        int4 it = make_int4(0, 0, 0, 0);
+        bool f = false;
+        if (j < end) {
+          it = xitems[j];
+          f = out.active(it.w);
+        }
+        unsigned long long big = __ballot(f);
+        while (big) {
+          const int k = __ffsll(big) - 1;
+          big &= big - 1;
+          const int p = __shfl(it.x, k), e0 = __shfl(it.y, k), e1 = __shfl(it.z, k);
+          double c = strided_sum<kWave, WEIGHTED>(e0, e1, lane, in_src, wt, X);
+          c = wave_sum(c);
+          if (lane == 0) hub_part[p] = c;
+        }
       }
     }
   }
@@ -599,19 +613,22 @@ __device__ __forceinline__ void rank_update(
     const int gw = blockIdx.x * kWavesPerBlock + wid;
     for (long long k0 = 0; gw + k0 * W < n1; k0 += kWave) {
       const long long ii = gw + (k0 + lane) * W;
-      int v = -1;
+      int v = -1, r0 = 0, r1 = 0;
       bool f = false;
       if (ii < n1) {
         v = hi[ii];
         f = out.active(v);
         if (!f) out.inactive(v);
+        else {
+          r0 = in_off[v];
+          r1 = in_off[v + 1];
+        }
       }
-      unsigned long long mask = __ballot(f);
-      while (mask) {
-        const int j = __ffsll(mask) - 1;
-        mask &= mask - 1;
-        const int vv = __shfl(v, j);
-        const int e0 = in_off[vv], e1 = in_off[vv + 1];
+      unsigned long long big = __ballot(f);
+      while (big) {
+        const int j = __ffsll(big) - 1;
+        big &= big - 1;
+        const int vv = __shfl(v, j), e0 = __shfl(r0, j), e1 = __shfl(r1, j);
         double c = strided_sum<kWave, WEIGHTED>(e0, e1, lane, in_src, wt, X);
         c = wave_sum(c);
         if (lane == 0) {
@@ -819,10 +836,12 @@ __global__ __launch_bounds__(kBlock) void k_apply_expand(
     const uint8_t *dN, uint8_t *cv,
     const int *__restrict__ hi_out, const int *__restrict__ counts,
     const int *__restrict__ hub_start, const int *__restrict__ chunk_hub, int CH, int n,
-    int t_exp, const int *__restrict__ rt, const Ctrl *__restrict__ ctrl, int it) {
+    int t_exp, const int *__restrict__ rt, long long pull_thresh, const Ctrl *__restrict__ ctrl,
+    int it) {
   const int done = ctrl->done;
   if (done && ctrl->iters < it + 1) return;  // converged before this iteration
-  const bool expand = !done;
+  // pull_thresh >= 0: k_pull_mark did the marking when the frontier was larger
+  const bool expand = !done && (pull_thresh < 0 || ctrl->aux[2 + (it & 1)] <= pull_thresh);
   __shared__ int s_e0[kBlock], s_e1[kBlock];
   __shared__ int s_wcnt[kWavesPerBlock];
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
@@ -859,14 +878,18 @@ __global__ __launch_bounds__(kBlock) void k_apply_expand(
           a = out_off[u] + (c - hub_start[i]) * CH;
           b = min(a + CH, out_off[u + 1]);
         }
-        unsigned long long mask = __ballot(f);
+        // each lane finds its candidate's targets in the range
+        int s0 = 0, s1 = 0;
+        if (f) {
+          s0 = lower_bound_idx(out_tgt, a, b, lo_t);
+          s1 = lower_bound_idx(out_tgt, s0, b, hi_t);
+        }
+        unsigned long long mask = __ballot(s1 > s0);
         while (mask) {
           const int j = __ffsll(mask) - 1;
           mask &= mask - 1;
-          const int aa = __shfl(a, j), bb = __shfl(b, j);
-          const int s0 = lower_bound_idx(out_tgt, aa, bb, lo_t);
-          const int s1 = lower_bound_idx(out_tgt, s0, bb, hi_t);
-          for (int e = s0 + lane; e < s1; e += kWave) mark(dV, ld_nt(out_tgt + e));
+          const int ss0 = __shfl(s0, j), ss1 = __shfl(s1, j);
+          for (int e = ss0 + lane; e < ss1; e += kWave) mark(dV, ld_nt(out_tgt + e));
         }
       }
     }
@@ -937,6 +960,138 @@ __global__ __launch_bounds__(kBlock) void k_apply_expand(
         const int e0 = out_off[v], e1 = out_off[v + 1];
         if (e1 - e0 <= t_exp)
           for (int e = e0; e < e1; ++e) mark(dV, ld_nt(out_tgt + e));
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------ pull expansion
+// The frontier of iteration `it` as a bitmap, bit v of fb[v / 32] = dN[v]
+// (dN bytes are 0 or 1), and its size added to ctrl->aux[2 + (it & 1)]; the
+// other counter is cleared for the next iteration.
+__global__ __launch_bounds__(kBlock) void k_frontier(const uint8_t *__restrict__ dN, int n,
+                                                     uint32_t *__restrict__ fb, Ctrl *ctrl,
+                                                     int it) {
+  if (ctrl->done) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->aux[2 + ((it + 1) & 1)] = 0;
+  const int nw = (n + 31) / 32;
+  int cnt = 0;
+  for (int w = blockIdx.x * kBlock + threadIdx.x; w < nw; w += gridDim.x * kBlock) {
+    const int v0 = w * 32;
+    uint32_t word = 0;
+    if (v0 + 32 <= n && (reinterpret_cast<uintptr_t>(dN) & 3) == 0) {
+      const uint32_t *q = reinterpret_cast<const uint32_t *>(dN + v0);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const uint32_t b = q[k] & 0x01010101u;  // byte i's low bit at bit 8i
+        word |= ((b | (b >> 7) | (b >> 14) | (b >> 21)) & 0xFu) << (4 * k);
+      }
+    } else {
+      for (int b = 0; v0 + b < n; ++b)
+        if (dN[v0 + b]) word |= 1u << b;
+    }
+    fb[w] = word;
+    cnt += __popc(word);
+  }
+  cnt = wave_sum_int(cnt);
+  if ((threadIdx.x & (kWave - 1)) == 0 && cnt)
+    atomicAdd((unsigned long long *)&ctrl->aux[2 + (it & 1)], (unsigned long long)cnt);
+}
+
+__device__ __forceinline__ bool in_frontier(const uint32_t *__restrict__ fb, int u) {
+  return (fb[u >> 5] >> (u & 31)) & 1u;
+}
+
+// Whether wavefront-uniform edge range [a, b) of in_src holds a frontier
+// vertex (stops at the first 64-edge step that finds one).
+__device__ __forceinline__ bool wave_any_frontier(const int *__restrict__ in_src,
+                                                  const uint32_t *__restrict__ fb, int a, int b,
+                                                  int lane) {
+  for (int e0 = a; e0 < b; e0 += kWave) {
+    const int e = e0 + lane;
+    if (__ballot(e < b && in_frontier(fb, in_src[e]))) return true;
+  }
+  return false;
+}
+
+// expandAffected (Alg. 5) in the pull direction, used when the frontier of
+// iteration `it` has more than `thresh` vertices: an unaffected vertex v
+// becomes affected when one of its in-neighbours is in the frontier, which
+// is the set that marking out(u) for every frontier vertex u produces.
+// Rows above the lane class are checked one wavefront per row (wavefront
+// class) or per chunk (top class: die-split items {p, e0, e1, v} when
+// xitems is set, else the split-class chunks), lane-class rows one lane each.
+__global__ __launch_bounds__(kBlock) void k_pull_mark(
+    const int *__restrict__ in_off, const int *__restrict__ in_src,
+    const int *__restrict__ hi_in, const int *__restrict__ counts,
+    const int *__restrict__ hub_start, const int *__restrict__ chunk_hub, int CH,
+    const int4 *__restrict__ xitems, const int *__restrict__ xoff,
+    const uint32_t *__restrict__ fb, uint8_t *dV, int n, int t1, long long thresh,
+    const Ctrl *__restrict__ ctrl, int it) {
+  if (ctrl->done || ctrl->aux[2 + (it & 1)] <= thresh) return;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+  const int B = gridDim.x;
+  const long long W = (long long)B * kWavesPerBlock;
+  const int gw = blockIdx.x * kWavesPerBlock + wid;
+  const int n1 = counts[kInWave];
+  // top class, chunk by chunk
+  const long long nchunks = xitems ? (long long)xoff[kXcds] : (long long)counts[kInChunks];
+  for (long long k0 = 0; gw + k0 * W < nchunks; k0 += kWave) {
+    const long long c = gw + (k0 + lane) * W;
+    int v = 0, a = 0, b = 0;
+    bool need = false;
+    if (c < nchunks) {
+      if (xitems) {
+        const int4 itm = xitems[c];
+        v = itm.w;
+        a = itm.y;
+        b = itm.z;
+      } else {
+        const int i = chunk_hub[c];
+        v = hi_in[n1 + i];
+        a = in_off[v] + ((int)c - hub_start[i]) * CH;
+        b = min(a + CH, in_off[v + 1]);
+      }
+      need = !dV[v];
+    }
+    unsigned long long mask = __ballot(need);
+    while (mask) {
+      const int j = __ffsll(mask) - 1;
+      mask &= mask - 1;
+      const int vv = __shfl(v, j), aa = __shfl(a, j), bb = __shfl(b, j);
+      if (wave_any_frontier(in_src, fb, aa, bb, lane) && lane == 0) dV[vv] = 1;
+    }
+  }
+  // wavefront class, one wavefront per row
+  for (long long k0 = 0; gw + k0 * W < n1; k0 += kWave) {
+    const long long ii = gw + (k0 + lane) * W;
+    int v = 0;
+    bool need = false;
+    if (ii < n1) {
+      v = hi_in[ii];
+      need = !dV[v];
+    }
+    unsigned long long mask = __ballot(need);
+    while (mask) {
+      const int j = __ffsll(mask) - 1;
+      mask &= mask - 1;
+      const int vv = __shfl(v, j);
+      if (wave_any_frontier(in_src, fb, in_off[vv], in_off[vv + 1], lane) && lane == 0)
+        dV[vv] = 1;
+    }
+  }
+  // lane class over ID tiles
+  const int ntiles = (n + kBlock - 1) / kBlock;
+  for (int t = blockIdx.x; t < ntiles; t += B) {
+    const int v = t * kBlock + tid;
+    if (v < n && !dV[v]) {
+      const int e0 = in_off[v], e1 = in_off[v + 1];
+      if (e1 - e0 <= t1) {
+        for (int e = e0; e < e1; ++e)
+          if (in_frontier(fb, in_src[e])) {
+            dV[v] = 1;
+            break;
+          }
       }
     }
   }

@@ -50,6 +50,7 @@ pr_tuning default_tuning() {
   t.grid_blocks = 0;
   t.relabel = -1;
   t.xcd_split_degree = 257;
+  t.expand_pull_per_mille = 20;
   return t;
 }
 pr_tuning g_tuning = default_tuning();
@@ -61,6 +62,7 @@ struct Workspace {
   int num_cus = 0;
   double *R1 = nullptr, *X0 = nullptr, *X1 = nullptr, *T = nullptr;
   uint8_t *flags = nullptr;  // dV | dN | cv, n bytes each
+  uint32_t *fbits = nullptr;  // frontier bitmap, (n + 31) / 32 words
   int *hi_in = nullptr, *hi_out = nullptr;
   int *hub_start_in = nullptr, *hub_start_out = nullptr;  // [n + 1]
   int *chunk_hub_in = nullptr, *chunk_hub_out = nullptr;  // [cap_chunks]
@@ -128,7 +130,8 @@ int fail(int code, const std::string &msg) {
 
 void free_arrays(Workspace &w) {
   (void)hipFree(w.R1); (void)hipFree(w.X0); (void)hipFree(w.X1); (void)hipFree(w.T);
-  (void)hipFree(w.flags); (void)hipFree(w.hi_in); (void)hipFree(w.hi_out);
+  (void)hipFree(w.flags); (void)hipFree(w.fbits); (void)hipFree(w.hi_in); (void)hipFree(w.hi_out);
+  w.fbits = nullptr;
   (void)hipFree(w.hub_start_in); (void)hipFree(w.hub_start_out);
   (void)hipFree(w.chunk_hub_in); (void)hipFree(w.chunk_hub_out); (void)hipFree(w.hub_part);
   (void)hipFree(w.tile_counts); (void)hipFree(w.partials);
@@ -200,6 +203,7 @@ void free_ws(Workspace &w) {
 }
 
 size_t ntiles_for(size_t n) { return (n + kPartTile - 1) / kPartTile; }
+size_t flag_stride(size_t n) { return (n + 255) / 256 * 256; }
 
 // Workgroups of a fixed-size launch: the tuning value, else as many as can
 // be resident at once (occupancy of `kernel` times the compute units).
@@ -286,7 +290,8 @@ int get_ws(size_t n, size_t m, int CH, int B, Workspace **out) {
         (e = hipMalloc(&w.X0, nn * sizeof(double))) != hipSuccess ||
         (e = hipMalloc(&w.X1, nn * sizeof(double))) != hipSuccess ||
         (e = hipMalloc(&w.T, nn * sizeof(double))) != hipSuccess ||
-        (e = hipMalloc(&w.flags, 3 * nn)) != hipSuccess ||
+        (e = hipMalloc(&w.flags, 3 * flag_stride(nn))) != hipSuccess ||
+        (e = hipMalloc(&w.fbits, ((nn + 31) / 32 + 16) * sizeof(uint32_t))) != hipSuccess ||
         (e = hipMalloc(&w.hi_in, nn * sizeof(int))) != hipSuccess ||
         (e = hipMalloc(&w.hi_out, nn * sizeof(int))) != hipSuccess ||
         (e = hipMalloc(&w.hub_start_in, (nn + 1) * sizeof(int))) != hipSuccess ||
@@ -370,7 +375,7 @@ int partition(Workspace &w, const int *off, int n, int m, int t1, int t2, int CH
   hipLaunchKernelGGL(k_part_count, dim3(nt), dim3(kBlock), 0, s, off, n, t1, t2, w.tile_counts,
                      nt);
   hipLaunchKernelGGL(k_scan_rows, dim3(2), dim3(kFinalBlock), 0, s, w.tile_counts, nt,
-                     w.counts + slot);
+                     w.counts + slot, (const int *)nullptr);
   hipLaunchKernelGGL(k_part_scatter, dim3(nt), dim3(kBlock), 0, s, off, n, t1, t2,
                      w.tile_counts, nt, (const int *)(w.counts + slot), hi);
   if (!T) {
@@ -387,7 +392,7 @@ int partition(Workspace &w, const int *off, int n, int m, int t1, int t2, int CH
   hipLaunchKernelGGL(k_xsplit_count, dim3(gb), dim3(kBlock), 0, s, off, xidx, (const int *)hi,
                      (const int *)w.counts, slot, xrs, gid, CH, (int)nb, w.xmat);
   hipLaunchKernelGGL(k_scan_rows, dim3(kXcds + 1), dim3(kFinalBlock), 0, s, w.xmat, (int)nb,
-                     w.xtot);
+                     w.xtot, (const int *)(w.counts + slot + 1));
   hipLaunchKernelGGL(k_xsplit_fill, dim3(gb), dim3(kBlock), 0, s, off, xidx, (const int *)hi,
                      w.counts, slot, chunk_slot, xrs, gid, CH, (int)nb,
                      (const int *)w.xmat, (const int *)w.xtot, w.xoff, hub_start, w.xitems);
@@ -416,7 +421,7 @@ int locality(Workspace &w, int n, int m, const int *group_off, const int *idx,
   hipLaunchKernelGGL(k_group_count, dim3(nt), dim3(kBlock), 0, s, group_off, n, w.tile_counts,
                      nt);
   hipLaunchKernelGGL(k_scan_rows, dim3(kGroups), dim3(kFinalBlock), 0, s, w.tile_counts, nt,
-                     w.group_totals);
+                     w.group_totals, (const int *)nullptr);
   hipLaunchKernelGGL(k_group_scatter, dim3(nt), dim3(kBlock), 0, s, group_off, n,
                      (const int *)w.tile_counts, (const int *)w.group_totals, nt, rs, w.newid);
   const int mb = std::min((m + kBlock - 1) / kBlock, 8 * std::max(1, w.num_cus) * 4);
@@ -622,7 +627,8 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
   const int B = prune ? grid_blocks(w, tn, k_rank_dfp<true>) : grid_blocks(w, tn, k_rank_dfp<false>);
   const int np = B + kHubFinalizeBlocks;
   CallTimer timer(w, s);
-  uint8_t *dV = w.flags, *dN = w.flags + n, *cv = w.flags + 2 * (size_t)n;
+  const size_t fs = flag_stride((size_t)n);  // each flag array 256-byte aligned
+  uint8_t *dV = w.flags, *dN = w.flags + fs, *cv = w.flags + 2 * fs;
   double *R = ranks_out;
   const int t1 = tn.lane_max_degree, t_exp = tn.expand_lane_max_degree, CH = tn.hub_chunk_edges;
   hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, s, w.ctrl);
@@ -657,13 +663,26 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
                        ins ? ins->src : nullptr, ni, n, dV, dN, w.ctrl);
     LAUNCH_TRY();
   }
+  // frontier size above which expandAffected pulls (-1: always push)
+  const long long pull_thresh =
+      tn.expand_pull_per_mille > 0 ? (long long)n * tn.expand_pull_per_mille / 1000 : -1;
+  const int fgrid = std::max(1, std::min((n / 32 + kBlock) / kBlock, 4 * std::max(1, w.num_cus)));
   auto apply_expand = [&](int it) {
+    if (pull_thresh >= 0) {
+      hipLaunchKernelGGL(k_frontier, dim3(fgrid), dim3(kBlock), 0, s, (const uint8_t *)dN, n,
+                         w.fbits, w.ctrl, it);
+      hipLaunchKernelGGL(k_pull_mark, dim3(B), dim3(kBlock), 0, s, g->in_offsets,
+                         g->in_sources, (const int *)w.hi_in, (const int *)w.counts,
+                         (const int *)w.hub_start_in, (const int *)w.chunk_hub_in, CH, xp.items,
+                         xp.off, (const uint32_t *)w.fbits, dV, n, t1, pull_thresh,
+                         (const Ctrl *)w.ctrl, it);
+    }
     hipLaunchKernelGGL(k_apply_expand, dim3(B), dim3(kBlock), 0, s, g->out_offsets,
                        g->out_targets, loc.pos, R, X, (const double *)w.T, dV,
                        (const uint8_t *)dN, cv,
                        (const int *)w.hi_out, (const int *)w.counts,
                        (const int *)w.hub_start_out, (const int *)w.chunk_hub_out, CH, n, t_exp,
-                       xs ? (const int *)w.xrt : nullptr, (const Ctrl *)w.ctrl, it);
+                       xs ? (const int *)w.xrt : nullptr, pull_thresh, (const Ctrl *)w.ctrl, it);
   };
   // initial expandAffected (Alg. 2, after initialAffected)
   apply_expand(-1);
@@ -1257,7 +1276,8 @@ int pr_set_tuning(const pr_tuning *t) {
       t->expand_lane_max_degree < 0 || t->expand_lane_max_degree > t->wave_max_degree ||
       t->iters_per_sync < 1 || t->iters_per_sync >= kRing || t->hub_chunk_edges < 0 ||
       t->grid_blocks < 0 || t->grid_blocks > (1 << 20) || t->relabel < -1 || t->relabel > 1 ||
-      t->xcd_split_degree < 0 || t->xcd_split_degree == 1)
+      t->xcd_split_degree < 0 || t->xcd_split_degree == 1 || t->expand_pull_per_mille < 0 ||
+      t->expand_pull_per_mille > 1000)
     return fail(PR_EINVAL, "tuning field out of range");
   g_tuning = *t;
   if (g_tuning.hub_chunk_edges == 0) g_tuning.hub_chunk_edges = 4096;

@@ -43,7 +43,12 @@ def test_status_codes_match_header():
 def test_struct_layouts():
     assert ctypes.sizeof(prhip.PrCsr) == 8 + 4 * 8
     assert ctypes.sizeof(prhip.PrEdges) == 24
-    assert ctypes.sizeof(prhip.PrTuning) == 32
+    assert ctypes.sizeof(prhip.PrTuning) == 9 * 4
+    # the binding's tuning fields are the header's, in order
+    text = open(os.path.join(ROOT, "include", "prhip.h")).read()
+    body = re.search(r"typedef struct pr_tuning \{(.*?)\} pr_tuning;", text, re.S).group(1)
+    names = re.findall(r"int32_t (\w+);", body)
+    assert names == [f for f, _ in prhip.PrTuning._fields_] == list(prhip.TUNING_FIELDS)
     assert ctypes.sizeof(prhip.PrStats) == 4 + 4 + 8 + 8 + 8 + 4 + 4 + 8 + 32
 
 
@@ -79,9 +84,11 @@ def test_tuning_validation(lib):
                 prhip.PrTuning(1, 5, 3, 1, 64, -2),     # grid < 0
                 prhip.PrTuning(1, 5, 3, 1, 64, 0, 2),   # relabel not in {-1, 0, 1}
                 prhip.PrTuning(1, 5, 3, 1, 64, 0, 0, -1),  # die-split degree < 0
-                prhip.PrTuning(1, 5, 3, 1, 64, 0, 0, 1)]:  # die-split degree 1
+                prhip.PrTuning(1, 5, 3, 1, 64, 0, 0, 1),   # die-split degree 1
+                prhip.PrTuning(1, 5, 3, 1, 64, 0, 0, 0, -1),   # pull threshold < 0
+                prhip.PrTuning(1, 5, 3, 1, 64, 0, 0, 0, 1001)]:  # pull threshold > 1000
         assert lib.pr_set_tuning(ctypes.byref(bad)) == prhip.PR_EINVAL
-    assert default["xcd_split_degree"] == 257
+    assert default["xcd_split_degree"] == 257 and default["expand_pull_per_mille"] == 20
     good = prhip.PrTuning(4, 64, 8, 3, 0, 100, 1, 2)
     assert lib.pr_set_tuning(ctypes.byref(good)) == 0
     got = prhip.get_tuning()

@@ -243,6 +243,29 @@ def test_dfp_every_class(tuning):
     assert abs(res.iterations - o.iters) <= 1
 
 
+@pytest.mark.parametrize("mode", ["dfp", "df"])
+@pytest.mark.parametrize("tuning", [dict(), dict(xcd_split_degree=0),
+                                    dict(xcd_split_degree=4, hub_chunk_edges=8, relabel=1),
+                                    dict(lane_max_degree=4, wave_max_degree=8, hub_chunk_edges=8,
+                                         expand_lane_max_degree=4, xcd_split_degree=0)])
+def test_dfp_pull_equals_push(mode, tuning):
+    """expandAffected marks the same set pulling over a frontier bitmap as
+    pushing over the frontier's out-edges, so the whole DF/DF-P trajectory is
+    the same: forced push (0), pull from a frontier of n/1000 (1), never
+    pull (1000) and the default give bit-identical ranks."""
+    g0, g1, b, prev = dynamic_case(scale=13, frac=1e-2, seed=6)
+    outs = []
+    for pm in (0, 1, 1000, None):
+        prhip.set_tuning()
+        prhip.set_tuning(**tuning, **({} if pm is None else dict(expand_pull_per_mille=pm)))
+        r, res = gpu_dfp(g1, b, prev, mode=mode)
+        outs.append((r, res.iterations))
+    o = oracle.dfp(g1.n, *g1.edges(), b, prev, prune=(mode == "dfp"))
+    assert np.abs(outs[0][0] - o.ranks).max() <= 1e-9
+    for r, it in outs[1:]:
+        assert it == outs[0][1] and np.array_equal(r, outs[0][0])
+
+
 def test_dfp_empty_batch_and_inplace():
     g0, g1, b, prev = dynamic_case(scale=10, frac=1e-3, seed=5)
     r, res = gpu_dfp(g1, gg.Batch.empty(), prev, tol=0.0)
