@@ -50,6 +50,7 @@ constexpr int kPartTile = 1024;  // vertices per partition block
 constexpr int kFinalBlock = 1024;
 constexpr int kHubFinalizeBlocks = 512;
 constexpr int kXcds = 8;  // accelerator dies; workgroup b is dispatched to die b mod 8
+constexpr int kLaneStage = 1536;  // contributions staged in LDS per round of a lane-class tile
 
 // Device-side control block of one call.
 struct Ctrl {
@@ -100,9 +101,10 @@ __device__ __forceinline__ int wave_sum_int(int x) {
   return x;
 }
 
-// Exclusive scan over a 1024-thread workgroup; *total gets the sum.
-__device__ __forceinline__ int block_exclusive_scan_1024(int s, int *total) {
-  __shared__ int wsum[kFinalBlock / kWave];
+// Exclusive scan over an NT-thread workgroup; *total gets the sum.
+template <int NT>
+__device__ __forceinline__ int block_exclusive_scan(int s, int *total) {
+  __shared__ int wsum[NT / kWave];
   __shared__ int tot;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
   int x = s;
@@ -115,7 +117,7 @@ __device__ __forceinline__ int block_exclusive_scan_1024(int s, int *total) {
   __syncthreads();
   if (tid == 0) {
     int run = 0;
-    for (int i = 0; i < kFinalBlock / kWave; ++i) { const int t = wsum[i]; wsum[i] = run; run += t; }
+    for (int i = 0; i < NT / kWave; ++i) { const int t = wsum[i]; wsum[i] = run; run += t; }
     tot = run;
   }
   __syncthreads();
@@ -123,6 +125,9 @@ __device__ __forceinline__ int block_exclusive_scan_1024(int s, int *total) {
   *total = tot;
   __syncthreads();
   return r;
+}
+__device__ __forceinline__ int block_exclusive_scan_1024(int s, int *total) {
+  return block_exclusive_scan<kFinalBlock>(s, total);
 }
 
 __global__ void k_ctrl_reset(Ctrl *ctrl) {
@@ -640,26 +645,64 @@ __device__ __forceinline__ void rank_update(
     }
   }
 
-  // 3) lane class over 256-vertex ID tiles
+  // 3) lane class over 256-vertex ID tiles. The tile's lane-class rows are
+  // laid end to end (exclusive scan of their degrees); the workgroup gathers
+  // their contributions edge-parallel into LDS, kLaneStage per round, and
+  // each lane then adds its own row's values in row order, carrying its sum
+  // across rounds: the sequential order of the oracle, so bit-identical.
   {
+    __shared__ int s_off[kBlock + 1];
+    __shared__ double s_val[kLaneStage];
     const int ntiles = (n + kBlock - 1) / kBlock;
     for (int t = blockIdx.x; t < ntiles; t += B) {
       const int v = t * kBlock + tid;
+      int e0 = 0, cnt = 0;
+      bool act = false;
       if (v < n) {
-        const int e0 = ld_nt(in_off + v), e1 = ld_nt(in_off + v + 1);
+        e0 = ld_nt(in_off + v);
+        const int e1 = ld_nt(in_off + v + 1);
         if (e1 - e0 <= t1) {
           if (out.active(v)) {
-            const double c = row_sum_seq<WEIGHTED>(in_src, wt, X, e0, e1);
-            const double d = out.finish(v, c);
-            dmax = fmax(dmax, d);
-            out.note(v, d);
+            act = true;
+            cnt = e1 - e0;
           } else {
             out.inactive(v);
           }
         }
       }
+      int total;
+      const int off = block_exclusive_scan<kBlock>(cnt, &total);
+      s_off[tid] = off;
+      s_e0[tid] = e0;
+      if (tid == 0) s_off[kBlock] = total;
+      __syncthreads();
+      double c = 0.0;
+      for (int c0 = 0; c0 < total; c0 += kLaneStage) {
+        const int c1 = min(c0 + kLaneStage, total);
+        for (int k = c0 + tid; k < c1; k += kBlock) {
+          int lo = 0, hi = kBlock;  // the row r with s_off[r] <= k < s_off[r + 1]
+          while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (s_off[mid] <= k) lo = mid;
+            else hi = mid;
+          }
+          s_val[k - c0] = contrib<WEIGHTED>(s_e0[lo] + (k - s_off[lo]), in_src, wt, X);
+        }
+        __syncthreads();
+        if (act) {
+          const int k1 = min(off + cnt, c1);
+          for (int k = max(off, c0); k < k1; ++k) c = c + s_val[k - c0];
+        }
+        __syncthreads();
+      }
+      if (act) {
+        const double d = out.finish(v, c);
+        dmax = fmax(dmax, d);
+        out.note(v, d);
+      }
     }
   }
+
   if (partials) {
     dmax = block_max<kBlock>(dmax, lds);
     if (tid == 0) partials[blockIdx.x] = dmax;
