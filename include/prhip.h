@@ -252,6 +252,10 @@ typedef struct pr_tuning {
   int32_t expand_pull_per_mille;
 } pr_tuning;
 
+/* Defaults: lane_max_degree 128, wave_max_degree 4096, expand_lane_max_degree
+ * 32, iters_per_sync 2, hub_chunk_edges 4096, grid_blocks 0, relabel -1,
+ * xcd_split_degree 129, expand_pull_per_mille 20. */
+
 /* Set (NULL = defaults) or read the process-wide tuning. PR_EINVAL if a
  * field is out of range (degrees < 0, lane > wave, iters_per_sync < 1,
  * xcd_split_degree == 1). */

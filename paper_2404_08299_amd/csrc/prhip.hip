@@ -42,14 +42,14 @@ std::mutex g_mu;
 pr_tuning default_tuning() {
   pr_tuning t;
   std::memset(&t, 0, sizeof(t));
-  t.lane_max_degree = 32;
+  t.lane_max_degree = 128;
   t.wave_max_degree = 4096;
   t.expand_lane_max_degree = 32;
   t.iters_per_sync = 2;
   t.hub_chunk_edges = 4096;
   t.grid_blocks = 0;
   t.relabel = -1;
-  t.xcd_split_degree = 257;
+  t.xcd_split_degree = 129;
   t.expand_pull_per_mille = 20;
   return t;
 }

@@ -88,7 +88,7 @@ def test_tuning_validation(lib):
                 prhip.PrTuning(1, 5, 3, 1, 64, 0, 0, 0, -1),   # pull threshold < 0
                 prhip.PrTuning(1, 5, 3, 1, 64, 0, 0, 0, 1001)]:  # pull threshold > 1000
         assert lib.pr_set_tuning(ctypes.byref(bad)) == prhip.PR_EINVAL
-    assert default["xcd_split_degree"] == 257 and default["expand_pull_per_mille"] == 20
+    assert default["xcd_split_degree"] == 129 and default["expand_pull_per_mille"] == 20
     good = prhip.PrTuning(4, 64, 8, 3, 0, 100, 1, 2)
     assert lib.pr_set_tuning(ctypes.byref(good)) == 0
     got = prhip.get_tuning()

@@ -22,8 +22,8 @@ def test_size_class():
 
 
 def test_coordinate_descent_finds_separable_minimum(monkeypatch):
-    target = dict(lane_max_degree=16, wave_max_degree=16384, hub_chunk_edges=1024, relabel=1,
-                  iters_per_sync=4, xcd_split_degree=64)
+    target = dict(lane_max_degree=64, wave_max_degree=16384, hub_chunk_edges=1024, relabel=1,
+                  iters_per_sync=4, xcd_split_degree=257)
 
     def fake_score(run, tuning, k1, k2, expected, repeats=2):
         prhip.set_tuning(**tuning)  # the real score applies the candidate
