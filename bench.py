@@ -435,6 +435,27 @@ def main():
                               speedup_vs_k_static=round(t_single / out["ppr"]["ms"], 2))
         log(f"comparisons: batched {out.get('batched')}, ppr {out.get('ppr')}")
 
+    if not args.no_compare and "dfp" in legs:
+        # the paper's method comparison on the same batches (one timed call
+        # each after a warm-up call): Naive-dynamic, Dynamic Traversal,
+        # Dynamic Frontier without pruning
+        tmp = torch.empty(n, dtype=torch.float64, device="cuda")
+        modes = []
+        for j, f in enumerate(fracs):
+            item = {"fraction": f}
+            for mode in ("nd", "dt", "df"):
+                prhip.dfp(dgs[j], dbs[j], prev, mode=mode, out=tmp)
+                _, t_mode = timed(lambda: prhip.dfp(dgs[j], dbs[j], prev, mode=mode, out=tmp))
+                item[f"{mode}_ms"] = round(t_mode, 3)
+                item[f"{mode}_iters"] = prhip.last_stats()["iterations"]
+            dm = float(np.mean(rec[j]["dfp_ms"])) if rec[j]["dfp_ms"] else None
+            if dm:
+                for mode in ("nd", "dt", "df"):
+                    item[f"dfp_speedup_vs_{mode}"] = round(item[f"{mode}_ms"] / dm, 2)
+            modes.append(item)
+        out["dynamic_methods"] = modes
+        log(f"methods: {modes}")
+
     if not args.no_accuracy and "dfp" in legs:
         acc = []
         ref = torch.empty(n, dtype=torch.float64, device="cuda")

@@ -114,6 +114,8 @@ int pr_dfp(const pr_csr *csr_old, const pr_csr *csr_new, const pr_edges *deletio
 #define PR_MODE_DFP 0 /* Dynamic Frontier with Pruning: Eq. 2 + pruning (Sec. 4.3)    */
 #define PR_MODE_DF 1  /* Dynamic Frontier: Eq. 1, no pruning (Sec. 4.3, Alg. 3)       */
 #define PR_MODE_ND 2  /* Naive-dynamic: Static from R^{t-1}, all vertices (Sec. 3.4.1) */
+#define PR_MODE_DT 3  /* Dynamic Traversal: every vertex reachable from the batch,     */
+                      /* Eq. 1 over that fixed set (Sec. 3.4.2, Alg. 7)              */
 
 /* pr_dfp with an explicit iteration cap and update variant. */
 int pr_dfp_ex(const pr_csr *csr_old, const pr_csr *csr_new, const pr_edges *deletions,

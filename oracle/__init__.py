@@ -63,14 +63,17 @@ def _bind(lib):
                                c.c_int64, _I32P, _F64P, c.c_double, c.c_double, c.c_double,
                                c.c_double, c.c_int32, c.c_int32, _F64P, _I32P, _F64P, _I64P,
                                _U8P]
+    lib.oracle_dt.argtypes = [c.c_int32, c.c_int64, _I32P, _I32P, c.c_int64, _I32P, _I32P,
+                              c.c_int64, _I32P, _F64P, c.c_double, c.c_double, c.c_int32, _F64P,
+                              _I32P, _F64P, _I64P]
     lib.oracle_ppr.argtypes = [c.c_int32, c.c_int64, _I32P, _I32P, c.c_int32, _F64P, c.c_double,
                                c.c_double, c.c_int32, _F64P, _I32P]
     lib.oracle_weighted.argtypes = [c.c_int32, c.c_int64, _I32P, _I32P, _F64P, _F64P,
                                     c.c_double, c.c_double, c.c_int32, _F64P, _F64P, _I32P, _F64P]
     lib.oracle_adjoint.argtypes = [c.c_int32, c.c_int64, _I32P, _I32P, _F64P, _F64P, _F64P,
                                    c.c_double, c.c_double, c.c_int32, _F64P, _F64P, _F64P, _I32P]
-    for f in (lib.oracle_static, lib.oracle_static_csr, lib.oracle_dfp, lib.oracle_ppr, lib.oracle_weighted,
-              lib.oracle_adjoint):
+    for f in (lib.oracle_static, lib.oracle_static_csr, lib.oracle_dfp, lib.oracle_dt, lib.oracle_ppr,
+              lib.oracle_weighted, lib.oracle_adjoint):
         f.restype = c.c_int
     return lib
 
@@ -174,6 +177,28 @@ def dfp(n, src, dst, batch, ranks_prev, alpha=ALPHA, tol=TOL, tau_f=TAU_F, tau_p
     stats = dict(affected_initial=int(st[0]), affected_max=int(st[1]),
                  edges_processed=int(st[2]), affected_ever=int(st[3]))
     return Result(r, it.value, d.value, rc, stats, tr[: it.value + 1] if trace else None)
+
+
+def dt(n, src, dst, batch, ranks_prev, alpha=ALPHA, tol=TOL, max_iter=MAX_ITERATIONS,
+       lib=None) -> Result:
+    """Dynamic Traversal (Alg. 7) on G^t = (src, dst): the vertices reachable
+    from the batch are affected, Eq. 1 runs over them. stats['affected']."""
+    lib = lib or load()
+    src, ps = _i32(src)
+    dst, pd = _i32(dst)
+    ds, pds = _i32(batch.del_src)
+    dd, pdd = _i32(batch.del_dst)
+    is_, pis = _i32(batch.ins_src)
+    rp, prp = _f64(ranks_prev)
+    r = np.empty(n, np.float64)
+    it = ctypes.c_int32(0)
+    d = ctypes.c_double(0.0)
+    na = ctypes.c_int64(0)
+    rc = lib.oracle_dt(n, src.size, ps, pd, ds.size, pds, pdd, is_.size, pis, prp, alpha, tol,
+                       max_iter, r.ctypes.data_as(_F64P), ctypes.byref(it), ctypes.byref(d),
+                       ctypes.byref(na))
+    _check(rc, "oracle_dt")
+    return Result(r, it.value, d.value, rc, dict(affected=int(na.value)), None)
 
 
 def ppr(n, src, dst, teleport, alpha=ALPHA, tol=TOL, max_iter=MAX_ITERATIONS, lib=None):

@@ -313,6 +313,86 @@ int oracle_dfp(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, int
 }
 
 /*
+ * Dynamic Traversal (Alg. 7, Sec. 3.4.2). Every vertex reachable from a
+ * changed edge is affected; Eq. 1 iterations then run over that fixed set
+ * from R^{t-1}, and every other vertex keeps its rank. Reachability starts
+ * from the marking of Alg. 5 (deletion targets, and the out-neighbours of
+ * every batch source, which include the source through its self-loop) and
+ * is closed under out-edges by a breadth-first search. Alg. 7 prints its
+ * closure loop expanding into the affected flags themselves; the closure is
+ * its evident intent (the prose: all vertices reachable from u are flagged).
+ * n_affected (optional) receives the size of the affected set.
+ */
+int oracle_dt(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, int64_t n_del,
+              const int32_t *del_src, const int32_t *del_dst, int64_t n_ins,
+              const int32_t *ins_src, const double *ranks_prev, double alpha, double tol,
+              int32_t max_iter, double *ranks, int32_t *iters, double *delta,
+              int64_t *n_affected) {
+  if (!(alpha > 0.0 && alpha < 1.0) || !(tol >= 0.0) || max_iter <= 0 || !ranks || !ranks_prev)
+    return OR_EINVAL;
+  if ((n_del > 0 && (!del_src || !del_dst)) || (n_ins > 0 && !ins_src)) return OR_EINVAL;
+  adjacency a;
+  int rc = adj_build(&a, n, m, src, dst);
+  if (rc) return rc;
+  for (int32_t u = 0; u < n; ++u)
+    if (a.out_deg[u] == 0) { adj_free(&a); return OR_EINVAL; }
+  for (int64_t i = 0; i < n_del; ++i)
+    if (del_src[i] < 0 || del_src[i] >= n || del_dst[i] < 0 || del_dst[i] >= n) {
+      adj_free(&a); return OR_EINVAL;
+    }
+  for (int64_t i = 0; i < n_ins; ++i)
+    if (ins_src[i] < 0 || ins_src[i] >= n) { adj_free(&a); return OR_EINVAL; }
+  double *R = malloc(sizeof(double) * (size_t)n), *Rn = malloc(sizeof(double) * (size_t)n);
+  uint8_t *dV = calloc((size_t)n, 1), *dN = calloc((size_t)n, 1);
+  int32_t *queue = malloc(sizeof(int32_t) * (size_t)n);
+  if (!R || !Rn || !dV || !dN || !queue) {
+    free(R); free(Rn); free(dV); free(dN); free(queue); adj_free(&a); return OR_ENOMEM;
+  }
+  for (int32_t v = 0; v < n; ++v) R[v] = Rn[v] = ranks_prev[v];
+  /* initialAffected, expandAffected (Alg. 5) */
+  for (int64_t i = 0; i < n_del; ++i) { dV[del_dst[i]] = 1; dN[del_src[i]] = 1; }
+  for (int64_t i = 0; i < n_ins; ++i) dN[ins_src[i]] = 1;
+  expand_affected(&a, dV, dN);
+  /* closure under out-edges: breadth-first search from every affected vertex */
+  int64_t head = 0, tail = 0;
+  for (int32_t v = 0; v < n; ++v)
+    if (dV[v]) queue[tail++] = v;
+  while (head < tail) {
+    const int32_t u = queue[head++];
+    for (int64_t i = a.out_off[u]; i < a.out_off[u + 1]; ++i) {
+      const int32_t v = a.out_tgt[i];
+      if (!dV[v]) { dV[v] = 1; queue[tail++] = v; }
+    }
+  }
+  if (n_affected) *n_affected = tail;
+  /* Eq. 1 over the affected set, the rest carried forward */
+  const double C0 = (1.0 - alpha) / (double)n;
+  int32_t it = 0;
+  double d = 0.0;
+  int converged = 0;
+  while (it < max_iter) {
+    for (int32_t v = 0; v < n; ++v) {
+      if (!dV[v]) { Rn[v] = R[v]; /* unreachable: unchanged */ continue; }
+      double c = 0.0;
+      for (int64_t i = a.in_off[v]; i < a.in_off[v + 1]; ++i) {
+        const int32_t u = a.in_src[i];
+        c = c + R[u] / (double)a.out_deg[u];
+      }
+      Rn[v] = C0 + alpha * c; /* Eq. 1 */
+    }
+    d = linf_delta(n, Rn, R);
+    double *t = R; R = Rn; Rn = t;
+    ++it;
+    if (d <= tol) { converged = 1; break; }
+  }
+  memcpy(ranks, R, sizeof(double) * (size_t)n);
+  if (iters) *iters = it;
+  if (delta) *delta = d;
+  free(R); free(Rn); free(dV); free(dN); free(queue); adj_free(&a);
+  return converged ? OR_OK : OR_NOT_CONVERGED;
+}
+
+/*
  * Personalised PageRank with k teleport vectors (vertex-major, s[v*k + j]):
  *   R_j[v] = alpha * sum_{u in in(v)} R_j[u]/|out(u)| + (1-alpha) * s_j[v],
  * started from 1/|V|; each vector stops on its own when its L-infinity

@@ -70,6 +70,7 @@ enum CountSlot {
   kOutSplit = 3,   // out-degree split class size
   kInChunks = 4,   // chunks of the in-degree split class
   kOutChunks = 5,  // chunks of the out-degree split class
+  kDtChanged = 6,  // a closure level of Dynamic Traversal marked a vertex
   kNumCounts = 8
 };
 
@@ -879,12 +880,14 @@ __global__ __launch_bounds__(kBlock) void k_apply_expand(
     const uint8_t *dN, uint8_t *cv,
     const int *__restrict__ hi_out, const int *__restrict__ counts,
     const int *__restrict__ hub_start, const int *__restrict__ chunk_hub, int CH, int n,
-    int t_exp, const int *__restrict__ rt, long long pull_thresh, const Ctrl *__restrict__ ctrl,
-    int it) {
+    int t_exp, const int *__restrict__ rt, long long pull_thresh, int do_mark,
+    const Ctrl *__restrict__ ctrl, int it) {
   const int done = ctrl->done;
   if (done && ctrl->iters < it + 1) return;  // converged before this iteration
-  // pull_thresh >= 0: k_pull_mark did the marking when the frontier was larger
-  const bool expand = !done && (pull_thresh < 0 || ctrl->aux[2 + (it & 1)] <= pull_thresh);
+  // pull_thresh >= 0: k_pull_mark did the marking when the frontier was
+  // larger; do_mark = 0: the apply step only (the affected set is fixed)
+  const bool expand =
+      do_mark && !done && (pull_thresh < 0 || ctrl->aux[2 + (it & 1)] <= pull_thresh);
   __shared__ int s_e0[kBlock], s_e1[kBlock];
   __shared__ int s_wcnt[kWavesPerBlock];
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
@@ -1070,8 +1073,16 @@ __global__ __launch_bounds__(kBlock) void k_pull_mark(
     const int *__restrict__ hub_start, const int *__restrict__ chunk_hub, int CH,
     const int4 *__restrict__ xitems, const int *__restrict__ xoff,
     const uint32_t *__restrict__ fb, uint8_t *dV, int n, int t1, long long thresh,
-    const Ctrl *__restrict__ ctrl, int it) {
+    uint8_t *newly, int *changed, const Ctrl *__restrict__ ctrl, int it) {
   if (ctrl->done || ctrl->aux[2 + (it & 1)] <= thresh) return;
+  // newly (optional): flags of the vertices marked here, and *changed = 1
+  auto set = [&](int v) {
+    dV[v] = 1;
+    if (newly) {
+      newly[v] = 1;
+      *changed = 1;
+    }
+  };
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
   const int B = gridDim.x;
   const long long W = (long long)B * kWavesPerBlock;
@@ -1102,7 +1113,7 @@ __global__ __launch_bounds__(kBlock) void k_pull_mark(
       const int j = __ffsll(mask) - 1;
       mask &= mask - 1;
       const int vv = __shfl(v, j), aa = __shfl(a, j), bb = __shfl(b, j);
-      if (wave_any_frontier(in_src, fb, aa, bb, lane) && lane == 0) dV[vv] = 1;
+      if (wave_any_frontier(in_src, fb, aa, bb, lane) && lane == 0) set(vv);
     }
   }
   // wavefront class, one wavefront per row
@@ -1120,7 +1131,7 @@ __global__ __launch_bounds__(kBlock) void k_pull_mark(
       mask &= mask - 1;
       const int vv = __shfl(v, j);
       if (wave_any_frontier(in_src, fb, in_off[vv], in_off[vv + 1], lane) && lane == 0)
-        dV[vv] = 1;
+        set(vv);
     }
   }
   // lane class over ID tiles
@@ -1132,7 +1143,7 @@ __global__ __launch_bounds__(kBlock) void k_pull_mark(
       if (e1 - e0 <= t1) {
         for (int e = e0; e < e1; ++e)
           if (in_frontier(fb, in_src[e])) {
-            dV[v] = 1;
+            set(v);
             break;
           }
       }

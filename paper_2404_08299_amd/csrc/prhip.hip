@@ -616,8 +616,9 @@ int run_static(const pr_csr *g, double alpha, double tol, int max_iter, const do
 
 int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *ins,
                          const double *prev, double alpha, double tol, double tau_f,
-                         double tau_p, int max_iter, bool prune, double *ranks_out) {
+                         double tau_p, int max_iter, int mode, double *ranks_out) {
   hipStream_t s = t_stream;
+  const bool prune = mode == PR_MODE_DFP, dt = mode == PR_MODE_DT;
   const int n = g->n;
   const pr_tuning tn = g_tuning;
   Workspace *wp = nullptr;
@@ -667,26 +668,52 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
   const long long pull_thresh =
       tn.expand_pull_per_mille > 0 ? (long long)n * tn.expand_pull_per_mille / 1000 : -1;
   const int fgrid = std::max(1, std::min((n / 32 + kBlock) / kBlock, 4 * std::max(1, w.num_cus)));
-  auto apply_expand = [&](int it) {
-    if (pull_thresh >= 0) {
+  auto apply_expand = [&](int it, bool mark) {
+    if (mark && pull_thresh >= 0) {
       hipLaunchKernelGGL(k_frontier, dim3(fgrid), dim3(kBlock), 0, s, (const uint8_t *)dN, n,
                          w.fbits, w.ctrl, it);
       hipLaunchKernelGGL(k_pull_mark, dim3(B), dim3(kBlock), 0, s, g->in_offsets,
                          g->in_sources, (const int *)w.hi_in, (const int *)w.counts,
                          (const int *)w.hub_start_in, (const int *)w.chunk_hub_in, CH, xp.items,
                          xp.off, (const uint32_t *)w.fbits, dV, n, t1, pull_thresh,
-                         (const Ctrl *)w.ctrl, it);
+                         (uint8_t *)nullptr, (int *)nullptr, (const Ctrl *)w.ctrl, it);
     }
     hipLaunchKernelGGL(k_apply_expand, dim3(B), dim3(kBlock), 0, s, g->out_offsets,
                        g->out_targets, loc.pos, R, X, (const double *)w.T, dV,
                        (const uint8_t *)dN, cv,
                        (const int *)w.hi_out, (const int *)w.counts,
                        (const int *)w.hub_start_out, (const int *)w.chunk_hub_out, CH, n, t_exp,
-                       xs ? (const int *)w.xrt : nullptr, pull_thresh, (const Ctrl *)w.ctrl, it);
+                       xs ? (const int *)w.xrt : nullptr, pull_thresh, mark ? 1 : 0,
+                       (const Ctrl *)w.ctrl, it);
   };
   // initial expandAffected (Alg. 2, after initialAffected)
-  apply_expand(-1);
+  apply_expand(-1, true);
   LAUNCH_TRY();
+  if (dt) {
+    // Dynamic Traversal (Alg. 7): close the affected set under out-edges,
+    // one level per pass (the vertices with an in-neighbour in the previous
+    // level's marks), until a pass marks nothing
+    HIP_TRY(hipMemcpyAsync(dN, dV, (size_t)n, hipMemcpyDeviceToDevice, s));
+    int *changed = w.counts + kDtChanged;
+    for (int level = 0;; ++level) {
+      hipLaunchKernelGGL(k_frontier, dim3(fgrid), dim3(kBlock), 0, s, (const uint8_t *)dN, n,
+                         w.fbits, w.ctrl, level);
+      HIP_TRY(hipMemsetAsync(cv, 0, (size_t)n, s));
+      HIP_TRY(hipMemsetAsync(changed, 0, sizeof(int), s));
+      hipLaunchKernelGGL(k_pull_mark, dim3(B), dim3(kBlock), 0, s, g->in_offsets,
+                         g->in_sources, (const int *)w.hi_in, (const int *)w.counts,
+                         (const int *)w.hub_start_in, (const int *)w.chunk_hub_in, CH, xp.items,
+                         xp.off, (const uint32_t *)w.fbits, dV, n, t1, -1LL, cv, changed,
+                         (const Ctrl *)w.ctrl, level);
+      LAUNCH_TRY();
+      HIP_TRY(hipMemcpyAsync(w.host_counts, changed, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      if (!w.host_counts[0]) break;
+      HIP_TRY(hipMemcpyAsync(dN, cv, (size_t)n, hipMemcpyDeviceToDevice, s));
+    }
+    HIP_TRY(hipMemsetAsync(cv, 0, (size_t)n, s));
+    HIP_TRY(hipMemsetAsync(dN, 0, (size_t)n, s));
+  }
   if (t_profiling) {
     hipLaunchKernelGGL(k_count_flags, dim3(std::min(1024, (n + kBlock - 1) / kBlock)),
                        dim3(kBlock), 0, s, (const uint8_t *)dV, n, w.ctrl, 0);
@@ -723,7 +750,7 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
     }
     hipLaunchKernelGGL(k_linf_final, dim3(1), dim3(kFinalBlock), 0, s,
                        (const double *)w.partials, np, w.ctrl, tol, it);
-    apply_expand(it);
+    apply_expand(it, !dt);  // DT: the affected set stays fixed
     LAUNCH_TRY();
     return PR_OK;
   };
@@ -1135,7 +1162,7 @@ int pr_dfp_ex(const pr_csr *csr_old, const pr_csr *csr_new, const pr_edges *dele
   if (rc) return rc;
   if ((rc = check_params(alpha, tol, max_iter))) return rc;
   if (!ranks_prev || !ranks_out) return fail(PR_EINVAL, "ranks_prev and ranks_out are required");
-  if (mode != PR_MODE_DFP && mode != PR_MODE_DF && mode != PR_MODE_ND)
+  if (mode != PR_MODE_DFP && mode != PR_MODE_DF && mode != PR_MODE_ND && mode != PR_MODE_DT)
     return fail(PR_EINVAL, "unknown mode");
   if (std::isnan(frontier_tol) || std::isnan(prune_tol))
     return fail(PR_EINVAL, "tolerances must not be NaN");
@@ -1146,7 +1173,7 @@ int pr_dfp_ex(const pr_csr *csr_old, const pr_csr *csr_new, const pr_edges *dele
   std::lock_guard<std::mutex> lock(g_mu);
   if (mode == PR_MODE_ND) return run_static(csr_new, alpha, tol, max_iter, ranks_prev, ranks_out);
   return run_dynamic_frontier(csr_new, deletions, insertions, ranks_prev, alpha, tol,
-                              frontier_tol, prune_tol, max_iter, mode == PR_MODE_DFP, ranks_out);
+                              frontier_tol, prune_tol, max_iter, mode, ranks_out);
 }
 
 int pr_dfp(const pr_csr *csr_old, const pr_csr *csr_new, const pr_edges *deletions,

@@ -18,7 +18,7 @@ SO_PATH = os.path.join(_PKG, "libprhip.so")
 
 PR_OK, PR_NOT_CONVERGED = 0, 1
 PR_EINVAL, PR_EGRAPH, PR_EBATCH, PR_ENOMEM, PR_EHIP = -1, -2, -3, -4, -5
-MODES = {"dfp": 0, "df": 1, "nd": 2}
+MODES = {"dfp": 0, "df": 1, "nd": 2, "dt": 3}
 
 ALPHA, TOL, FRONTIER_TOL, PRUNE_TOL, MAX_ITERATIONS = 0.85, 1e-10, 1e-6, 1e-6, 500
 
@@ -219,7 +219,7 @@ def static(g: DeviceGraph, alpha=ALPHA, tol=TOL, max_iter=MAX_ITERATIONS, out=No
 def dfp(g_new: DeviceGraph, batch: DeviceBatch, ranks_prev, alpha=ALPHA, tol=TOL,
         frontier_tol=FRONTIER_TOL, prune_tol=PRUNE_TOL, max_iter=MAX_ITERATIONS, mode="dfp",
         out=None, g_old: DeviceGraph | None = None) -> Result:
-    """DF-P (default), DF or ND update through pr_dfp / pr_dfp_ex."""
+    """DF-P (default), DF, ND or DT update through pr_dfp / pr_dfp_ex."""
     torch = _torch()
     lib = load_library()
     if out is None:

@@ -334,6 +334,56 @@ def pin_dfp_accuracy(lib):
     assert err_df <= 10 * oracle.TAU_F * ref.max()
 
 
+# ------------------------------------------------------------------ DT pins
+def _reachable(g, seeds):
+    """Brute force: every vertex reachable from `seeds` along out-edges."""
+    seen = set(seeds)
+    stack = list(seeds)
+    while stack:
+        u = stack.pop()
+        for w in g.out_targets[g.out_offsets[u]:g.out_offsets[u + 1]].tolist():
+            if w not in seen:
+                seen.add(w)
+                stack.append(w)
+    return seen
+
+
+def pin_dt_exact_and_reachability(lib):
+    """DT (Alg. 7) re-solves only the vertices reachable from the batch. A
+    vertex no changed edge reaches has no changed ancestor, so its exact rank
+    does not change: started from the exact ranks of G^{t-1}, DT lands on the
+    dense solution of G^t, and the unreachable vertices keep their ranks bit
+    for bit. The affected count equals brute-force reachability from the
+    batch sources and the deletion targets."""
+    cases = [(9, 6, 30, 0.8), (10, 8, 5, 1.0), (9, 10, 12, 0.0)]
+    for scale, ef, size, ins in cases:
+        g0 = gg.rmat_graph(scale, ef, seed=scale + size)
+        b = gg.random_batch(g0, size, seed=size, insert_frac=ins)
+        g = gg.apply_batch(g0, b)
+        s, d = g.edges()
+        prev = dense_solve(g0.n, *g0.edges())
+        res = oracle.dt(g.n, s, d, b, prev, tol=1e-15, max_iter=5000, lib=lib)
+        assert res.status == oracle.OK
+        ref = dense_solve(g.n, s, d)
+        err = np.abs(res.ranks - ref).max()
+        assert err <= 1e-13, (scale, size, err)
+        seeds = set(b.del_src.tolist()) | set(b.ins_src.tolist()) | set(b.del_dst.tolist())
+        reach = _reachable(g, seeds)
+        assert res.stats["affected"] == len(reach), (res.stats, len(reach))
+        keep = np.array(sorted(set(range(g.n)) - reach), dtype=np.int64)
+        assert np.array_equal(res.ranks[keep], prev[keep])
+
+
+def pin_dt_empty_batch(lib):
+    """Nothing reachable: one iteration with a zero change, ranks unchanged."""
+    g = gg.rmat_graph(8, 8, seed=4)
+    s, d = g.edges()
+    prev = oracle.static(g.n, s, d, lib=lib).ranks
+    res = oracle.dt(g.n, s, d, gg.Batch.empty(), prev, tol=0.0, lib=lib)
+    assert res.status == oracle.OK and res.iters == 1 and res.delta == 0.0
+    assert res.stats["affected"] == 0 and np.array_equal(res.ranks, prev)
+
+
 # ----------------------------------------------------------------- PPR pins
 def pin_ppr_dense_and_linearity(lib):
     g = gg.rmat_graph(9, 8, seed=8)
@@ -412,5 +462,6 @@ ALL_PINS = [
     pin_static_out_star, pin_static_local_closed_form, pin_static_invariants,
     pin_static_contraction, pin_dfp_empty_batch, pin_dfp_eq2_fixed_point,
     pin_dfp_frontier_reachability, pin_dfp_initial_marking, pin_dfp_eq2_one_step,
-    pin_dfp_accuracy, pin_ppr_dense_and_linearity, pin_weighted_dense, pin_adjoint_dense_and_fd,
+    pin_dfp_accuracy, pin_dt_exact_and_reachability, pin_dt_empty_batch,
+    pin_ppr_dense_and_linearity, pin_weighted_dense, pin_adjoint_dense_and_fd,
 ]

@@ -68,8 +68,12 @@ def test_argument_errors_before_hip(lib):
     bad = prhip.PrEdges(None, None, 3)
     assert lib.pr_dfp(None, ctypes.byref(csr2), ctypes.byref(bad), None, ctypes.c_void_p(8), 0.85,
                       1e-10, 1e-6, 1e-6, ctypes.c_void_p(8)) == prhip.PR_EINVAL
-    assert lib.pr_dfp_ex(None, ctypes.byref(csr2), None, None, ctypes.c_void_p(8), 0.85, 1e-10,
-                         1e-6, 1e-6, 500, 7, ctypes.c_void_p(8)) == prhip.PR_EINVAL
+    for mode in (-1, 4, 7):  # PR_MODE_DFP, _DF, _ND, _DT are 0 .. 3
+        assert lib.pr_dfp_ex(None, ctypes.byref(csr2), None, None, ctypes.c_void_p(8), 0.85,
+                             1e-10, 1e-6, 1e-6, 500, mode, ctypes.c_void_p(8)) == prhip.PR_EINVAL
+    text = open(os.path.join(ROOT, "include", "prhip.h")).read()
+    for name, val in prhip.MODES.items():
+        assert re.search(r"#define PR_MODE_%s %d\b" % (name.upper(), val), text), name
 
 
 def test_tuning_validation(lib):

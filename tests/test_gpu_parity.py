@@ -266,6 +266,36 @@ def test_dfp_pull_equals_push(mode, tuning):
         assert it == outs[0][1] and np.array_equal(r, outs[0][0])
 
 
+@pytest.mark.parametrize("frac", [1e-4, 1e-2])
+@pytest.mark.parametrize("tuning", [dict(), dict(xcd_split_degree=0), ALL_CLASSES,
+                                    dict(grid_blocks=5, relabel=1), XSPLIT[0]])
+def test_dt_vs_oracle(tuning, frac):
+    """Dynamic Traversal (Alg. 7): the affected set is the closure of the
+    batch under out-edges (its size must match exactly), then Eq. 1 over it."""
+    prhip.set_tuning(**tuning)
+    g0, g1, b, prev = dynamic_case(scale=12, frac=frac, seed=7)
+    prhip.set_profiling(True)
+    try:
+        r, res = gpu_dfp(g1, b, prev, mode="dt")
+        aff = prhip.last_stats()["affected_initial"]
+    finally:
+        prhip.set_profiling(False)
+    o = oracle.dt(g1.n, *g1.edges(), b, prev)
+    assert res.converged and np.abs(r - o.ranks).max() <= 1e-9
+    assert abs(res.iterations - o.iters) <= 1
+    assert aff == o.stats["affected"]
+
+
+def test_dt_bitwise_and_empty():
+    prhip.set_tuning(**ALL_LANE)
+    g0, g1, b, prev = dynamic_case(scale=11, frac=1e-3, seed=8)
+    r, res = gpu_dfp(g1, b, prev, mode="dt")
+    o = oracle.dt(g1.n, *g1.edges(), b, prev)
+    assert res.iterations == o.iters and np.array_equal(r, o.ranks)
+    r, res = gpu_dfp(g1, gg.Batch.empty(), prev, mode="dt", tol=0.0)
+    assert res.iterations == 1 and np.array_equal(r, prev)
+
+
 def test_dfp_empty_batch_and_inplace():
     g0, g1, b, prev = dynamic_case(scale=10, frac=1e-3, seed=5)
     r, res = gpu_dfp(g1, gg.Batch.empty(), prev, tol=0.0)

@@ -37,6 +37,8 @@ MUTANTS = {
     "adjoint_transposed": ("c = c + w[a.out_eid[i]] * L[a.out_tgt[i]];", "c = c + w[a.in_eid[i]] * L[a.in_src[i]];"),
     "adjoint_edge_grad_transposed": ("grad_w[e] = alpha * r[src[e]] * L[dst[e]];", "grad_w[e] = alpha * r[dst[e]] * L[src[e]];"),
     "adjoint_grad_s_undamped": ("grad_s[v] = (1.0 - alpha) * L[v];", "grad_s[v] = L[v];"),
+    "dt_closure_one_level": ("while (head < tail) {", "while (0) {"),
+    "dt_deletion_target_unmarked": ("{ dV[del_dst[i]] = 1; dN[del_src[i]] = 1; }", "{ dN[del_src[i]] = 1; }"),
 }
 
 
