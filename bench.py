@@ -448,6 +448,10 @@ def main():
                 _, t_mode = timed(lambda: prhip.dfp(dgs[j], dbs[j], prev, mode=mode, out=tmp))
                 item[f"{mode}_ms"] = round(t_mode, 3)
                 item[f"{mode}_iters"] = prhip.last_stats()["iterations"]
+            # the batch applied on the device (pr_apply_batch: both views of G^t from G^{t-1})
+            prhip.apply_batch(dg0, dbs[j])
+            _, t_apply = timed(lambda: prhip.apply_batch(dg0, dbs[j]))
+            item["apply_batch_ms"] = round(t_apply, 3)
             dm = float(np.mean(rec[j]["dfp_ms"])) if rec[j]["dfp_ms"] else None
             if dm:
                 for mode in ("nd", "dt", "df"):

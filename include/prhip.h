@@ -185,6 +185,34 @@ int pr_adjoint(const pr_csr *csr, const double *in_weights, const double *ranks,
                const double *grad_ranks, double alpha, double tol, int max_iter,
                double *grad_weights, double *grad_teleport, double *lambda_out);
 
+/* Output views of pr_apply_batch: device arrays owned by the caller. */
+typedef struct pr_csr_out {
+  int32_t n, m;           /* n as in the input; m = input m - deletions + insertions */
+  int32_t *in_offsets;    /* [n+1] */
+  int32_t *in_sources;    /* [m]   */
+  int32_t *out_offsets;   /* [n+1] (NULL: the out view is not built) */
+  int32_t *out_targets;   /* [m]   (NULL with out_offsets)             */
+} pr_csr_out;
+
+/*
+ * Applies a batch update on the device (Sec. 3.3): G^t = G^{t-1} minus the
+ * deletions plus the insertions, both CSR views, rows ascending. The paper
+ * does this on the host before its timed region; here it runs on the GPU,
+ * so a dynamic pipeline never leaves the device.
+ *   old          G^{t-1}; out_targets required when out->out_offsets is set
+ *   deletions    pairs (src[i] -> dst[i]) present in G^{t-1}, no self-loops
+ *   insertions   pairs absent from G^{t-1} (dst required here)
+ *   out          G^t; out->n = old->n and out->m = old->m - deletions +
+ *                insertions; its arrays must not alias old's
+ * The batch must be normalised (the set differences): a repeated pair, a
+ * deletion that is absent or an insertion that is present returns
+ * PR_EBATCH (out then holds unspecified values; nothing is written outside
+ * its arrays). Uses rocPRIM's radix sort for the batch keys and allocates
+ * stream-ordered scratch.
+ */
+int pr_apply_batch(const pr_csr *old, const pr_edges *deletions, const pr_edges *insertions,
+                   const pr_csr_out *out);
+
 /*
  * Checks the input contract on the device: offsets start at 0, are
  * non-decreasing and end at m; every ID is in [0, n); rows are strictly

@@ -11,8 +11,8 @@ INCLUDE = os.path.join(ROOT, "include")
 SO = os.path.join(PKG, "libprhip.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = [os.path.join(CSRC, "prhip.hip")]
-HEADERS = [os.path.join(CSRC, f) for f in ("kernels.h", "wave.h")] + [
+SOURCES = [os.path.join(CSRC, "prhip.hip"), os.path.join(CSRC, "apply.hip")]
+HEADERS = [os.path.join(CSRC, f) for f in ("kernels.h", "wave.h", "apply.h")] + [
     os.path.join(INCLUDE, "prhip.h")]
 
 # -ffp-contract=off: every product and sum rounds as written, so the lane

@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "batched.h"
+#include "apply.h"
 #include "kernels.h"
 #include "ppr.h"
 #include "prhip.h"
@@ -1251,6 +1252,51 @@ int pr_adjoint(const pr_csr *csr, const double *in_weights, const double *ranks,
     (void)hipStreamSynchronize(t_stream);
   }
   return rc;
+}
+
+int pr_apply_batch(const pr_csr *old, const pr_edges *deletions, const pr_edges *insertions,
+                   const pr_csr_out *out) {
+  reset_stats();
+  int rc = check_csr(old, false);
+  if (rc) return rc;
+  if (!out || !out->in_offsets || !out->in_sources)
+    return fail(PR_EINVAL, "out and its in view are required");
+  const bool outview = out->out_offsets != nullptr;
+  if (outview && (!out->out_targets || !old->out_targets))
+    return fail(PR_EINVAL, "the out view needs old->out_targets and out->out_targets");
+  if ((rc = check_edges(deletions, "deletions"))) return rc;
+  if ((rc = check_edges(insertions, "insertions"))) return rc;
+  const int nd = deletions ? deletions->count : 0, ni = insertions ? insertions->count : 0;
+  if ((nd > 0 && !deletions->dst) || (ni > 0 && !insertions->dst))
+    return fail(PR_EINVAL, "deletions.dst and insertions.dst are required");
+  if (out->n != old->n || (long long)out->m != (long long)old->m - nd + ni)
+    return fail(PR_EINVAL, "out->n must equal old->n and out->m = old->m - deletions + insertions");
+  std::lock_guard<std::mutex> lock(g_mu);
+  const int32_t *ds = nd ? deletions->src : nullptr, *dd = nd ? deletions->dst : nullptr;
+  const int32_t *is = ni ? insertions->src : nullptr, *id = ni ? insertions->dst : nullptr;
+  int err = 0;
+  const char *what = nullptr;
+  // in view: rows are targets, entries sources
+  int e = prhip_apply_view(old->n, old->in_offsets, old->in_sources, out->m, dd, ds, nd, id, is, ni,
+                           out->in_offsets, out->in_sources, t_stream, &err, &what);
+  if (e) return fail(PR_EHIP, std::string("pr_apply_batch: ") + (what ? what : "") + ": " +
+                                  hipGetErrorString((hipError_t)e));
+  if (!err && outview) {
+    e = prhip_apply_view(old->n, old->out_offsets, old->out_targets, out->m, ds, dd, nd, is, id, ni,
+                         out->out_offsets, out->out_targets, t_stream, &err, &what);
+    if (e) return fail(PR_EHIP, std::string("pr_apply_batch: ") + (what ? what : "") + ": " +
+                                    hipGetErrorString((hipError_t)e));
+  }
+  if (err) {
+    std::string msg = "batch is not a normalised update of this graph:";
+    if (err & 1) msg += " vertex ID out of range;";
+    if (err & 2) msg += " repeated pair;";
+    if (err & 4) msg += " deletion absent;";
+    if (err & 8) msg += " insertion already present;";
+    if (err & (16 | 32)) msg += " edge count inconsistent;";
+    return fail(PR_EBATCH, msg);
+  }
+  return PR_OK;
 }
 
 int pr_validate_csr(const pr_csr *g) {

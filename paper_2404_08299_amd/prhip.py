@@ -35,6 +35,12 @@ class PrCsr(ctypes.Structure):
                 ("out_offsets", ctypes.c_void_p), ("out_targets", ctypes.c_void_p)]
 
 
+class PrCsrOut(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int32),
+                ("in_offsets", ctypes.c_void_p), ("in_sources", ctypes.c_void_p),
+                ("out_offsets", ctypes.c_void_p), ("out_targets", ctypes.c_void_p)]
+
+
 class PrEdges(ctypes.Structure):
     _fields_ = [("src", ctypes.c_void_p), ("dst", ctypes.c_void_p), ("count", ctypes.c_int32)]
 
@@ -61,7 +67,7 @@ class PrStats(ctypes.Structure):
 
 
 EXPORTED = ["pr_static", "pr_dfp", "pr_dfp_ex", "pr_ppr", "pr_static_batched", "pr_weighted",
-            "pr_adjoint",
+            "pr_adjoint", "pr_apply_batch",
             "pr_validate_csr", "pr_set_tuning",
             "pr_get_tuning", "pr_last_stats", "pr_set_profiling", "pr_set_stream",
             "pr_last_error", "pr_release"]
@@ -100,8 +106,9 @@ def load_library(path: str = SO_PATH):
     lib.pr_last_error.restype = ctypes.c_char_p
     lib.pr_release.argtypes = []
     lib.pr_release.restype = None
+    lib.pr_apply_batch.argtypes = [P(PrCsr), P(PrEdges), P(PrEdges), P(PrCsrOut)]
     for f in ("pr_static", "pr_dfp", "pr_dfp_ex", "pr_ppr", "pr_static_batched", "pr_weighted",
-              "pr_adjoint",
+              "pr_adjoint", "pr_apply_batch",
               "pr_validate_csr", "pr_set_tuning",
               "pr_get_tuning", "pr_last_stats", "pr_set_profiling"):
         getattr(lib, f).restype = ctypes.c_int
@@ -240,6 +247,28 @@ def dfp(g_new: DeviceGraph, batch: DeviceBatch, ranks_prev, alpha=ALPHA, tol=TOL
                            frontier_tol, prune_tol, max_iter, MODES[mode], out.data_ptr())
     _check(rc, lib)
     return _result(rc, out)
+
+
+def apply_batch(g_old: DeviceGraph, batch: DeviceBatch, out_view: bool = True) -> DeviceGraph:
+    """G^t = G^{t-1} - deletions + insertions on the device (pr_apply_batch);
+    the batch must be normalised (set differences) and carry insertion
+    targets. Returns a new DeviceGraph."""
+    torch = _torch()
+    lib = load_library()
+    nd, ni = int(batch.del_src.numel()), int(batch.ins_src.numel())
+    m = g_old.m - nd + ni
+    dev = g_old.in_offsets.device
+    e = lambda k: torch.empty(k, dtype=torch.int32, device=dev)
+    io, isrc = e(g_old.n + 1), e(max(m, 1))
+    oo, otg = (e(g_old.n + 1), e(max(m, 1))) if out_view else (None, None)
+    p = lambda x: None if x is None else x.data_ptr()
+    out = PrCsrOut(g_old.n, m, p(io), p(isrc), p(oo), p(otg))
+    _bind_stream(lib, torch)
+    de, ie = batch.edges()
+    rc = lib.pr_apply_batch(ctypes.byref(g_old.csr()), ctypes.byref(de), ctypes.byref(ie),
+                            ctypes.byref(out))
+    _check(rc, lib)
+    return DeviceGraph(g_old.n, m, io, isrc[:m], oo, otg[:m] if otg is not None else None)
 
 
 def ppr(g: DeviceGraph, teleport, alpha=ALPHA, tol=TOL, max_iter=MAX_ITERATIONS, out=None):

@@ -68,6 +68,14 @@ def test_argument_errors_before_hip(lib):
     bad = prhip.PrEdges(None, None, 3)
     assert lib.pr_dfp(None, ctypes.byref(csr2), ctypes.byref(bad), None, ctypes.c_void_p(8), 0.85,
                       1e-10, 1e-6, 1e-6, ctypes.c_void_p(8)) == prhip.PR_EINVAL
+    # pr_apply_batch: output sizes and required arrays are checked before any HIP call
+    out = prhip.PrCsrOut(4, 5, 8, 8, None, None)  # m must be 4 - 0 + 0
+    assert lib.pr_apply_batch(ctypes.byref(csr2), None, None, ctypes.byref(out)) == prhip.PR_EINVAL
+    out = prhip.PrCsrOut(4, 5, 8, 8, None, None)
+    ins = prhip.PrEdges(8, None, 1)  # insertion targets are required here
+    assert lib.pr_apply_batch(ctypes.byref(csr2), None, ctypes.byref(ins),
+                              ctypes.byref(out)) == prhip.PR_EINVAL
+    assert lib.pr_apply_batch(ctypes.byref(csr2), None, None, None) == prhip.PR_EINVAL
     for mode in (-1, 4, 7):  # PR_MODE_DFP, _DF, _ND, _DT are 0 .. 3
         assert lib.pr_dfp_ex(None, ctypes.byref(csr2), None, None, ctypes.c_void_p(8), 0.85,
                              1e-10, 1e-6, 1e-6, 500, mode, ctypes.c_void_p(8)) == prhip.PR_EINVAL
