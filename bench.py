@@ -460,6 +460,35 @@ def main():
         out["dynamic_methods"] = modes
         log(f"methods: {modes}")
 
+    if not args.no_compare and "static" in legs:
+        # ablation of the rank kernel's design choices: rank-kernel time per
+        # launch (6 Static iterations at tol 0 on G^{t-1}) under each setting
+        settings = {
+            "default": {},
+            "no_partition_lane_per_vertex": dict(lane_max_degree=1 << 30, wave_max_degree=1 << 30),
+            "paper_two_kernels_32": dict(lane_max_degree=32, wave_max_degree=1 << 30,
+                                         xcd_split_degree=0),
+            "no_die_split": dict(xcd_split_degree=0),
+            "no_relabel": dict(relabel=0),
+            "no_die_split_no_relabel": dict(xcd_split_degree=0, relabel=0),
+        }
+        tmp = torch.empty(n, dtype=torch.float64, device="cuda")
+        abl = {}
+        prhip.set_profiling(True)
+        for name, kw in settings.items():
+            prhip.set_tuning()
+            prhip.set_tuning(**kw)
+            with warnings.catch_warnings():
+                warnings.simplefilter("ignore")
+                prhip.static(dg0, tol=0.0, max_iter=2, out=tmp)
+                prhip.static(dg0, tol=0.0, max_iter=6, out=tmp)
+            st = prhip.last_stats()
+            abl[name] = round(st["rank_kernel_ms"] / st["rank_kernel_launches"] * 1e3, 1)
+        prhip.set_profiling(False)
+        prhip.set_tuning()
+        out["ablation_rank_us"] = abl
+        log(f"ablation (rank kernel us per launch): {abl}")
+
     if not args.no_accuracy and "dfp" in legs:
         acc = []
         ref = torch.empty(n, dtype=torch.float64, device="cuda")

@@ -313,7 +313,10 @@ typedef struct pr_stats {
   int32_t rank_kernel_launches;
   int32_t reserved0;
   double total_ms;
-  double reserved[4];
+  int64_t affected_max;      /* DF/DF-P/DT, with profiling: largest affected set */
+  int64_t edges_processed;   /* of an iteration, and the in-edges of the affected */
+                             /* vertices summed over the iterations (-1: n/a)    */
+  double reserved[2];
 } pr_stats;
 
 int pr_last_stats(pr_stats *out);

@@ -63,7 +63,8 @@ class PrStats(ctypes.Structure):
                 ("final_delta", ctypes.c_double), ("affected_initial", ctypes.c_int64),
                 ("rank_kernel_ms", ctypes.c_double), ("rank_kernel_launches", ctypes.c_int32),
                 ("reserved0", ctypes.c_int32), ("total_ms", ctypes.c_double),
-                ("reserved", ctypes.c_double * 4)]
+                ("affected_max", ctypes.c_int64), ("edges_processed", ctypes.c_int64),
+                ("reserved", ctypes.c_double * 2)]
 
 
 EXPORTED = ["pr_static", "pr_dfp", "pr_dfp_ex", "pr_ppr", "pr_static_batched", "pr_weighted",
@@ -202,7 +203,8 @@ def last_stats() -> dict:
     lib.pr_last_stats(ctypes.byref(s))
     return dict(iterations=s.iterations, converged=bool(s.converged), final_delta=s.final_delta,
                 affected_initial=s.affected_initial, rank_kernel_ms=s.rank_kernel_ms,
-                rank_kernel_launches=s.rank_kernel_launches, total_ms=s.total_ms)
+                rank_kernel_launches=s.rank_kernel_launches, total_ms=s.total_ms,
+                affected_max=s.affected_max, edges_processed=s.edges_processed)
 
 
 def _result(rc, out):

@@ -296,6 +296,34 @@ def test_dt_bitwise_and_empty():
     assert res.iterations == 1 and np.array_equal(r, prev)
 
 
+@pytest.mark.parametrize("mode", ["dfp", "df", "dt"])
+def test_affected_counters_match_oracle(mode):
+    """With every row summed in the oracle's order the trajectory is the
+    oracle's, so the profiling counters must equal its statistics: the
+    affected set after the initial marking, the largest affected set of an
+    iteration, and the in-edges processed over all iterations."""
+    prhip.set_tuning(**ALL_LANE)
+    g0, g1, b, prev = dynamic_case(scale=11, frac=1e-3, seed=12)
+    prhip.set_profiling(True)
+    try:
+        r, res = gpu_dfp(g1, b, prev, mode=mode)
+        st = prhip.last_stats()
+    finally:
+        prhip.set_profiling(False)
+    s_, d_ = g1.edges()
+    if mode == "dt":
+        o = oracle.dt(g1.n, s_, d_, b, prev)
+        assert st["affected_max"] == st["affected_initial"] == o.stats["affected"]
+        # the fixed set's in-edges, once per iteration
+        assert st["edges_processed"] % res.iterations == 0
+    else:
+        o = oracle.dfp(g1.n, s_, d_, b, prev, prune=(mode == "dfp"))
+        assert st["affected_initial"] == o.stats["affected_initial"]
+        assert st["affected_max"] == o.stats["affected_max"]
+        assert st["edges_processed"] == o.stats["edges_processed"]
+    assert res.iterations == o.iters and np.array_equal(r, o.ranks)
+
+
 def test_dfp_empty_batch_and_inplace():
     g0, g1, b, prev = dynamic_case(scale=10, frac=1e-3, seed=5)
     r, res = gpu_dfp(g1, gg.Batch.empty(), prev, tol=0.0)
