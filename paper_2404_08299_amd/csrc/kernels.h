@@ -59,7 +59,9 @@ struct Ctrl {
   int err;        // nonzero: a batch vertex ID was out of range
   int pad;
   double delta;   // L-infinity change of the last performed iteration
-  long long aux[4];
+  // 0 affected after the initial marking, 2-3 frontier sizes (by parity),
+  // 4 affected this iteration, 5 largest affected set, 6 in-edges processed
+  long long aux[8];
 };
 
 // Device array of class counts, written by the partition and plan kernels.
@@ -138,7 +140,7 @@ __global__ void k_ctrl_reset(Ctrl *ctrl) {
     ctrl->err = 0;
     ctrl->pad = 0;
     ctrl->delta = 0.0;
-    for (int i = 0; i < 4; ++i) ctrl->aux[i] = 0;
+    for (int i = 0; i < 8; ++i) ctrl->aux[i] = 0;
   }
 }
 
@@ -1308,6 +1310,35 @@ __global__ __launch_bounds__(kBlock) void k_count_flags(const uint8_t *__restric
   c = wave_sum_int(c);
   if ((threadIdx.x & (kWave - 1)) == 0 && c)
     atomicAdd((unsigned long long *)&ctrl->aux[slot], (unsigned long long)c);
+}
+
+// Profiling of DF/DF-P/DT: the affected vertices an iteration is about to
+// update, and their in-edges; k_affected_fold keeps the largest set and
+// adds the edges to the running total.
+__global__ __launch_bounds__(kBlock) void k_count_affected(const uint8_t *__restrict__ dV,
+                                                           const int *__restrict__ in_off, int n,
+                                                           Ctrl *ctrl) {
+  if (ctrl->done) return;
+  int c = 0;
+  long long e = 0;
+  for (int v = blockIdx.x * kBlock + threadIdx.x; v < n; v += gridDim.x * kBlock)
+    if (dV[v]) {
+      ++c;
+      e += in_off[v + 1] - in_off[v];
+    }
+  c = wave_sum_int(c);
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) e += __shfl_xor(e, o);
+  if ((threadIdx.x & (kWave - 1)) == 0 && (c || e)) {
+    atomicAdd((unsigned long long *)&ctrl->aux[4], (unsigned long long)c);
+    atomicAdd((unsigned long long *)&ctrl->aux[6], (unsigned long long)e);
+  }
+}
+__global__ void k_affected_fold(Ctrl *ctrl) {
+  if (threadIdx.x == 0 && !ctrl->done) {
+    if (ctrl->aux[4] > ctrl->aux[5]) ctrl->aux[5] = ctrl->aux[4];
+    ctrl->aux[4] = 0;
+  }
 }
 
 // ------------------------------------------------------------ validation

@@ -53,6 +53,7 @@ __global__ __launch_bounds__(kBlock) void k_ppr_rank(
     int K, const double *__restrict__ X, const double *__restrict__ R, double *__restrict__ Rn,
     double *__restrict__ Xn, const double *__restrict__ S, double *__restrict__ part,
     const int *__restrict__ vdone, double alpha, double *__restrict__ pmax,
+    const int4 *__restrict__ xitems, const int *__restrict__ xoff,
     const Ctrl *__restrict__ ctrl) {
   if (ctrl->done) return;
   extern __shared__ double s_max[];  // [kWavesPerBlock][K]
@@ -62,8 +63,24 @@ __global__ __launch_bounds__(kBlock) void k_ppr_rank(
   const int W = gridDim.x * kWavesPerBlock;
   const int gw = blockIdx.x * kWavesPerBlock + wid;
   const double oma = 1.0 - alpha;
+  if (xitems) {
+    // long rows cut by source range: list x ({partial, e0, e1, vertex} items)
+    // is summed by the workgroups on die x, one wavefront per item
+    const int B = gridDim.x;
+    const int x0 = B >= kXcds ? (int)blockIdx.x % kXcds : (int)blockIdx.x;
+    const int xstep = B >= kXcds ? kXcds : B;
+    const int loc = B >= kXcds ? (int)blockIdx.x / kXcds : 0;
+    const int nloc = B >= kXcds ? (B - 1 - x0) / kXcds + 1 : 1;
+    for (int x = x0; x < kXcds; x += xstep)
+      for (int j = xoff[x] + loc * kWavesPerBlock + wid; j < xoff[x + 1];
+           j += nloc * kWavesPerBlock) {
+        const int4 it = xitems[j];
+        for (int k = lane; k < K; k += kWave)
+          if (!vdone[k]) part[(size_t)it.x * K + k] = ppr_row_sum(in_src, X, K, k, it.y, it.z);
+      }
+  }
   // chunks of long rows: partial row sums
-  for (int c = gw; c < nch; c += W) {
+  for (int c = gw; !xitems && c < nch; c += W) {
     const int i = chunk_hub[c];
     const int v = hi[n1 + i];
     const int r0 = in_off[v], r1 = in_off[v + 1];

@@ -370,7 +370,7 @@ int partition(Workspace &w, const int *off, int n, int m, int t1, int t2, int CH
               const int *xidx = nullptr, XPlan *xp = nullptr, const int *xrs = nullptr,
               const int *gid = nullptr) {
   if (!xrs) xrs = w.xrs;
-  const int T = xidx ? xsplit_min_degree(g_tuning) : 0;
+  const int T = xidx ? std::max(xsplit_min_degree(g_tuning), t1 + 1) : 0;
   if (T) t2 = T - 1;
   const int nt = (int)ntiles_for(n);
   hipLaunchKernelGGL(k_part_count, dim3(nt), dim3(kBlock), 0, s, off, n, t1, t2, w.tile_counts,
@@ -503,6 +503,8 @@ void collect_profile(Workspace &w, int iters) {
 void reset_stats() {
   std::memset(&t_stats, 0, sizeof(t_stats));
   t_stats.affected_initial = -1;
+  t_stats.affected_max = -1;
+  t_stats.edges_processed = -1;
   t_err.clear();
 }
 
@@ -715,9 +717,18 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
     HIP_TRY(hipMemsetAsync(cv, 0, (size_t)n, s));
     HIP_TRY(hipMemsetAsync(dN, 0, (size_t)n, s));
   }
+  // profiling: the affected set each iteration is about to update (counted
+  // after the marking that produced it, outside the rank-kernel timing)
+  const int cgrid = std::min(1024, (n + kBlock - 1) / kBlock);
+  auto count_affected = [&]() {
+    hipLaunchKernelGGL(k_count_affected, dim3(cgrid), dim3(kBlock), 0, s, (const uint8_t *)dV,
+                       g->in_offsets, n, w.ctrl);
+    hipLaunchKernelGGL(k_affected_fold, dim3(1), dim3(64), 0, s, w.ctrl);
+  };
   if (t_profiling) {
-    hipLaunchKernelGGL(k_count_flags, dim3(std::min(1024, (n + kBlock - 1) / kBlock)),
-                       dim3(kBlock), 0, s, (const uint8_t *)dV, n, w.ctrl, 0);
+    hipLaunchKernelGGL(k_count_flags, dim3(cgrid), dim3(kBlock), 0, s, (const uint8_t *)dV, n,
+                       w.ctrl, 0);
+    count_affected();
     LAUNCH_TRY();
   }
   const double C0 = (1.0 - alpha) / (double)n;
@@ -752,6 +763,7 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
     hipLaunchKernelGGL(k_linf_final, dim3(1), dim3(kFinalBlock), 0, s,
                        (const double *)w.partials, np, w.ctrl, tol, it);
     apply_expand(it, !dt);  // DT: the affected set stays fixed
+    if (t_profiling) count_affected();
     LAUNCH_TRY();
     return PR_OK;
   };
@@ -762,7 +774,11 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
   HIP_TRY(hipStreamSynchronize(s));
   const Ctrl &last = w.host_ctrl[(launched - 1) % kRing];
   if (last.err) return fail(PR_EBATCH, "batch vertex ID outside [0, n)");
-  if (t_profiling) t_stats.affected_initial = last.aux[0];
+  if (t_profiling) {
+    t_stats.affected_initial = last.aux[0];
+    t_stats.affected_max = last.aux[5];
+    t_stats.edges_processed = last.aux[6];
+  }
   t_stats.total_ms = timer.ms();
   collect_profile(w, iters);
   return t_stats.converged ? PR_OK : PR_NOT_CONVERGED;
@@ -772,7 +788,7 @@ constexpr int kPprChunk = 256;  // in-edges per wavefront before a row is split
 
 int ppr_ws(Workspace &w, size_t n, size_t m, size_t K, size_t B) {
   const size_t nbuf = 4 * n * K;
-  const size_t npart = (m / kPprChunk + n + 1) * K;
+  const size_t npart = std::max(m / kPprChunk + n + 1, xsplit_items_bound(n, m, kPprChunk)) * K;
   const size_t npmax = (B + kHubFinalizeBlocks + 16) * K;
   if (nbuf > w.cap_ppr_buf || npart > w.cap_ppr_part || npmax > w.cap_ppr_pmax ||
       K > w.cap_ppr_k || n > w.cap_ppr_n) {
@@ -819,12 +835,18 @@ int run_ppr(const pr_csr *g, const double *teleport, int K, double alpha, double
   double *Rb[2] = {w.ppr_buf, w.ppr_buf + nk};
   double *Xb[2] = {w.ppr_buf + 2 * nk, w.ppr_buf + 3 * nk};
   hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, s, w.ctrl);
-  // rows longer than kPprChunk form the split class (class 1 of Alg. 4 empty)
+  // rows longer than kPprChunk form the split class (class 1 of Alg. 4
+  // empty), cut by source range as well when the die split is on
+  const bool xs = xsplit_min_degree(tn) > 0;
+  if (xs && (rc = xcd_ranges(w, g->out_offsets, n, s))) return rc;
+  XPlan xp;
   rc = partition(w, g->in_offsets, n, g->m, kPprChunk, kPprChunk, kPprChunk, w.hi_in, kInWave,
-                 kInChunks, w.hub_start_in, w.chunk_hub_in, s);
+                 kInChunks, w.hub_start_in, w.chunk_hub_in, s, xs ? g->in_sources : nullptr, &xp);
   if (rc) return rc;
   Locality loc;
-  if ((rc = locality(w, n, g->m, g->out_offsets, g->in_sources, tn, true, s, &loc))) return rc;
+  if ((rc = locality(w, n, g->m, g->out_offsets, g->in_sources, tn, true, s, &loc,
+                     xs ? w.xrs : nullptr)))
+    return rc;
   const int ib = (int)std::min<size_t>((nk + kBlock - 1) / kBlock, (size_t)B * 4);
   hipLaunchKernelGGL(k_ppr_init, dim3(ib), dim3(kBlock), 0, s, n, K, g->out_offsets, loc.pos,
                      Rb[0], Xb[0], w.ppr_vdone, w.ppr_viters);
@@ -839,7 +861,8 @@ int run_ppr(const pr_csr *g, const double *teleport, int K, double alpha, double
                        (const int *)w.hub_start_in, (const int *)w.chunk_hub_in,
                        (const uint8_t *)w.ppr_split, kPprChunk, n, K, (const double *)Xb[a],
                        (const double *)Rb[a], Rb[b], Xb[b], teleport, w.ppr_part,
-                       (const int *)w.ppr_vdone, alpha, w.ppr_pmax, (const Ctrl *)w.ctrl);
+                       (const int *)w.ppr_vdone, alpha, w.ppr_pmax, xp.items, xp.off,
+                       (const Ctrl *)w.ctrl);
     if (prof) HIP_TRY(hipEventRecord(after, s));
     hipLaunchKernelGGL(k_ppr_finalize, dim3(F), dim3(kBlock), shm, s, g->out_offsets, loc.pos,
                        (const int *)w.hi_in, (const int *)w.counts, (const int *)w.hub_start_in,

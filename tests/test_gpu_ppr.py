@@ -28,9 +28,12 @@ def teleports(n, k, seeds_per, seed):
     return T
 
 
+@pytest.mark.parametrize("xsplit", [129, 0])
 @pytest.mark.parametrize("scale,k,relabel", [(11, 8, 0), (12, 64, 1), (10, 70, 0), (9, 1, 1)])
-def test_ppr_vs_oracle(scale, k, relabel):
-    prhip.set_tuning(relabel=relabel)
+def test_ppr_vs_oracle(scale, k, relabel, xsplit):
+    """Long rows (in-degree > 256) cut into 256-edge chunks, by source range
+    first when the die split is on (xcd_split_degree > 0)."""
+    prhip.set_tuning(relabel=relabel, xcd_split_degree=xsplit)
     g = gg.rmat_graph(scale, 8, seed=scale)
     T = teleports(g.n, k, min(16, g.n), seed=2)
     res, its = prhip.ppr(prhip.DeviceGraph.from_host(g), torch.from_numpy(T).cuda())
@@ -65,8 +68,11 @@ def test_ppr_uniform_teleport_matches_static_and_linearity():
     assert np.abs(R[:, 4] - (0.3 * R[:, 0] + 0.7 * R[:, 1])).max() <= 1e-13
 
 
-def test_ppr_hub_rows_split():
+@pytest.mark.parametrize("tuning", [dict(), dict(xcd_split_degree=0), dict(grid_blocks=5),
+                                    dict(grid_blocks=13, relabel=1)])
+def test_ppr_hub_rows_split(tuning):
     """In-star with a center of in-degree 3000 (> 256): chunked rows."""
+    prhip.set_tuning(**tuning)
     k = 3000
     g = gg.from_edges(k + 1, np.arange(1, k + 1, dtype=np.int32), np.zeros(k, np.int32))
     T = teleports(g.n, 5, 4, seed=1)
