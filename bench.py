@@ -392,11 +392,18 @@ def main():
         out["value"] = round(gteps, 3)
         out["static_gbs_per_iteration"] = round(gbs, 1)
         out["batches"] = per_batch
+        out["rank_gteps"] = round(g0.m / (avg_rank_ms / 1e3) / 1e9, 2)
+        out["paper_style_medges_per_s"] = round(
+            float(np.mean([ms[j] / (np.mean(rec[j]["static_ms"]) / 1e3) / 1e6
+                           for j in range(len(fracs)) if rec[j]["static_ms"]])), 1)
         out["roofline"] = {"bound": "hbm", "kernel": "k_rank_static",
                            "achieved": round(achieved, 1) if achieved else None,
                            "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
                            "traffic": read_traffic(),
+                           "traffic_kind": "L2-to-fabric bytes per launch (rocprofv3 FETCH_SIZE + "
+                                           "WRITE_SIZE, copy-calibrated; Infinity Cache hits "
+                                           "included, not DRAM-only)",
                            "avg_launch_us": round(avg_rank_ms * 1e3, 2),
                            "algorithmic_bytes_per_launch": algorithmic_bytes(n, g0.m)}
 
@@ -509,6 +516,10 @@ def main():
 
     if args.temporal_batches > 0:
         out["temporal"] = temporal_leg(args, gg, prhip, torch, np)
+
+    if "static" in legs:
+        # measured ceiling of a plain streaming device copy on this machine
+        out["roofline"]["copy_ceiling_gbs"] = round(copy_probe(), 1)
 
     cpu = None
     if not args.no_cpu_baseline:
