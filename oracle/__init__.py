@@ -72,8 +72,13 @@ def _bind(lib):
                                     c.c_double, c.c_double, c.c_int32, _F64P, _F64P, _I32P, _F64P]
     lib.oracle_adjoint.argtypes = [c.c_int32, c.c_int64, _I32P, _I32P, _F64P, _F64P, _F64P,
                                    c.c_double, c.c_double, c.c_int32, _F64P, _F64P, _F64P, _I32P]
+    lib.oracle_static_rows.argtypes = [c.c_int32, _I32P, _I32P, _I32P, _F64P, c.c_double,
+                                       c.c_int64, _I32P, _F64P]
+    lib.oracle_dfp_csr.argtypes = [c.c_int32, _I32P, _I32P, _I32P, _I32P, c.c_int64, _I32P, _I32P,
+                                   c.c_int64, _I32P, _F64P, c.c_double, c.c_double, c.c_double,
+                                   c.c_double, c.c_int32, c.c_int32, _F64P, _I32P, _F64P, _I64P]
     for f in (lib.oracle_static, lib.oracle_static_csr, lib.oracle_dfp, lib.oracle_dt, lib.oracle_ppr,
-              lib.oracle_weighted, lib.oracle_adjoint):
+              lib.oracle_weighted, lib.oracle_adjoint, lib.oracle_static_rows, lib.oracle_dfp_csr):
         f.restype = c.c_int
     return lib
 
@@ -153,6 +158,23 @@ def static_csr(n, in_offsets, in_sources, out_offsets, alpha=ALPHA, tol=TOL,
     return Result(r, it.value, d.value, rc), sec.value
 
 
+def static_rows(n, in_offsets, in_sources, out_offsets, ranks, rows, alpha=ALPHA, lib=None):
+    """One Eq. 1 update from `ranks` for the listed rows only (sources in
+    ascending order), over a given in-CSR and out-offsets: a sample of one
+    step of an iteration on a graph too large for the full oracle here."""
+    lib = lib or load()
+    io, pio = _i32(in_offsets)
+    isrc, pis = _i32(in_sources)
+    oo, poo = _i32(out_offsets)
+    r, pr = _f64(ranks)
+    rows, prow = _i32(rows)
+    out = np.empty(rows.size, np.float64)
+    rc = lib.oracle_static_rows(n, pio, pis, poo, pr, alpha, rows.size, prow,
+                                out.ctypes.data_as(_F64P))
+    _check(rc, "oracle_static_rows")
+    return out
+
+
 def dfp(n, src, dst, batch, ranks_prev, alpha=ALPHA, tol=TOL, tau_f=TAU_F, tau_p=TAU_P,
         max_iter=MAX_ITERATIONS, prune=True, trace=False, lib=None) -> Result:
     """Alg. 2 (DF-P when prune, DF otherwise) on G^t = (src, dst).
@@ -177,6 +199,33 @@ def dfp(n, src, dst, batch, ranks_prev, alpha=ALPHA, tol=TOL, tau_f=TAU_F, tau_p
     stats = dict(affected_initial=int(st[0]), affected_max=int(st[1]),
                  edges_processed=int(st[2]), affected_ever=int(st[3]))
     return Result(r, it.value, d.value, rc, stats, tr[: it.value + 1] if trace else None)
+
+
+def dfp_csr(g, batch, ranks_prev, alpha=ALPHA, tol=TOL, tau_f=TAU_F, tau_p=TAU_P,
+            max_iter=MAX_ITERATIONS, prune=True, lib=None) -> Result:
+    """The same run as dfp() over G^t given in both CSR views (an object with
+    n, in_offsets, in_sources, out_offsets, out_targets), for graphs whose
+    adjacency construction from an edge list is too slow here."""
+    lib = lib or load()
+    io, pio = _i32(g.in_offsets)
+    isrc, pis_ = _i32(g.in_sources)
+    oo, poo = _i32(g.out_offsets)
+    ot, pot = _i32(g.out_targets)
+    ds, pds = _i32(batch.del_src)
+    dd, pdd = _i32(batch.del_dst)
+    is_, pis = _i32(batch.ins_src)
+    rp, prp = _f64(ranks_prev)
+    r = np.empty(g.n, np.float64)
+    it = ctypes.c_int32(0)
+    d = ctypes.c_double(0.0)
+    st = np.zeros(4, np.int64)
+    rc = lib.oracle_dfp_csr(g.n, pio, pis_, poo, pot, ds.size, pds, pdd, is_.size, pis, prp, alpha,
+                            tol, tau_f, tau_p, max_iter, 1 if prune else 0, r.ctypes.data_as(_F64P),
+                            ctypes.byref(it), ctypes.byref(d), st.ctypes.data_as(_I64P))
+    _check(rc, "oracle_dfp_csr")
+    stats = dict(affected_initial=int(st[0]), affected_max=int(st[1]),
+                 edges_processed=int(st[2]), affected_ever=int(st[3]))
+    return Result(r, it.value, d.value, rc, stats)
 
 
 def dt(n, src, dst, batch, ranks_prev, alpha=ALPHA, tol=TOL, max_iter=MAX_ITERATIONS,

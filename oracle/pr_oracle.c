@@ -213,6 +213,29 @@ int oracle_static_csr(int32_t n, const int32_t *in_off, const int32_t *in_src,
   return rc;
 }
 
+/* One update of Eq. 1 for the listed rows only, from the given R:
+ *   out[i] = (1 - alpha)/|V| + alpha * sum_{u in in(rows[i])} R[u]/|out(u)|,
+ * sources in ascending order, as in the Static iteration. For graphs too
+ * large for the full iteration here: a sample of one step of a long run. */
+int oracle_static_rows(int32_t n, const int32_t *in_off, const int32_t *in_src,
+                       const int32_t *out_off, const double *R, double alpha, int64_t k,
+                       const int32_t *rows, double *out) {
+  if (n <= 0 || !in_off || !in_src || !out_off || !R || k < 0 || (k && (!rows || !out)))
+    return OR_EINVAL;
+  const double C0 = (1.0 - alpha) / (double)n;
+  for (int64_t i = 0; i < k; ++i) {
+    const int32_t v = rows[i];
+    if (v < 0 || v >= n) return OR_EINVAL;
+    double c = 0.0;
+    for (int64_t e = in_off[v]; e < in_off[v + 1]; ++e) {
+      const int32_t u = in_src[e];
+      c = c + R[u] / (double)(out_off[u + 1] - out_off[u]);
+    }
+    out[i] = C0 + alpha * c;
+  }
+  return OR_OK;
+}
+
 /* expandAffected of Alg. 5: for each u with delta_N[u], mark every v in out(u). */
 static void expand_affected(const adjacency *a, uint8_t *dV, const uint8_t *dN) {
   for (int32_t u = 0; u < a->n; ++u)
@@ -235,29 +258,23 @@ static void expand_affected(const adjacency *a, uint8_t *dV, const uint8_t *dN) 
  * trace (may be NULL): (max_iter + 1) x n bytes; row i is delta_V at the
  * start of iteration i (row 0 after the initial marking).
  */
-int oracle_dfp(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, int64_t n_del,
-               const int32_t *del_src, const int32_t *del_dst, int64_t n_ins,
-               const int32_t *ins_src, const double *ranks_prev, double alpha, double tol,
-               double tau_f, double tau_p, int32_t max_iter, int32_t prune, double *ranks,
-               int32_t *iters, double *delta, int64_t *stats, uint8_t *trace) {
-  if (!(alpha > 0.0 && alpha < 1.0) || !(tol >= 0.0) || max_iter <= 0 || !ranks || !ranks_prev)
-    return OR_EINVAL;
-  if ((n_del > 0 && (!del_src || !del_dst)) || (n_ins > 0 && !ins_src)) return OR_EINVAL;
-  adjacency a;
-  int rc = adj_build(&a, n, m, src, dst);
-  if (rc) return rc;
+static int dfp_run(const adjacency *ap, int64_t n_del, const int32_t *del_src,
+                   const int32_t *del_dst, int64_t n_ins, const int32_t *ins_src,
+                   const double *ranks_prev, double alpha, double tol, double tau_f,
+                   double tau_p, int32_t max_iter, int32_t prune, double *ranks, int32_t *iters,
+                   double *delta, int64_t *stats, uint8_t *trace) {
+  const adjacency a = *ap;
+  const int32_t n = a.n;
   for (int32_t u = 0; u < n; ++u)
-    if (a.out_deg[u] == 0) { adj_free(&a); return OR_EINVAL; }
+    if (a.out_deg[u] == 0) return OR_EINVAL;
   for (int64_t i = 0; i < n_del; ++i)
-    if (del_src[i] < 0 || del_src[i] >= n || del_dst[i] < 0 || del_dst[i] >= n) {
-      adj_free(&a); return OR_EINVAL;
-    }
+    if (del_src[i] < 0 || del_src[i] >= n || del_dst[i] < 0 || del_dst[i] >= n) return OR_EINVAL;
   for (int64_t i = 0; i < n_ins; ++i)
-    if (ins_src[i] < 0 || ins_src[i] >= n) { adj_free(&a); return OR_EINVAL; }
+    if (ins_src[i] < 0 || ins_src[i] >= n) return OR_EINVAL;
   double *R = malloc(sizeof(double) * (size_t)n), *Rn = malloc(sizeof(double) * (size_t)n);
   uint8_t *dV = calloc((size_t)n, 1), *dN = calloc((size_t)n, 1), *ever = calloc((size_t)n, 1);
   if (!R || !Rn || !dV || !dN || !ever) {
-    free(R); free(Rn); free(dV); free(dN); free(ever); adj_free(&a); return OR_ENOMEM;
+    free(R); free(Rn); free(dV); free(dN); free(ever); return OR_ENOMEM;
   }
   /* initialise both rank vectors from the previous ranks (Alg. 2) */
   for (int32_t v = 0; v < n; ++v) R[v] = Rn[v] = ranks_prev[v];
@@ -308,8 +325,58 @@ int oracle_dfp(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, int
   if (iters) *iters = it;
   if (delta) *delta = d;
   if (stats) { stats[0] = aff0; stats[1] = affmax; stats[2] = edges; stats[3] = ever_n; }
-  free(R); free(Rn); free(dV); free(dN); free(ever); adj_free(&a);
+  free(R); free(Rn); free(dV); free(dN); free(ever);
   return converged ? OR_OK : OR_NOT_CONVERGED;
+}
+
+static int dfp_args_ok(double alpha, double tol, int32_t max_iter, const double *ranks,
+                       const double *ranks_prev, int64_t n_del, const int32_t *del_src,
+                       const int32_t *del_dst, int64_t n_ins, const int32_t *ins_src) {
+  if (!(alpha > 0.0 && alpha < 1.0) || !(tol >= 0.0) || max_iter <= 0 || !ranks || !ranks_prev)
+    return 0;
+  return !((n_del > 0 && (!del_src || !del_dst)) || (n_ins > 0 && !ins_src));
+}
+
+int oracle_dfp(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, int64_t n_del,
+               const int32_t *del_src, const int32_t *del_dst, int64_t n_ins,
+               const int32_t *ins_src, const double *ranks_prev, double alpha, double tol,
+               double tau_f, double tau_p, int32_t max_iter, int32_t prune, double *ranks,
+               int32_t *iters, double *delta, int64_t *stats, uint8_t *trace) {
+  if (!dfp_args_ok(alpha, tol, max_iter, ranks, ranks_prev, n_del, del_src, del_dst, n_ins,
+                   ins_src))
+    return OR_EINVAL;
+  adjacency a;
+  int rc = adj_build(&a, n, m, src, dst);
+  if (rc) return rc;
+  rc = dfp_run(&a, n_del, del_src, del_dst, n_ins, ins_src, ranks_prev, alpha, tol, tau_f, tau_p,
+               max_iter, prune, ranks, iters, delta, stats, trace);
+  adj_free(&a);
+  return rc;
+}
+
+/* The same DF/DF-P run over a given G^t in both CSR views (int32, rows
+ * ascending), without building an adjacency from an edge list: for graphs
+ * whose edge-list construction is too slow here. */
+int oracle_dfp_csr(int32_t n, const int32_t *in_off, const int32_t *in_src,
+                   const int32_t *out_off, const int32_t *out_tgt, int64_t n_del,
+                   const int32_t *del_src, const int32_t *del_dst, int64_t n_ins,
+                   const int32_t *ins_src, const double *ranks_prev, double alpha, double tol,
+                   double tau_f, double tau_p, int32_t max_iter, int32_t prune, double *ranks,
+                   int32_t *iters, double *delta, int64_t *stats) {
+  if (!dfp_args_ok(alpha, tol, max_iter, ranks, ranks_prev, n_del, del_src, del_dst, n_ins,
+                   ins_src) || !out_tgt)
+    return OR_EINVAL;
+  adjacency a;
+  int rc = adj_wrap_csr(&a, n, in_off, in_src, out_off);
+  if (rc) return rc;
+  a.out_off = malloc(sizeof(int64_t) * ((size_t)n + 1));
+  if (!a.out_off) { free(a.in_off); free(a.out_deg); return OR_ENOMEM; }
+  for (int32_t u = 0; u <= n; ++u) a.out_off[u] = out_off[u];
+  a.out_tgt = (int32_t *)out_tgt;
+  rc = dfp_run(&a, n_del, del_src, del_dst, n_ins, ins_src, ranks_prev, alpha, tol, tau_f, tau_p,
+               max_iter, prune, ranks, iters, delta, stats, NULL);
+  free(a.in_off); free(a.out_deg); free(a.out_off);
+  return rc;
 }
 
 /*

@@ -196,6 +196,69 @@ __global__ __launch_bounds__(kFinalBlock) void k_scan_rows(int *__restrict__ row
   if (threadIdx.x == 0) totals[blockIdx.x] = total;
 }
 
+// The same scan for long rows, in three launches over tiles of kScanTile
+// entries (grid: tiles x rows): tile sums into tsum (ntmax per row), a
+// k_scan_rows pass over tsum, then every tile rescanned from its offset.
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kBlock * kScanItems;
+
+__device__ __forceinline__ int scan_row_len(int stride, const int *dlen) {
+  return dlen ? min(stride, *dlen) : stride;
+}
+
+__global__ __launch_bounds__(kBlock) void k_rows_tile_sums(const int *__restrict__ rows, int stride,
+                                                           const int *__restrict__ dlen,
+                                                           int *__restrict__ tsum, int ntmax) {
+  const int len = scan_row_len(stride, dlen);
+  const int *row = rows + (size_t)blockIdx.y * stride;
+  const int base = blockIdx.x * kScanTile;
+  int s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int i = base + k * kBlock + (int)threadIdx.x;
+    if (i < len) s += row[i];
+  }
+  int total;
+  (void)block_exclusive_scan<kBlock>(s, &total);
+  if (threadIdx.x == 0) tsum[(size_t)blockIdx.y * ntmax + blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kBlock) void k_rows_tile_apply(int *__restrict__ rows, int stride,
+                                                            const int *__restrict__ dlen,
+                                                            const int *__restrict__ tsum,
+                                                            int ntmax) {
+  __shared__ int s_v[kScanTile];
+  const int len = scan_row_len(stride, dlen);
+  int *row = rows + (size_t)blockIdx.y * stride;
+  const int base = blockIdx.x * kScanTile;
+  if (base >= len) return;  // the whole workgroup: before any barrier
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int i = k * kBlock + tid;
+    s_v[i] = base + i < len ? row[base + i] : 0;
+  }
+  __syncthreads();
+  int *mine = s_v + tid * kScanItems;
+  int loc = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) loc += mine[k];
+  int total;
+  int run = block_exclusive_scan<kBlock>(loc, &total) + tsum[(size_t)blockIdx.y * ntmax + blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int x = mine[k];
+    mine[k] = run;
+    run += x;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int i = k * kBlock + tid;
+    if (base + i < len) row[base + i] = s_v[i];
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_part_scatter(const int *__restrict__ off, int n,
                                                          int t1, int t2,
                                                          const int *__restrict__ tile_counts,

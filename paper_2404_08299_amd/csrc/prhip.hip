@@ -365,6 +365,27 @@ int xcd_ranges(Workspace &w, const int *goff, int n, hipStream_t s) {
 // the top class. With `xidx` (the rows' original, ascending indices; needs
 // the ranges in w.xrs) the top class is the die-split class of rows with
 // degree >= xsplit_min_degree; otherwise rows above t2, cut into chunks.
+// Exclusive scan of `nrows` rows of `rows` (row r at rows + r * stride), each
+// min(stride, *dlen) long (dlen a device count, or null), in place; totals[r]
+// gets row r's sum. Rows longer than a few thousand entries are scanned by
+// tiles over the whole chip, with `scratch` (cap ints, not `rows`) holding the
+// tile sums; shorter rows by one workgroup each.
+void scan_rows(int *rows, int nrows, int stride, int *totals, const int *dlen, int *scratch,
+               size_t cap, hipStream_t s) {
+  const int ntmax = (stride + kScanTile - 1) / kScanTile;
+  if (stride <= 8 * kFinalBlock || (size_t)nrows * ntmax > cap || scratch == rows) {
+    hipLaunchKernelGGL(k_scan_rows, dim3(nrows), dim3(kFinalBlock), 0, s, rows, stride, totals,
+                       dlen);
+    return;
+  }
+  hipLaunchKernelGGL(k_rows_tile_sums, dim3(ntmax, nrows), dim3(kBlock), 0, s,
+                     (const int *)rows, stride, dlen, scratch, ntmax);
+  hipLaunchKernelGGL(k_scan_rows, dim3(nrows), dim3(kFinalBlock), 0, s, scratch, ntmax, totals,
+                     (const int *)nullptr);
+  hipLaunchKernelGGL(k_rows_tile_apply, dim3(ntmax, nrows), dim3(kBlock), 0, s, rows, stride,
+                     dlen, (const int *)scratch, ntmax);
+}
+
 int partition(Workspace &w, const int *off, int n, int m, int t1, int t2, int CH, int *hi,
               int slot, int chunk_slot, int *hub_start, int *chunk_hub, hipStream_t s,
               const int *xidx = nullptr, XPlan *xp = nullptr, const int *xrs = nullptr,
@@ -392,8 +413,8 @@ int partition(Workspace &w, const int *off, int n, int m, int t1, int t2, int CH
   const int gb = (int)std::min<size_t>((nb + kBlock - 1) / kBlock, 16 * std::max(1, w.num_cus));
   hipLaunchKernelGGL(k_xsplit_count, dim3(gb), dim3(kBlock), 0, s, off, xidx, (const int *)hi,
                      (const int *)w.counts, slot, xrs, gid, CH, (int)nb, w.xmat);
-  hipLaunchKernelGGL(k_scan_rows, dim3(kXcds + 1), dim3(kFinalBlock), 0, s, w.xmat, (int)nb,
-                     w.xtot, (const int *)(w.counts + slot + 1));
+  scan_rows(w.xmat, kXcds + 1, (int)nb, w.xtot, (const int *)(w.counts + slot + 1), w.tile_counts,
+            kGroups * ntiles_for(w.cap_n), s);
   hipLaunchKernelGGL(k_xsplit_fill, dim3(gb), dim3(kBlock), 0, s, off, xidx, (const int *)hi,
                      w.counts, slot, chunk_slot, xrs, gid, CH, (int)nb,
                      (const int *)w.xmat, (const int *)w.xtot, w.xoff, hub_start, w.xitems);

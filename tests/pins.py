@@ -186,6 +186,22 @@ def pin_static_contraction(lib):
         assert ek <= ALPHA ** k * e0 * (1 + 1e-9), (k, ek, ALPHA ** k * e0)
 
 
+def pin_static_rows_dense(lib):
+    """One Eq. 1 step for listed rows (the sampled check of full-size runs)
+    equals the dense product (1-a)/N + a * A x, row by row, for an arbitrary
+    positive x (not a PageRank iterate), repeated and unordered rows."""
+    g = gg.rmat_graph(9, 8, seed=11)
+    s, d = g.edges()
+    A = dense_A(g.n, s, d)
+    x = np.random.default_rng(3).random(g.n) + 0.1
+    ref = (1 - ALPHA) / g.n + ALPHA * (A @ x)
+    rows = np.concatenate([np.arange(g.n), [g.n - 1, 0, 7, 7]]).astype(np.int32)[::-1]
+    got = oracle.static_rows(g.n, g.in_offsets, g.in_sources, g.out_offsets, x, rows, lib=lib)
+    assert np.abs(got - ref[rows]).max() <= 1e-14 * np.abs(ref).max()
+    assert oracle.static_rows(g.n, g.in_offsets, g.in_sources, g.out_offsets, x,
+                              np.zeros(0, np.int32), lib=lib).size == 0
+
+
 # ---------------------------------------------------------------- DF-P pins
 def _affected_all(n):
     """A marking-only batch whose insertion sources are every vertex:
@@ -311,6 +327,23 @@ def pin_dfp_eq2_one_step(lib):
     assert abs(res.ranks[0] - rc) <= 4e-16 * rc
     assert res.trace[0].tolist() == [1, 1] + [0] * (k - 1)
     assert res.trace[1].tolist() == [1, 1] + [0] * (k - 1)
+
+
+def pin_dfp_csr_input(lib):
+    """DF-P over a given CSR (both views) equals DF-P over the edge list the
+    oracle builds its own adjacency from, bit for bit: the CSR entry only
+    changes where the rows come from. Scrambled IDs, deletions and
+    insertions, DF and DF-P."""
+    g0 = gg.rmat_graph(10, 8, seed=21)
+    s0, d0 = g0.edges()
+    prev = oracle.static(g0.n, s0, d0, tol=1e-12, lib=lib).ranks
+    b = gg.random_batch(g0, 200, seed=4)
+    g1 = gg.apply_batch(g0, b)
+    s1, d1 = g1.edges()
+    for prune in (True, False):
+        a = oracle.dfp(g1.n, s1, d1, b, prev, prune=prune, lib=lib)
+        c = oracle.dfp_csr(g1, b, prev, prune=prune, lib=lib)
+        assert a.iters == c.iters and np.array_equal(a.ranks, c.ranks) and a.stats == c.stats
 
 
 def pin_dfp_accuracy(lib):
@@ -460,8 +493,9 @@ def pin_adjoint_dense_and_fd(lib):
 ALL_PINS = [
     pin_static_dense, pin_static_cycle, pin_static_single_vertex, pin_static_in_star,
     pin_static_out_star, pin_static_local_closed_form, pin_static_invariants,
-    pin_static_contraction, pin_dfp_empty_batch, pin_dfp_eq2_fixed_point,
+    pin_static_contraction, pin_static_rows_dense, pin_dfp_empty_batch, pin_dfp_eq2_fixed_point,
     pin_dfp_frontier_reachability, pin_dfp_initial_marking, pin_dfp_eq2_one_step,
+    pin_dfp_csr_input,
     pin_dfp_accuracy, pin_dt_exact_and_reachability, pin_dt_empty_batch,
     pin_ppr_dense_and_linearity, pin_weighted_dense, pin_adjoint_dense_and_fd,
 ]

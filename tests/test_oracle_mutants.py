@@ -38,6 +38,9 @@ MUTANTS = {
     "adjoint_edge_grad_transposed": ("grad_w[e] = alpha * r[src[e]] * L[dst[e]];", "grad_w[e] = alpha * r[dst[e]] * L[src[e]];"),
     "adjoint_grad_s_undamped": ("grad_s[v] = (1.0 - alpha) * L[v];", "grad_s[v] = L[v];"),
     "dt_closure_one_level": ("while (head < tail) {", "while (0) {"),
+    "rows_outdeg_of_target": ("c = c + R[u] / (double)(out_off[u + 1] - out_off[u]);",
+                              "c = c + R[u] / (double)(out_off[v + 1] - out_off[v]);"),
+    "rows_undamped": ("out[i] = C0 + alpha * c;", "out[i] = C0 + c;"),
     "dt_deletion_target_unmarked": ("{ dV[del_dst[i]] = 1; dN[del_src[i]] = 1; }", "{ dN[del_src[i]] = 1; }"),
 }
 
