@@ -7,12 +7,12 @@
 //  1. keys (row << 32 | col) of the deletions and of the insertions, sorted
 //     (rocPRIM radix sort), duplicates rejected;
 //  2. per-row change counts, new degrees, new offsets (multi-workgroup scan);
-//  3. one pass over the rows: a wavefront owns 64 consecutive rows; its lanes
-//     copy their unchanged short rows, then the wavefront handles its changed
-//     or long rows together: every kept old entry and every insertion goes to
-//     its rank in the merged row, found by binary search over the row's
-//     (sorted) deletions and insertions. A deletion that is not in the row or
-//     an insertion that already is raises the error flag.
+//  3. one pass over the rows: a wavefront owns 64 consecutive rows; it copies
+//     their unchanged short rows edge-parallel, laid end to end, then handles
+//     its changed or long rows together: every kept old entry and every
+//     insertion goes to its rank in the merged row, found by binary search
+//     over the row's (sorted) deletions and insertions. A deletion that is
+//     not in the row or an insertion that already is raises the error flag.
 #include <hip/hip_runtime.h>
 #include <rocprim/device/device_radix_sort.hpp>
 
@@ -25,7 +25,7 @@ namespace prhip_apply {
 constexpr int kBlock = 256;
 constexpr int kWave = 64;
 constexpr int kScanTile = 1024;   // offsets per workgroup in the scan
-constexpr int kShortRow = 64;     // rows up to this long are copied by one lane
+constexpr int kLongRow = 4096;    // longer rows are cut into chunks of this many entries
 
 using u64 = unsigned long long;
 
@@ -180,33 +180,96 @@ __device__ __forceinline__ int count_below(const int *__restrict__ cols, int a, 
   return lo - a;
 }
 
-// Rebuild every row. err bit 4: a deletion not in its row; bit 8: an
-// insertion already in its row. Every write stays inside the row's new range
-// [new_off[r], new_off[r+1]) and below m_new, whatever the batch: an invalid
-// batch leaves unspecified output, never a write out of bounds.
+// Rebuild every row of at most kLongRow entries (longer rows: k_long_rows).
+// err bit 4: a deletion not in its row; bit 8: an insertion already in its
+// row. Every write stays inside the row's new range [new_off[r],
+// new_off[r+1]) and below m_new, whatever the batch: an invalid batch leaves
+// unspecified output, never a write out of bounds.
+__device__ __forceinline__ void put(int *__restrict__ new_cols, int m_new, int *err, int pos, int lo,
+                                    int hi, int c) {
+  if (pos >= lo && pos < hi && pos >= 0 && pos < m_new) new_cols[pos] = c;
+  else atomicOr(err, 32);
+}
+
 __global__ __launch_bounds__(kBlock) void k_rows(const int *__restrict__ off, const int *__restrict__ cols,
                                                  const u64 *__restrict__ dk, int nd, const u64 *__restrict__ ik,
                                                  int ni, const int *__restrict__ dcnt,
                                                  const int *__restrict__ icnt, int n,
                                                  const int *__restrict__ new_off, int m_new,
                                                  int *__restrict__ new_cols, int *err) {
-  auto put = [&](int pos, int lo, int hi, int c) {
-    if (pos >= lo && pos < hi && pos >= 0 && pos < m_new) new_cols[pos] = c;
-    else atomicOr(err, 32);
-  };
   const int lane = threadIdx.x & (kWave - 1);
   const long long nw = (long long)gridDim.x * (kBlock / kWave);
   for (long long wv = (long long)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; wv * kWave < n; wv += nw) {
     const int r = (int)(wv * kWave) + lane;
-    bool special = false;
+    bool special = false, lng = false;
+    int o0 = 0, cnt = 0, no = 0, ne = 0;
     if (r < n) {
-      const int o0 = off[r], o1 = off[r + 1];
-      special = dcnt[r] != 0 || icnt[r] != 0 || o1 - o0 > kShortRow;
-      if (!special) {
-        const int no = new_off[r], ne = new_off[r + 1];
-        for (int i = o0; i < o1; ++i) put(no + (i - o0), no, ne, cols[i]);
+      o0 = off[r];
+      const int o1 = off[r + 1];
+      lng = o1 - o0 > kLongRow;
+      if (!lng) {
+        special = dcnt[r] != 0 || icnt[r] != 0;
+        if (!special) {
+          cnt = o1 - o0;
+          no = new_off[r];
+          ne = new_off[r + 1];
+        }
       }
     }
+    if (__ballot(special || lng) == 0) {
+      // no changed or long row among the 64: their entries are one run with
+      // one shift in both arrays, copied with eight loads per lane in flight
+      int total = cnt;
+      for (int o = kWave / 2; o > 0; o >>= 1) total += __shfl_xor(total, o);
+      const int s0 = __shfl(o0, 0), d0 = __shfl(no, 0), d1 = d0 + total;
+      for (int k0 = 0; k0 < total; k0 += 8 * kWave) {
+        int v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int k = k0 + u * kWave + lane;
+          v[u] = k < total ? cols[s0 + k] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int k = k0 + u * kWave + lane;
+          if (k < total) put(new_cols, m_new, err, d0 + k, d0, d1, v[u]);
+        }
+      }
+      continue;
+    }
+    // Unchanged rows keep their entries, shifted: laid end to end (a
+    // wavefront scan of their lengths) they are copied edge-parallel, four
+    // entries per lane in flight, so a wavefront's loads and stores are
+    // contiguous runs. Entry k of the run belongs to the last row j whose
+    // start excl_j is <= k.
+    int x = cnt;
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int y = __shfl_up(x, o);
+      if (lane >= o) x += y;
+    }
+    const int excl = x - cnt, total = __shfl(x, kWave - 1);
+    for (int k0 = 0; k0 < total; k0 += 4 * kWave) {
+      int dst[4], dlo[4], dhi[4], val[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = min(k0 + u * kWave + lane, total - 1);
+        int lo = 0, hi = kWave;
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (__shfl(excl, mid) <= k) lo = mid;
+          else hi = mid;
+        }
+        const int b = __shfl(excl, lo), s0 = __shfl(o0, lo);
+        dlo[u] = __shfl(no, lo);
+        dhi[u] = __shfl(ne, lo);
+        dst[u] = dlo[u] + (k - b);
+        val[u] = cols[s0 + (k - b)];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (k0 + u * kWave + lane < total) put(new_cols, m_new, err, dst[u], dlo[u], dhi[u], val[u]);
+    }
+    // changed rows, one at a time by the whole wavefront
     unsigned long long mask = __ballot(special);
     while (mask) {
       const int j = __ffsll(mask) - 1;
@@ -222,7 +285,7 @@ __global__ __launch_bounds__(kBlock) void k_rows(const int *__restrict__ off, co
         const int dbelow = nd_r ? count_below_key(dk, da, db, c) : 0;
         if (dbelow < nd_r && col_of(dk[da + dbelow]) == c) continue;  // deleted
         const int ibelow = ni_r ? count_below_key(ik, ia, ib, c) : 0;
-        put(no + (i - o0) - dbelow + ibelow, no, ne, c);
+        put(new_cols, m_new, err, no + (i - o0) - dbelow + ibelow, no, ne, c);
       }
       // insertions
       for (int q = ia + lane; q < ib; q += kWave) {
@@ -230,13 +293,92 @@ __global__ __launch_bounds__(kBlock) void k_rows(const int *__restrict__ off, co
         const int obelow = count_below(cols, o0, o1, c);
         if (obelow < o1 - o0 && cols[o0 + obelow] == c) atomicOr(err, 8);
         const int dbelow = nd_r ? count_below_key(dk, da, db, c) : 0;
-        put(no + obelow - dbelow + (q - ia), no, ne, c);
+        put(new_cols, m_new, err, no + obelow - dbelow + (q - ia), no, ne, c);
       }
       // every deletion must be present
       for (int q = da + lane; q < db; q += kWave) {
         const int c = col_of(dk[q]);
         const int obelow = count_below(cols, o0, o1, c);
         if (!(obelow < o1 - o0 && cols[o0 + obelow] == c)) atomicOr(err, 4);
+      }
+    }
+  }
+}
+
+// rowat[k] = the row holding old entry k * kLongRow, for k < nbk (entries
+// beyond off[n] are never named). Each such entry lies in exactly one row.
+__global__ __launch_bounds__(kBlock) void k_rowat(const int *__restrict__ off, int n, int nbk,
+                                                  int *__restrict__ rowat) {
+  for (int r = blockIdx.x * kBlock + threadIdx.x; r < n; r += gridDim.x * kBlock) {
+    const int o0 = off[r], o1 = off[r + 1];
+    for (long long k = ((long long)o0 + kLongRow - 1) / kLongRow; k * kLongRow < o1 && k < nbk; ++k)
+      rowat[k] = r;
+  }
+}
+
+// Rows longer than kLongRow, cut into the chunks [b * kLongRow, (b+1) *
+// kLongRow) of the old entries, one workgroup per chunk. A long row
+// overlapping chunk b holds entry b * kLongRow or starts inside the chunk and
+// then holds entry (b + 1) * kLongRow: it is rowat[b] or rowat[b + 1]. The
+// workgroup of the chunk where a changed row starts also places its
+// insertions and checks its deletions.
+__global__ __launch_bounds__(kBlock) void k_long_rows(const int *__restrict__ off, const int *__restrict__ cols,
+                                                      const u64 *__restrict__ dk, int nd,
+                                                      const u64 *__restrict__ ik, int ni,
+                                                      const int *__restrict__ dcnt,
+                                                      const int *__restrict__ icnt, int n,
+                                                      const int *__restrict__ rowat, int nbk,
+                                                      const int *__restrict__ new_off, int m_new,
+                                                      int *__restrict__ new_cols, int *err) {
+  const int tid = threadIdx.x;
+  for (int b = blockIdx.x; b < nbk; b += gridDim.x) {
+    const long long c0 = (long long)b * kLongRow, c1 = c0 + kLongRow;
+    const int cand[2] = {rowat[b], b + 1 < nbk ? rowat[b + 1] : -1};
+    for (int t = 0; t < 2; ++t) {
+      const int L = cand[t];
+      if (L < 0 || L >= n || (t == 1 && L == cand[0])) continue;
+      const int o0 = off[L], o1 = off[L + 1];
+      if (o1 - o0 <= kLongRow) continue;
+      const int lo = (int)max((long long)o0, c0), hi = (int)min((long long)o1, c1);
+      const int no = new_off[L], ne = new_off[L + 1];
+      const int nd_r = dcnt[L], ni_r = icnt[L];
+      if (nd_r == 0 && ni_r == 0) {
+        // unchanged: a shifted copy, sixteen entries per thread in flight
+        int v[kLongRow / kBlock];
+#pragma unroll
+        for (int u = 0; u < kLongRow / kBlock; ++u) {
+          const int i = lo + u * kBlock + tid;
+          v[u] = i < hi ? cols[i] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < kLongRow / kBlock; ++u) {
+          const int i = lo + u * kBlock + tid;
+          if (i < hi) put(new_cols, m_new, err, no + (i - o0), no, ne, v[u]);
+        }
+        continue;
+      }
+      const int da = nd_r ? first_of_row(dk, nd, L) : 0, db = da + nd_r;
+      const int ia = ni_r ? first_of_row(ik, ni, L) : 0, ib = ia + ni_r;
+      for (int i = lo + tid; i < hi; i += kBlock) {
+        const int c = cols[i];
+        const int dbelow = nd_r ? count_below_key(dk, da, db, c) : 0;
+        if (dbelow < nd_r && col_of(dk[da + dbelow]) == c) continue;  // deleted
+        const int ibelow = ni_r ? count_below_key(ik, ia, ib, c) : 0;
+        put(new_cols, m_new, err, no + (i - o0) - dbelow + ibelow, no, ne, c);
+      }
+      if (o0 >= c0 && o0 < c1) {
+        for (int q = ia + tid; q < ib; q += kBlock) {
+          const int c = col_of(ik[q]);
+          const int obelow = count_below(cols, o0, o1, c);
+          if (obelow < o1 - o0 && cols[o0 + obelow] == c) atomicOr(err, 8);
+          const int dbelow = nd_r ? count_below_key(dk, da, db, c) : 0;
+          put(new_cols, m_new, err, no + obelow - dbelow + (q - ia), no, ne, c);
+        }
+        for (int q = da + tid; q < db; q += kBlock) {
+          const int c = col_of(dk[q]);
+          const int obelow = count_below(cols, o0, o1, c);
+          if (!(obelow < o1 - o0 && cols[o0 + obelow] == c)) atomicOr(err, 4);
+        }
       }
     }
   }
@@ -254,13 +396,15 @@ int grid_for(long long work) {
 using namespace prhip_apply;
 
 // See apply.h.
-int prhip_apply_view(int n, const int *off, const int *cols, int m_new, const int *del_row,
+int prhip_apply_view(int n, const int *off, const int *cols, int m_old, int m_new, const int *del_row,
                      const int *del_col, int nd, const int *ins_row, const int *ins_col, int ni,
                      int *new_off, int *new_cols, hipStream_t s, int *err_out, const char **what) {
   *err_out = 0;
   *what = nullptr;
   const int nt = (n + kScanTile - 1) / kScanTile;
-  // scratch: keys in/out for both lists, counts, degrees, tile sums, error word
+  const int nbk = (int)(((long long)m_old + kLongRow - 1) / kLongRow);  // long-row chunks
+  // scratch: keys in/out for both lists, counts, degrees, tile sums, error
+  // word, the row of every chunk start
   size_t bytes = 0;
   u64 *dk_in = nullptr, *dk = nullptr, *ik_in = nullptr, *ik = nullptr;
   int *dcnt = nullptr, *icnt = nullptr, *deg = nullptr, *tsum = nullptr, *err = nullptr;
@@ -282,7 +426,7 @@ int prhip_apply_view(int n, const int *off, const int *cols, int m_new, const in
       (e = hipMallocAsync((void **)&dk, (size_t)(nd + 1) * sizeof(u64), s)) != hipSuccess ||
       (e = hipMallocAsync((void **)&ik_in, (size_t)(ni + 1) * sizeof(u64), s)) != hipSuccess ||
       (e = hipMallocAsync((void **)&ik, (size_t)(ni + 1) * sizeof(u64), s)) != hipSuccess ||
-      (e = hipMallocAsync((void **)&dcnt, ((size_t)3 * n + nt + 16) * sizeof(int), s)) != hipSuccess ||
+      (e = hipMallocAsync((void **)&dcnt, ((size_t)3 * n + nt + 16 + nbk + 1) * sizeof(int), s)) != hipSuccess ||
       (e = hipMallocAsync(&tmp, tmp_b + 16, s)) != hipSuccess)
     return done(e, "scratch allocation");
   (void)bytes;
@@ -290,8 +434,10 @@ int prhip_apply_view(int n, const int *off, const int *cols, int m_new, const in
   deg = icnt + n;
   tsum = deg + n;
   err = tsum + nt + 8;
+  int *rowat = err + 8;
   if ((e = hipMemsetAsync(dcnt, 0, (size_t)2 * n * sizeof(int), s)) != hipSuccess ||
-      (e = hipMemsetAsync(err, 0, sizeof(int), s)) != hipSuccess)
+      (e = hipMemsetAsync(err, 0, sizeof(int), s)) != hipSuccess ||
+      (e = hipMemsetAsync(rowat, 0xff, (size_t)(nbk + 1) * sizeof(int), s)) != hipSuccess)
     return done(e, "memset");
   if (nd > 0) {
     hipLaunchKernelGGL(k_keys, dim3(grid_for(nd)), dim3(kBlock), 0, s, del_row, del_col, nd, n, dk_in, err);
@@ -318,6 +464,12 @@ int prhip_apply_view(int n, const int *off, const int *cols, int m_new, const in
   hipLaunchKernelGGL(k_rows, dim3(grid_for((long long)n)), dim3(kBlock), 0, s, off, cols, (const u64 *)dk, nd,
                      (const u64 *)ik, ni, (const int *)dcnt, (const int *)icnt, n, (const int *)new_off,
                      m_new, new_cols, err);
+  if (nbk > 0) {
+    hipLaunchKernelGGL(k_rowat, dim3(grid_for((long long)n)), dim3(kBlock), 0, s, off, n, nbk, rowat);
+    hipLaunchKernelGGL(k_long_rows, dim3(nbk < 65536 ? nbk : 65536), dim3(kBlock), 0, s, off, cols,
+                       (const u64 *)dk, nd, (const u64 *)ik, ni, (const int *)dcnt, (const int *)icnt, n,
+                       (const int *)rowat, nbk, (const int *)new_off, m_new, new_cols, err);
+  }
   if ((e = hipGetLastError()) != hipSuccess) return done(e, "kernel launch");
   int h_err = 0;
   if ((e = hipMemcpyAsync(&h_err, err, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess ||

@@ -1321,12 +1321,12 @@ int pr_apply_batch(const pr_csr *old, const pr_edges *deletions, const pr_edges 
   int err = 0;
   const char *what = nullptr;
   // in view: rows are targets, entries sources
-  int e = prhip_apply_view(old->n, old->in_offsets, old->in_sources, out->m, dd, ds, nd, id, is, ni,
+  int e = prhip_apply_view(old->n, old->in_offsets, old->in_sources, old->m, out->m, dd, ds, nd, id, is, ni,
                            out->in_offsets, out->in_sources, t_stream, &err, &what);
   if (e) return fail(PR_EHIP, std::string("pr_apply_batch: ") + (what ? what : "") + ": " +
                                   hipGetErrorString((hipError_t)e));
   if (!err && outview) {
-    e = prhip_apply_view(old->n, old->out_offsets, old->out_targets, out->m, ds, dd, nd, is, id, ni,
+    e = prhip_apply_view(old->n, old->out_offsets, old->out_targets, old->m, out->m, ds, dd, nd, is, id, ni,
                          out->out_offsets, out->out_targets, t_stream, &err, &what);
     if (e) return fail(PR_EHIP, std::string("pr_apply_batch: ") + (what ? what : "") + ": " +
                                     hipGetErrorString((hipError_t)e));

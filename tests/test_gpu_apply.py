@@ -62,6 +62,26 @@ def test_hub_rows_empty_batch_and_in_view_only():
     check(g, b, out_view=False)
 
 
+def test_rows_over_many_chunks():
+    """Rows of 20000 entries span several 4096-entry chunks of the long-row
+    pass: an unchanged in-hub, and an out-hub whose deletions and insertions
+    fall in different chunks, plus a changed row that starts inside a chunk."""
+    k = 20000
+    hub_in = np.arange(1, k + 1)
+    hub_out = np.arange(k + 1, 2 * k + 1)
+    src = np.concatenate([hub_in, np.zeros(k, np.int64), [1] * 4500]).astype(np.int32)
+    dst = np.concatenate([np.zeros(k, np.int64), hub_out, np.arange(2 * k + 2, 2 * k + 4502)]).astype(np.int32)
+    g = gg.from_edges(2 * k + 4502, src, dst)
+    ins_dst = np.array([1, 5, 4100, 9000, 2 * k + 1], np.int32)  # out-row 0: new targets (absent)
+    del_dst = np.array([k + 1, k + 4097, k + 9000, 2 * k], np.int32)
+    b = gg.Batch(np.concatenate([np.zeros(del_dst.size, np.int32), [1, 1]]).astype(np.int32),
+                 np.concatenate([del_dst, [2 * k + 2, 2 * k + 4000]]).astype(np.int32),
+                 np.concatenate([np.zeros(ins_dst.size, np.int32), [1]]).astype(np.int32),
+                 np.concatenate([ins_dst, [3]]).astype(np.int32))
+    check(g, b)
+    check(g, gg.Batch.empty())
+
+
 def test_temporal_chain_on_device():
     g0, steps = gg.temporal_stream(20000, 300000, seed=9, batches=5)
     dg = prhip.DeviceGraph.from_host(g0)

@@ -132,3 +132,16 @@ def test_dfp_full_size_vs_static(full, j):
     err = float((d.ranks - s.ranks).abs().max())
     print(f"DF-P {FRACS[j]:g}|E|: {d.iterations} iterations, |DF-P - Static| {err:.2e}", flush=True)
     assert d.converged and err <= 1e-8
+
+
+def test_apply_full_size_vs_host(full):
+    """The batch applied on the device (both views) equals the host merge at
+    scale 24, where rows reach 2.4e5 entries, for the largest decade."""
+    g, dg, _ = full
+    b = batch_of(g, len(FRACS) - 1)
+    new = prhip.apply_batch(dg, prhip.DeviceBatch.from_host(b))
+    h = gg.apply_batch(g, b)
+    assert new.m == h.m
+    for dev, host in ((new.in_offsets, h.in_offsets), (new.in_sources, h.in_sources),
+                      (new.out_offsets, h.out_offsets), (new.out_targets, h.out_targets)):
+        assert np.array_equal(dev.cpu().numpy(), host)
