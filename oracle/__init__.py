@@ -72,13 +72,13 @@ def _bind(lib):
                                     c.c_double, c.c_double, c.c_int32, _F64P, _F64P, _I32P, _F64P]
     lib.oracle_adjoint.argtypes = [c.c_int32, c.c_int64, _I32P, _I32P, _F64P, _F64P, _F64P,
                                    c.c_double, c.c_double, c.c_int32, _F64P, _F64P, _F64P, _I32P]
-    lib.oracle_static_rows.argtypes = [c.c_int32, _I32P, _I32P, _I32P, _F64P, c.c_double,
-                                       c.c_int64, _I32P, _F64P]
+    lib.oracle_pull_rows.argtypes = [c.c_int32, _I32P, _I32P, _I32P, _F64P, _F64P, c.c_int32,
+                                     _F64P, c.c_double, c.c_int64, _I32P, _I32P, _F64P]
     lib.oracle_dfp_csr.argtypes = [c.c_int32, _I32P, _I32P, _I32P, _I32P, c.c_int64, _I32P, _I32P,
                                    c.c_int64, _I32P, _F64P, c.c_double, c.c_double, c.c_double,
                                    c.c_double, c.c_int32, c.c_int32, _F64P, _I32P, _F64P, _I64P]
     for f in (lib.oracle_static, lib.oracle_static_csr, lib.oracle_dfp, lib.oracle_dt, lib.oracle_ppr,
-              lib.oracle_weighted, lib.oracle_adjoint, lib.oracle_static_rows, lib.oracle_dfp_csr):
+              lib.oracle_weighted, lib.oracle_adjoint, lib.oracle_pull_rows, lib.oracle_dfp_csr):
         f.restype = c.c_int
     return lib
 
@@ -158,21 +158,33 @@ def static_csr(n, in_offsets, in_sources, out_offsets, alpha=ALPHA, tol=TOL,
     return Result(r, it.value, d.value, rc), sec.value
 
 
-def static_rows(n, in_offsets, in_sources, out_offsets, ranks, rows, alpha=ALPHA, lib=None):
-    """One Eq. 1 update from `ranks` for the listed rows only (sources in
-    ascending order), over a given in-CSR and out-offsets: a sample of one
-    step of an iteration on a graph too large for the full oracle here."""
+def pull_rows(n, in_offsets, in_sources, out_offsets, ranks, rows, cols=None, weights=None,
+              teleport=None, alpha=ALPHA, lib=None):
+    """One update of the pull iteration for listed rows (and vectors `cols`
+    of a vertex-major ranks[n][k]) only, over a given in-CSR: Eq. 1 by
+    default, the weighted forward with per-in-edge `weights`, personalised
+    PageRank with a teleport[n][k]. A sample of one step of an iteration on a
+    graph too large for the full oracle here."""
     lib = lib or load()
     io, pio = _i32(in_offsets)
     isrc, pis = _i32(in_sources)
-    oo, poo = _i32(out_offsets)
-    r, pr = _f64(ranks)
+    oo, poo = (None, None) if out_offsets is None else _i32(out_offsets)
+    r = np.ascontiguousarray(ranks, dtype=np.float64)
+    ld = 1 if r.ndim == 1 else r.shape[1]
     rows, prow = _i32(rows)
+    cl, pcl = (None, None) if cols is None else _i32(cols)
+    w, pw = (None, None) if weights is None else _f64(weights)
+    t, pt = (None, None) if teleport is None else _f64(teleport)
     out = np.empty(rows.size, np.float64)
-    rc = lib.oracle_static_rows(n, pio, pis, poo, pr, alpha, rows.size, prow,
-                                out.ctypes.data_as(_F64P))
-    _check(rc, "oracle_static_rows")
+    rc = lib.oracle_pull_rows(n, pio, pis, poo, pw, r.ctypes.data_as(_F64P), ld, pt, alpha,
+                              rows.size, prow, pcl, out.ctypes.data_as(_F64P))
+    _check(rc, "oracle_pull_rows")
     return out
+
+
+def static_rows(n, in_offsets, in_sources, out_offsets, ranks, rows, alpha=ALPHA, lib=None):
+    """One Eq. 1 update from `ranks` for the listed rows only."""
+    return pull_rows(n, in_offsets, in_sources, out_offsets, ranks, rows, alpha=alpha, lib=lib)
 
 
 def dfp(n, src, dst, batch, ranks_prev, alpha=ALPHA, tol=TOL, tau_f=TAU_F, tau_p=TAU_P,

@@ -213,25 +213,36 @@ int oracle_static_csr(int32_t n, const int32_t *in_off, const int32_t *in_src,
   return rc;
 }
 
-/* One update of Eq. 1 for the listed rows only, from the given R:
- *   out[i] = (1 - alpha)/|V| + alpha * sum_{u in in(rows[i])} R[u]/|out(u)|,
- * sources in ascending order, as in the Static iteration. For graphs too
- * large for the full iteration here: a sample of one step of a long run. */
-int oracle_static_rows(int32_t n, const int32_t *in_off, const int32_t *in_src,
-                       const int32_t *out_off, const double *R, double alpha, int64_t k,
-                       const int32_t *rows, double *out) {
-  if (n <= 0 || !in_off || !in_src || !out_off || !R || k < 0 || (k && (!rows || !out)))
+/* One update of a pull iteration for listed (row, vector) pairs only, from
+ * the given R (n x ld, vertex-major; vector j is column j):
+ *   out[i] = t + alpha * sum_{u in in(v)} x_u,  v = rows[i], j = cols ? cols[i] : 0,
+ *   x_u = w ? w[e] * R[u][j] : R[u][j] / |out(u)|  (e the in-edge u -> v, in
+ *         in-CSR order),
+ *   t = s ? (1 - alpha) * s[v][j] : (1 - alpha)/|V|,
+ * sources in ascending order, as in the full iterations: Eq. 1 (Static),
+ * personalised PageRank (s per vector) and the weighted forward (w per
+ * edge). For graphs too large for the full iteration here: a sample of one
+ * step of a long run. */
+int oracle_pull_rows(int32_t n, const int32_t *in_off, const int32_t *in_src,
+                     const int32_t *out_off, const double *w, const double *R, int32_t ld,
+                     const double *s, double alpha, int64_t k, const int32_t *rows,
+                     const int32_t *cols, double *out) {
+  if (n <= 0 || !in_off || !in_src || (!w && !out_off) || !R || ld <= 0 || k < 0 ||
+      (k && (!rows || !out)))
     return OR_EINVAL;
   const double C0 = (1.0 - alpha) / (double)n;
   for (int64_t i = 0; i < k; ++i) {
-    const int32_t v = rows[i];
-    if (v < 0 || v >= n) return OR_EINVAL;
+    const int32_t v = rows[i], j = cols ? cols[i] : 0;
+    if (v < 0 || v >= n || j < 0 || j >= ld) return OR_EINVAL;
     double c = 0.0;
     for (int64_t e = in_off[v]; e < in_off[v + 1]; ++e) {
       const int32_t u = in_src[e];
-      c = c + R[u] / (double)(out_off[u + 1] - out_off[u]);
+      const double x = R[(size_t)u * (size_t)ld + (size_t)j];
+      if (w) c = c + w[e] * x;
+      else c = c + x / (double)(out_off[u + 1] - out_off[u]);
     }
-    out[i] = C0 + alpha * c;
+    const double t = s ? (1.0 - alpha) * s[(size_t)v * (size_t)ld + (size_t)j] : C0;
+    out[i] = t + alpha * c;
   }
   return OR_OK;
 }

@@ -202,6 +202,35 @@ def pin_static_rows_dense(lib):
                               np.zeros(0, np.int32), lib=lib).size == 0
 
 
+def pin_pull_rows_weighted_and_ppr_dense(lib):
+    """The same row step with per-in-edge weights, and with K teleport vectors
+    (sampled (row, vector) pairs of a vertex-major [n][K] iterate): equal to
+    the dense products (1-a) S[:, j] + a * A_w X[:, j] and (1-a) S[:, j] +
+    a * A X[:, j], column by column."""
+    g = gg.rmat_graph(8, 8, seed=12)
+    rng = np.random.default_rng(5)
+    dst = np.repeat(np.arange(g.n), g.in_degree())
+    src = g.in_sources
+    w = rng.random(g.m) + 0.05
+    K = 3
+    X = rng.random((g.n, K)) + 0.1
+    S = rng.random((g.n, K))
+    rows = rng.integers(0, g.n, 300).astype(np.int32)
+    cols = rng.integers(0, K, 300).astype(np.int32)
+    Aw = dense_A(g.n, src, dst, w)
+    A = dense_A(g.n, src, dst)
+    for weights, M in ((w, Aw), (None, A)):
+        ref = (1 - ALPHA) * S + ALPHA * (M @ X)
+        got = oracle.pull_rows(g.n, g.in_offsets, g.in_sources, g.out_offsets, X, rows, cols=cols,
+                               weights=weights, teleport=S, lib=lib)
+        assert np.abs(got - ref[rows, cols]).max() <= 1e-14 * np.abs(ref).max()
+    # weighted, one vector, uniform teleport term
+    got = oracle.pull_rows(g.n, g.in_offsets, g.in_sources, None, X[:, 1].copy(), rows,
+                           weights=w, lib=lib)
+    ref = (1 - ALPHA) / g.n + ALPHA * (Aw @ X[:, 1])
+    assert np.abs(got - ref[rows]).max() <= 1e-14 * np.abs(ref).max()
+
+
 # ---------------------------------------------------------------- DF-P pins
 def _affected_all(n):
     """A marking-only batch whose insertion sources are every vertex:
@@ -493,7 +522,8 @@ def pin_adjoint_dense_and_fd(lib):
 ALL_PINS = [
     pin_static_dense, pin_static_cycle, pin_static_single_vertex, pin_static_in_star,
     pin_static_out_star, pin_static_local_closed_form, pin_static_invariants,
-    pin_static_contraction, pin_static_rows_dense, pin_dfp_empty_batch, pin_dfp_eq2_fixed_point,
+    pin_static_contraction, pin_static_rows_dense, pin_pull_rows_weighted_and_ppr_dense,
+    pin_dfp_empty_batch, pin_dfp_eq2_fixed_point,
     pin_dfp_frontier_reachability, pin_dfp_initial_marking, pin_dfp_eq2_one_step,
     pin_dfp_csr_input,
     pin_dfp_accuracy, pin_dt_exact_and_reachability, pin_dt_empty_batch,

@@ -38,9 +38,12 @@ MUTANTS = {
     "adjoint_edge_grad_transposed": ("grad_w[e] = alpha * r[src[e]] * L[dst[e]];", "grad_w[e] = alpha * r[dst[e]] * L[src[e]];"),
     "adjoint_grad_s_undamped": ("grad_s[v] = (1.0 - alpha) * L[v];", "grad_s[v] = L[v];"),
     "dt_closure_one_level": ("while (head < tail) {", "while (0) {"),
-    "rows_outdeg_of_target": ("c = c + R[u] / (double)(out_off[u + 1] - out_off[u]);",
-                              "c = c + R[u] / (double)(out_off[v + 1] - out_off[v]);"),
-    "rows_undamped": ("out[i] = C0 + alpha * c;", "out[i] = C0 + c;"),
+    "rows_outdeg_of_target": ("else c = c + x / (double)(out_off[u + 1] - out_off[u]);",
+                              "else c = c + x / (double)(out_off[v + 1] - out_off[v]);"),
+    "rows_undamped": ("out[i] = t + alpha * c;", "out[i] = t + c;"),
+    "rows_teleport_vector_major": ("(1.0 - alpha) * s[(size_t)v * (size_t)ld + (size_t)j] : C0;",
+                                   "(1.0 - alpha) * s[(size_t)j * (size_t)n + (size_t)v] : C0;"),
+    "rows_weight_ignored": ("if (w) c = c + w[e] * x;", "if (w) c = c + x;"),
     "dt_deletion_target_unmarked": ("{ dV[del_dst[i]] = 1; dN[del_src[i]] = 1; }", "{ dN[del_src[i]] = 1; }"),
 }
 
