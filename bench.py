@@ -188,8 +188,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
-              f"(the method is single-GPU; sharding is described in DESIGN.md)", file=sys.stderr)
+        print(f"bench.py: the path runs on one GPU; --gpus {args.gpus} is not supported",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
