@@ -174,6 +174,8 @@ def main():
     ap.add_argument("--batch-graphs", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="run the batched leg at the default tuning instead of autotuning it")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the untimed comparison runs (single calls vs batched)")
     ap.add_argument("--cpu-iters", type=int, default=8)
@@ -274,6 +276,18 @@ def main():
         aux["bouts"] = [torch.empty(g.n, dtype=torch.float64, device="cuda") for g in bgs]
         log(f"{len(bgs)} batched graphs: N={sum(g.n for g in bgs)} M={sum(g.m for g in bgs)} "
             f"({time.time() - t:.1f} s)")
+        aux["btune"] = {}
+        if not args.no_tune:
+            # degree-bucket thresholds of the batched call picked by the autotuner
+            # (coordinate descent, each candidate timed at two iteration caps)
+            import tempfile
+            from paper_2404_08299_amd import autotune
+            t = time.time()
+            with tempfile.TemporaryDirectory() as td:
+                aux["btune"] = autotune.tune_batched(bgs, expected_iters=80, refresh=True,
+                                                     cache_path=os.path.join(td, "tuning.json"))
+            prhip.set_tuning()
+            log(f"batched autotune: {aux['btune']} ({time.time() - t:.1f} s)")
     torch.cuda.synchronize()
 
     # R^{t-1}: Static on G^{t-1} (untimed)
@@ -314,9 +328,11 @@ def main():
                 other["ppr_ms"].append((t1 - t0) * 1e3)
                 other["ppr_iters"].append(int(its.max()))
         if "batched" in legs:
+            prhip.set_tuning(**aux["btune"])
             t0 = time.perf_counter()
             _, its = prhip.static_batched(aux["bgs"], outs=aux["bouts"])
             t1 = time.perf_counter()
+            prhip.set_tuning()
             if record:
                 other["batched_ms"].append((t1 - t0) * 1e3)
                 other["batched_iters"].append(int(its.max()))
@@ -418,7 +434,8 @@ def main():
         bm = float(np.mean(other["batched_ms"]))
         out["batched"] = {"graphs": len(aux["bgs"]), "n": sum(g.n for g in aux["bgs"]),
                           "m": sum(g.m for g in aux["bgs"]), "ms": round(bm, 3),
-                          "max_iters": other["batched_iters"][0]}
+                          "max_iters": other["batched_iters"][0],
+                          "tuning": aux["btune"] or "default"}
     if "adjoint" in legs:
         out["adjoint"] = {"workload": f"weighted_rmat{args.aux_scale}_ef16_1024_targets",
                           "forward_ms": round(float(np.mean(other["fw_ms"])), 3),
@@ -429,10 +446,14 @@ def main():
     # ------------------------------------------------------------ untimed comparisons
     if not args.no_compare:
         if "batched" in legs:
+            # the plain per-graph forward: pr_static on each graph, default tuning
             _, t_single = timed(lambda: [prhip.static(g) for g in aux["bgs"]])
+            # at the batched call's tuning, single calls give the same bits
+            prhip.set_tuning(**aux["btune"])
             ref, _ = prhip.static_batched(aux["bgs"], outs=aux["bouts"])
             same = all(torch.equal(prhip.static(g).ranks, r)
                        for g, r in zip(aux["bgs"][:8], ref.ranks[:8]))
+            prhip.set_tuning()
             out["batched"].update(sum_of_single_calls_ms=round(t_single, 3),
                                   speedup=round(t_single / out["batched"]["ms"], 2),
                                   bitwise_equal_to_single_calls=same)
