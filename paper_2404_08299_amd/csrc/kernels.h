@@ -1365,6 +1365,87 @@ __global__ __launch_bounds__(kBlock) void k_map_sources(const int *__restrict__ 
     st_nt(dst + e, newid[ld_nt(src + e)]);
 }
 
+// The same renumbering split by the die-split plan. Rows with at least T
+// in-edges are mapped item by item, list x by the workgroups on die x (the
+// items of list x have their sources in range x, so the newid entries a die
+// reads are that range's eighth of the table, as the rank kernel's gathers
+// are). A wavefront loads 64 items, one per lane, and maps them one after
+// the other with all its lanes.
+__global__ __launch_bounds__(kBlock) void k_map_split(const int4 *__restrict__ xitems,
+                                                      const int *__restrict__ xoff,
+                                                      const int *__restrict__ src,
+                                                      const int *__restrict__ newid,
+                                                      int *__restrict__ dst) {
+  const int B = gridDim.x, lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const int x0 = B >= kXcds ? (int)blockIdx.x % kXcds : (int)blockIdx.x;
+  const int xstep = B >= kXcds ? kXcds : B;
+  const int loc = B >= kXcds ? (int)blockIdx.x / kXcds : 0;
+  const int nloc = B >= kXcds ? (B - 1 - x0) / kXcds + 1 : 1;
+  const long long Wx = (long long)nloc * kWavesPerBlock * kWave;
+  for (int x = x0; x < kXcds; x += xstep) {
+    const int end = xoff[x + 1];
+    for (long long j0 = xoff[x] + (long long)(loc * kWavesPerBlock + wid) * kWave; j0 < end;
+         j0 += Wx) {
+      const long long j = j0 + lane;
+      const int4 it = j < end ? xitems[j] : make_int4(0, 0, 0, 0);
+      const int cnt = (int)min((long long)kWave, end - j0);
+      for (int q = 0; q < cnt; ++q) {
+        const int e0 = __shfl(it.y, q), e1 = __shfl(it.z, q);
+        for (int e = e0 + lane; e < e1; e += kWave) st_nt(dst + e, newid[ld_nt(src + e)]);
+      }
+    }
+  }
+}
+
+// Rows with fewer than T in-edges: a wavefront takes 64 consecutive rows.
+// When none of them is long their entries are one contiguous run; otherwise
+// the short rows are laid end to end (a scan of their lengths) and entry k
+// belongs to the last row whose start excl_j is <= k (a cross-lane binary
+// search). Either way the loads of a wavefront are contiguous runs.
+__global__ __launch_bounds__(kBlock) void k_map_short(const int *__restrict__ in_off,
+                                                      const int *__restrict__ src, int n, int T,
+                                                      const int *__restrict__ newid,
+                                                      int *__restrict__ dst) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const long long nw = (long long)gridDim.x * kWavesPerBlock;
+  for (long long wv = (long long)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; wv * kWave < n;
+       wv += nw) {
+    const int r = (int)(wv * kWave) + lane;
+    int e0 = 0, cnt = 0;
+    bool lng = false;
+    if (r < n) {
+      e0 = in_off[r];
+      const int d = in_off[r + 1] - e0;
+      lng = d >= T;
+      if (!lng) cnt = d;
+    }
+    int x = cnt;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int y = __shfl_up(x, o);
+      if (lane >= o) x += y;
+    }
+    const int excl = x - cnt, total = __shfl(x, kWave - 1);
+    if (__ballot(lng) == 0) {
+      const int base = __shfl(e0, 0);
+      for (int k = lane; k < total; k += kWave) st_nt(dst + base + k, newid[ld_nt(src + base + k)]);
+      continue;
+    }
+    for (int k0 = 0; k0 < total; k0 += kWave) {
+      const int k = min(k0 + lane, total - 1);
+      int lo = 0, hi = kWave;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (__shfl(excl, mid) <= k) lo = mid;
+        else hi = mid;
+      }
+      const int e = __shfl(e0, lo) + (k - __shfl(excl, lo));
+      const int u = ld_nt(src + e);
+      if (k0 + lane < total) st_nt(dst + e, newid[u]);
+    }
+  }
+}
+
 // Count of affected vertices (profiling only).
 __global__ __launch_bounds__(kBlock) void k_count_flags(const uint8_t *__restrict__ f, int n,
                                                         Ctrl *ctrl, int slot) {

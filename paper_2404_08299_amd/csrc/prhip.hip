@@ -431,9 +431,14 @@ struct Locality {
   const int *pos;
   const int *src;
 };
+// With a die-split plan `xp` over the rows of row_off (those with at least T
+// entries, ranges rs), the split rows are mapped on the die that owns each
+// segment and the shorter rows by k_map_short; otherwise one edge-parallel
+// pass maps every entry.
 int locality(Workspace &w, int n, int m, const int *group_off, const int *idx,
              const pr_tuning &tn, bool allowed, hipStream_t s, Locality *out,
-             const int *rs = nullptr) {
+             const int *rs = nullptr, const XPlan *xp = nullptr, const int *row_off = nullptr,
+             int T = 0) {
   const bool on = allowed && (tn.relabel > 0 || (tn.relabel < 0 && n >= (1 << 20)));
   if (!on) {
     *out = Locality{nullptr, idx};
@@ -446,9 +451,18 @@ int locality(Workspace &w, int n, int m, const int *group_off, const int *idx,
                      w.group_totals, (const int *)nullptr);
   hipLaunchKernelGGL(k_group_scatter, dim3(nt), dim3(kBlock), 0, s, group_off, n,
                      (const int *)w.tile_counts, (const int *)w.group_totals, nt, rs, w.newid);
-  const int mb = std::min((m + kBlock - 1) / kBlock, 8 * std::max(1, w.num_cus) * 4);
-  hipLaunchKernelGGL(k_map_sources, dim3(mb), dim3(kBlock), 0, s, idx, m, (const int *)w.newid,
-                     w.src_p);
+  if (xp && xp->items && rs && row_off && T > 0) {
+    const int gs = kXcds * 4 * std::max(1, w.num_cus);
+    hipLaunchKernelGGL(k_map_split, dim3(gs), dim3(kBlock), 0, s, (const int4 *)xp->items,
+                       (const int *)xp->off, idx, (const int *)w.newid, w.src_p);
+    const int gr = (int)std::min<long long>(((long long)n + kBlock - 1) / kBlock, 65536);
+    hipLaunchKernelGGL(k_map_short, dim3(gr), dim3(kBlock), 0, s, row_off, idx, n, T,
+                       (const int *)w.newid, w.src_p);
+  } else {
+    const int mb = std::min((m + kBlock - 1) / kBlock, 8 * std::max(1, w.num_cus) * 4);
+    hipLaunchKernelGGL(k_map_sources, dim3(mb), dim3(kBlock), 0, s, idx, m, (const int *)w.newid,
+                       w.src_p);
+  }
   LAUNCH_TRY();
   *out = Locality{w.newid, w.src_p};
   return PR_OK;
@@ -570,7 +584,8 @@ int run_pull(const PullProblem &P, double alpha, double tol, int max_iter, doubl
   if (rc) return rc;
   Locality loc;
   if ((rc = locality(w, n, P.m, P.group_off, P.row_idx, tn, P.relabel, s, &loc,
-                     xs ? w.xrs : nullptr)))
+                     xs ? w.xrs : nullptr, &xp, P.row_off,
+                     std::max(xsplit_min_degree(tn), tn.lane_max_degree + 1))))
     return rc;
   // R[0] is the caller's output vector; with `init` (which may alias it) the
   // start vector is copied into it.
@@ -665,19 +680,20 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
                        (const int *)nullptr, n, w.xrt);
     LAUNCH_TRY();
   }
-  Locality loc;
-  if ((rc = locality(w, n, g->m, g->out_offsets, g->in_sources, tn, true, s, &loc,
-                     xs ? w.xrs : nullptr)))
-    return rc;
-  double *X = w.X0;
-  hipLaunchKernelGGL(k_dfp_init, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n,
-                     g->out_offsets, loc.pos, prev, R, X, dV, dN, cv);
-  LAUNCH_TRY();
   XPlan xp;
   rc = partition(w, g->in_offsets, n, g->m, t1, tn.wave_max_degree, CH, w.hi_in, kInWave,
                  kInChunks, w.hub_start_in, w.chunk_hub_in, s, xs ? g->in_sources : nullptr,
                  &xp);
   if (rc) return rc;
+  Locality loc;
+  if ((rc = locality(w, n, g->m, g->out_offsets, g->in_sources, tn, true, s, &loc,
+                     xs ? w.xrs : nullptr, &xp, g->in_offsets,
+                     std::max(xsplit_min_degree(tn), t1 + 1))))
+    return rc;
+  double *X = w.X0;
+  hipLaunchKernelGGL(k_dfp_init, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n,
+                     g->out_offsets, loc.pos, prev, R, X, dV, dN, cv);
+  LAUNCH_TRY();
   rc = partition(w, g->out_offsets, n, g->m, t_exp, tn.wave_max_degree, CH, w.hi_out, kOutWave,
                  kOutChunks, w.hub_start_out, w.chunk_hub_out, s);
   if (rc) return rc;
