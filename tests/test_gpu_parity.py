@@ -26,7 +26,9 @@ XSPLIT = [dict(xcd_split_degree=2, lane_max_degree=1),
           dict(xcd_split_degree=8, hub_chunk_edges=4, relabel=1),
           dict(xcd_split_degree=5, grid_blocks=5, relabel=1),
           dict(xcd_split_degree=3, grid_blocks=13, hub_chunk_edges=2, relabel=1),
-          dict(xcd_split_degree=16, relabel=0, grid_blocks=64)]
+          dict(xcd_split_degree=16, relabel=0, grid_blocks=64),
+          # a wavefront class between the lane class and the die split, relabelled
+          dict(lane_max_degree=4, xcd_split_degree=16, relabel=1)]
 
 
 @pytest.fixture(autouse=True)
