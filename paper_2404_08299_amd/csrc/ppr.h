@@ -132,8 +132,19 @@ __global__ __launch_bounds__(kBlock) void k_ppr_finalize(
     const size_t px = (size_t)xpos(pos, v) * K, pv = (size_t)v * K;
     for (int k = lane; k < K; k += kWave) {
       if (vdone[k]) continue;
+      // the row's partial rows in chunk order, four loads in flight
       double c = 0.0;
-      for (int q = hub_start[i]; q < hub_start[i + 1]; ++q) c = c + part[(size_t)q * K + k];
+      int q = hub_start[i];
+      const int q1 = hub_start[i + 1];
+      for (; q + 4 <= q1; q += 4) {
+        const double p0 = part[(size_t)q * K + k], p1 = part[(size_t)(q + 1) * K + k];
+        const double p2 = part[(size_t)(q + 2) * K + k], p3 = part[(size_t)(q + 3) * K + k];
+        c = c + p0;
+        c = c + p1;
+        c = c + p2;
+        c = c + p3;
+      }
+      for (; q < q1; ++q) c = c + part[(size_t)q * K + k];
       const double r = oma * S[pv + k] + alpha * c;
       Rn[pv + k] = r;
       Xn[px + k] = r / d;
@@ -148,32 +159,58 @@ __global__ __launch_bounds__(kBlock) void k_ppr_finalize(
   }
 }
 
-// Per-vector convergence: vector k's maximum over the np partial rows; a
-// vector meeting tol is frozen with its iteration count. ctrl->done once every
-// vector is frozen.
-__global__ __launch_bounds__(kBlock) void k_ppr_linf(const double *__restrict__ pmax, int np,
-                                                     int K, int *__restrict__ vdone,
-                                                     int *__restrict__ viters,
-                                                     double *__restrict__ vdelta, Ctrl *ctrl,
-                                                     double tol, int it, int max_iter) {
+// Per-vector maxima of the np partial rows of pmax ([np][K]) in
+// kPprColBlocks row chunks, cmax[chunk][k]: a wavefront's lanes read 64
+// consecutive vectors of one row at a time (coalesced), the four wavefronts
+// of a workgroup split the chunk's rows.
+constexpr int kPprColBlocks = 64;
+
+__global__ __launch_bounds__(kBlock) void k_ppr_colmax(const double *__restrict__ pmax, int np,
+                                                       int K, double *__restrict__ cmax,
+                                                       const Ctrl *__restrict__ ctrl) {
   if (ctrl->done) return;
-  __shared__ double lds[kWavesPerBlock];
-  __shared__ int s_open;
-  if (threadIdx.x == 0) s_open = 0;
-  __syncthreads();
-  for (int k = 0; k < K; ++k) {
-    if (vdone[k]) continue;  // uniform
+  __shared__ double s_m[kWavesPerBlock][kWave];
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const int r0 = (int)((long long)np * blockIdx.x / gridDim.x);
+  const int r1 = (int)((long long)np * (blockIdx.x + 1) / gridDim.x);
+  for (int k0 = 0; k0 < K; k0 += kWave) {
+    const int k = k0 + lane;
     double m = 0.0;
-    for (int b = threadIdx.x; b < np; b += kBlock) m = fmax(m, pmax[(size_t)b * K + k]);
-    m = block_max<kBlock>(m, lds);
-    if (threadIdx.x == 0) {
-      vdelta[k] = m;
-      viters[k] = it + 1;
-      if (m <= tol) vdone[k] = 1;
-      else s_open = 1;
+    if (k < K)
+      for (int r = r0 + wid; r < r1; r += kWavesPerBlock) m = fmax(m, pmax[(size_t)r * K + k]);
+    s_m[wid][lane] = m;
+    __syncthreads();
+    if (wid == 0 && k < K) {
+      double t = s_m[0][lane];
+      for (int i = 1; i < kWavesPerBlock; ++i) t = fmax(t, s_m[i][lane]);
+      cmax[(size_t)blockIdx.x * K + k] = t;
     }
     __syncthreads();
   }
+}
+
+// Per-vector convergence: vector k's maximum over the nb chunk maxima (one
+// thread per vector); a vector meeting tol is frozen with its iteration
+// count. ctrl->done once every vector is frozen.
+__global__ __launch_bounds__(kBlock) void k_ppr_linf(const double *__restrict__ cmax, int nb,
+                                                     int K, int *__restrict__ vdone,
+                                                     int *__restrict__ viters,
+                                                     double *__restrict__ vdelta, Ctrl *ctrl,
+                                                     double tol, int it) {
+  if (ctrl->done) return;
+  __shared__ int s_open;
+  if (threadIdx.x == 0) s_open = 0;
+  __syncthreads();
+  for (int k = threadIdx.x; k < K; k += kBlock) {
+    if (vdone[k]) continue;
+    double m = 0.0;
+    for (int b = 0; b < nb; ++b) m = fmax(m, cmax[(size_t)b * K + k]);
+    vdelta[k] = m;
+    viters[k] = it + 1;
+    if (m <= tol) vdone[k] = 1;
+    else s_open = 1;  // every writer stores 1
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
     ctrl->iters = it + 1;
     if (!s_open) ctrl->done = 1;

@@ -826,7 +826,8 @@ constexpr int kPprChunk = 256;  // in-edges per wavefront before a row is split
 int ppr_ws(Workspace &w, size_t n, size_t m, size_t K, size_t B) {
   const size_t nbuf = 4 * n * K;
   const size_t npart = std::max(m / kPprChunk + n + 1, xsplit_items_bound(n, m, kPprChunk)) * K;
-  const size_t npmax = (B + kHubFinalizeBlocks + 16) * K;
+  // partial maxima of the rank and finalize workgroups, then the chunk maxima
+  const size_t npmax = (B + kHubFinalizeBlocks + 16 + kPprColBlocks) * K;
   if (nbuf > w.cap_ppr_buf || npart > w.cap_ppr_part || npmax > w.cap_ppr_pmax ||
       K > w.cap_ppr_k || n > w.cap_ppr_n) {
     const size_t a = std::max(nbuf, w.cap_ppr_buf), b = std::max(npart, w.cap_ppr_part);
@@ -906,9 +907,12 @@ int run_ppr(const pr_csr *g, const double *teleport, int K, double alpha, double
                        K, (const double *)w.ppr_part, (const double *)Rb[a], Rb[b], Xb[b],
                        teleport, (const int *)w.ppr_vdone, alpha, w.ppr_pmax + (size_t)B * K,
                        (const Ctrl *)w.ctrl);
-    hipLaunchKernelGGL(k_ppr_linf, dim3(1), dim3(kBlock), 0, s, (const double *)w.ppr_pmax,
-                       B + F, K, w.ppr_vdone, w.ppr_viters, w.ppr_vdelta, w.ctrl, tol, it,
-                       max_iter);
+    double *cmax = w.ppr_pmax + (size_t)(B + F + 16) * K;
+    hipLaunchKernelGGL(k_ppr_colmax, dim3(kPprColBlocks), dim3(kBlock), 0, s,
+                       (const double *)w.ppr_pmax, B + F, K, cmax, (const Ctrl *)w.ctrl);
+    hipLaunchKernelGGL(k_ppr_linf, dim3(1), dim3(kBlock), 0, s, (const double *)cmax,
+                       kPprColBlocks, K, w.ppr_vdone, w.ppr_viters, w.ppr_vdelta, w.ctrl, tol,
+                       it);
     LAUNCH_TRY();
     return PR_OK;
   };
