@@ -106,7 +106,7 @@ __global__ __launch_bounds__(kBlock) void k_rank_batched(
   extern __shared__ unsigned long long s_gmax[];
   clear_table(s_gmax, G);
   const BatchOut out{out_off, pos, gid, C0g, gdone, R, Rn, Xn, alpha, s_gmax};
-  rank_update<false>(in_off, in_src, nullptr, X, hi, counts, hub_start, chunk_hub, hub_part, CH,
+  rank_update<false, 4>(in_off, in_src, nullptr, X, hi, counts, hub_start, chunk_hub, hub_part, CH,
                      n, t1, xitems, xoff, out, nullptr);
   flush_table(s_gmax, G, gpart + (size_t)blockIdx.x * G);
 }

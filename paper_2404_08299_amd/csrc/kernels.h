@@ -592,7 +592,23 @@ struct DynOut {
 // dN flag, which is the clearing of delta_N at the start of the iteration in
 // Alg. 2), computes the new value (finish) and may record its |change|
 // elsewhere (note). partials may be null (no per-workgroup maximum).
-template <bool WEIGHTED, class Out>
+// Die-split items of one die's list, dealt out in groups of G = 2^LG
+// consecutive items, group g to wavefront g mod Wd: slot s of wavefront gwx
+// (s = 0, 1, ...) holds item beg + (gwx + (s >> LG) * Wd) * G + (s & (G - 1)).
+// Every item of the list is in exactly one slot of one wavefront. Lists long
+// enough to give every wavefront kItemSpread groups of 16 keep runs of 16
+// consecutive items together (LG = 4); shorter ones are spread item by item
+// (LG = 0), so that no wavefront of the die sits idle while others work
+// through consecutive chunks of a long row. The host picks LG from the list
+// lengths and launches that instantiation (a mapping chosen inside the
+// kernel, at run time, made the loop about a third slower).
+constexpr int kItemSpread = 8;
+template <int LG>
+__device__ __forceinline__ long long item_of(int beg, int gwx, long long s, long long Wd) {
+  return beg + ((gwx + (s >> LG) * Wd) << LG) + (s & ((1 << LG) - 1));
+}
+
+template <bool WEIGHTED, int LG, class Out>
 __device__ __forceinline__ void rank_update(
     const int *__restrict__ in_off, const int *__restrict__ in_src,
     const double *__restrict__ wt, const double *__restrict__ X, const int *__restrict__ hi,
@@ -616,14 +632,15 @@ __device__ __forceinline__ void rank_update(
     const int xstep = B >= kXcds ? kXcds : B;
     const int loc = B >= kXcds ? (int)blockIdx.x / kXcds : 0;
     const int nloc = B >= kXcds ? (B - 1 - x0) / kXcds + 1 : 1;
-    // a wavefront loads 64 consecutive items {partial, e0, e1, vertex} (one
-    // per lane), keeps those of active vertices and sums them one by one
-    const long long Wx = (long long)nloc * kWavesPerBlock * kWave;
+    // a wavefront loads 64 items {partial, e0, e1, vertex} (one per lane),
+    // keeps those of active vertices and sums them one by one; the items are
+    // dealt out to the Wd wavefronts of the die by item_of
+    const long long Wd = (long long)nloc * kWavesPerBlock;
+    const int gwx = loc * kWavesPerBlock + wid;
     for (int x = x0; x < kXcds; x += xstep) {
-      const int end = xoff[x + 1];
-      for (long long j0 = xoff[x] + (long long)(loc * kWavesPerBlock + wid) * kWave; j0 < end;
-           j0 += Wx) {
-        const long long j = j0 + lane;
+      const int beg = xoff[x], end = xoff[x + 1];
+      for (long long k0 = 0; item_of<LG>(beg, gwx, k0, Wd) < end; k0 += kWave) {
+        const long long j = item_of<LG>(beg, gwx, k0 + lane, Wd);
         int4 it = make_int4(0, 0, 0, 0);
         bool f = false;
         if (j < end) {
@@ -779,7 +796,7 @@ __device__ __forceinline__ void rank_update(
 // adjoint iteration). in_src: the row indices in the gather-side numbering
 // (pos); wt: per-edge weights aligned with them (WEIGHTED); X, Xn: gathered
 // values in that numbering; R, Rn: the iterate in vertex order.
-template <bool WEIGHTED>
+template <bool WEIGHTED, int LG>
 __global__ __launch_bounds__(kBlock) void k_rank_static(
     const int *__restrict__ in_off, const int *__restrict__ in_src,
     const double *__restrict__ wt, const int *__restrict__ out_off,
@@ -792,11 +809,11 @@ __global__ __launch_bounds__(kBlock) void k_rank_static(
     const Ctrl *__restrict__ ctrl) {
   if (ctrl->done) return;
   const StaticOut out{out_off, pos, R, Rn, Xn, C0, alpha, tele, tscale, WEIGHTED};
-  rank_update<WEIGHTED>(in_off, in_src, wt, X, hi, counts, hub_start, chunk_hub, hub_part, CH, n,
-                        t1, xitems, xoff, out, partials);
+  rank_update<WEIGHTED, LG>(in_off, in_src, wt, X, hi, counts, hub_start, chunk_hub, hub_part, CH,
+                            n, t1, xitems, xoff, out, partials);
 }
 
-template <bool PRUNE>
+template <bool PRUNE, int LG>
 __global__ __launch_bounds__(kBlock) void k_rank_dfp(
     const int *__restrict__ in_off, const int *__restrict__ in_src,
     const int *__restrict__ out_off, const double *__restrict__ X, const double *__restrict__ R,
@@ -807,7 +824,7 @@ __global__ __launch_bounds__(kBlock) void k_rank_dfp(
     double tau_f, double tau_p, double *__restrict__ partials, const Ctrl *__restrict__ ctrl) {
   if (ctrl->done) return;
   const DynOut<PRUNE> out{out_off, R, T, dV, dN, cv, C0, alpha, tau_f, tau_p};
-  rank_update<false>(in_off, in_src, nullptr, X, hi, counts, hub_start, chunk_hub, hub_part, CH, n,
+  rank_update<false, LG>(in_off, in_src, nullptr, X, hi, counts, hub_start, chunk_hub, hub_part, CH, n,
                      t1, xitems, xoff, out, partials);
 }
 
@@ -1369,8 +1386,9 @@ __global__ __launch_bounds__(kBlock) void k_map_sources(const int *__restrict__ 
 // in-edges are mapped item by item, list x by the workgroups on die x (the
 // items of list x have their sources in range x, so the newid entries a die
 // reads are that range's eighth of the table, as the rank kernel's gathers
-// are). A wavefront loads 64 items, one per lane, and maps them one after
-// the other with all its lanes.
+// are). A wavefront loads 64 items, one per lane, dealt out as in the rank
+// kernel (item_of), and maps them one after the other with all its lanes.
+template <int LG>
 __global__ __launch_bounds__(kBlock) void k_map_split(const int4 *__restrict__ xitems,
                                                       const int *__restrict__ xoff,
                                                       const int *__restrict__ src,
@@ -1381,15 +1399,17 @@ __global__ __launch_bounds__(kBlock) void k_map_split(const int4 *__restrict__ x
   const int xstep = B >= kXcds ? kXcds : B;
   const int loc = B >= kXcds ? (int)blockIdx.x / kXcds : 0;
   const int nloc = B >= kXcds ? (B - 1 - x0) / kXcds + 1 : 1;
-  const long long Wx = (long long)nloc * kWavesPerBlock * kWave;
+  const long long Wd = (long long)nloc * kWavesPerBlock;
+  const int gwx = loc * kWavesPerBlock + wid;
   for (int x = x0; x < kXcds; x += xstep) {
-    const int end = xoff[x + 1];
-    for (long long j0 = xoff[x] + (long long)(loc * kWavesPerBlock + wid) * kWave; j0 < end;
-         j0 += Wx) {
-      const long long j = j0 + lane;
+    const int beg = xoff[x], end = xoff[x + 1];
+    for (long long k0 = 0; item_of<LG>(beg, gwx, k0, Wd) < end; k0 += kWave) {
+      const long long j = item_of<LG>(beg, gwx, k0 + lane, Wd);
       const int4 it = j < end ? xitems[j] : make_int4(0, 0, 0, 0);
-      const int cnt = (int)min((long long)kWave, end - j0);
-      for (int q = 0; q < cnt; ++q) {
+      unsigned long long vm = __ballot(j < end);
+      while (vm) {
+        const int q = __ffsll(vm) - 1;
+        vm &= vm - 1;
         const int e0 = __shfl(it.y, q), e1 = __shfl(it.z, q);
         for (int e = e0 + lane; e < e1; e += kWave) st_nt(dst + e, newid[ld_nt(src + e)]);
       }

@@ -103,6 +103,7 @@ struct Workspace {
   Ctrl *ctrl = nullptr;
   Ctrl *host_ctrl = nullptr;  // pinned ring
   int *host_counts = nullptr;  // pinned
+  int *host_xoff = nullptr;    // pinned copy of the die-split list offsets
   hipEvent_t sync_ev[kRing] = {};
   std::vector<hipEvent_t> prof_ev;
   hipEvent_t call_ev[2] = {};
@@ -195,6 +196,7 @@ void free_ws(Workspace &w) {
   (void)hipFree(w.counts); (void)hipFree(w.group_totals); (void)hipFree(w.ctrl);
   if (w.host_ctrl) (void)hipHostFree(w.host_ctrl);
   if (w.host_counts) (void)hipHostFree(w.host_counts);
+  if (w.host_xoff) (void)hipHostFree(w.host_xoff);
   if (w.events_ready) {
     for (auto &e : w.sync_ev) (void)hipEventDestroy(e);
     for (auto &e : w.call_ev) (void)hipEventDestroy(e);
@@ -269,6 +271,7 @@ int get_ws(size_t n, size_t m, int CH, int B, Workspace **out) {
     w.xrt = w.xrs + 48;
     HIP_TRY(hipHostMalloc(&w.host_ctrl, kRing * sizeof(Ctrl), hipHostMallocDefault));
     HIP_TRY(hipHostMalloc(&w.host_counts, kNumCounts * sizeof(int), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc(&w.host_xoff, 16 * sizeof(int), hipHostMallocDefault));
     HIP_TRY(hipDeviceGetAttribute(&w.num_cus, hipDeviceAttributeMultiprocessorCount, dev));
     w.events_ready = true;
   }
@@ -423,6 +426,30 @@ int partition(Workspace &w, const int *off, int n, int m, int t1, int t2, int CH
   return PR_OK;
 }
 
+// The die-split list offsets of plan xp on the host (one wait on the stream),
+// for item_lg below. No plan: nothing to read.
+int read_plan(Workspace &w, const XPlan &xp, hipStream_t s) {
+  if (!xp.items) return PR_OK;
+  HIP_TRY(hipMemcpyAsync(w.host_xoff, xp.off, (kXcds + 1) * sizeof(int), hipMemcpyDeviceToHost,
+                         s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return PR_OK;
+}
+
+// How a grid of B workgroups deals out each die's items (see item_of): in
+// runs of 16 when every one of the die's wavefronts gets kItemSpread runs of
+// the shortest list, one by one otherwise. Returns LG (4 or 0).
+int item_lg(const Workspace &w, const XPlan &xp, int B) {
+  if (!xp.items) return 4;
+  long long shortest = -1;
+  for (int x = 0; x < kXcds; ++x) {
+    const long long len = (long long)w.host_xoff[x + 1] - w.host_xoff[x];
+    if (shortest < 0 || len < shortest) shortest = len;
+  }
+  const long long Wd = (long long)std::max(1, B / kXcds) * kWavesPerBlock;
+  return shortest >= Wd * 16 * kItemSpread ? 4 : 0;
+}
+
 // Gather-side numbering (degree-based grouping by the degrees of
 // `group_off`) and the row indices `idx` mapped into it. Returns the
 // numbering to use (nullptr = identity) and the index array the pull kernels
@@ -453,7 +480,8 @@ int locality(Workspace &w, int n, int m, const int *group_off, const int *idx,
                      (const int *)w.tile_counts, (const int *)w.group_totals, nt, rs, w.newid);
   if (xp && xp->items && rs && row_off && T > 0) {
     const int gs = kXcds * 4 * std::max(1, w.num_cus);
-    hipLaunchKernelGGL(k_map_split, dim3(gs), dim3(kBlock), 0, s, (const int4 *)xp->items,
+    auto map_fn = item_lg(w, *xp, gs) ? k_map_split<4> : k_map_split<0>;
+    hipLaunchKernelGGL(map_fn, dim3(gs), dim3(kBlock), 0, s, (const int4 *)xp->items,
                        (const int *)xp->off, idx, (const int *)w.newid, w.src_p);
     const int gr = (int)std::min<long long>(((long long)n + kBlock - 1) / kBlock, 65536);
     hipLaunchKernelGGL(k_map_short, dim3(gr), dim3(kBlock), 0, s, row_off, idx, n, T,
@@ -570,8 +598,8 @@ int run_pull(const PullProblem &P, double alpha, double tol, int max_iter, doubl
   if (rc) return rc;
   Workspace &w = *wp;
   const bool weighted = P.w != nullptr;
-  const int B = weighted ? grid_blocks(w, tn, k_rank_static<true>)
-                         : grid_blocks(w, tn, k_rank_static<false>);
+  const int B = weighted ? grid_blocks(w, tn, k_rank_static<true, 4>)
+                         : grid_blocks(w, tn, k_rank_static<false, 4>);
   const int np = B + kHubFinalizeBlocks;
   CallTimer timer(w, s);
   hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, s, w.ctrl);
@@ -582,6 +610,10 @@ int run_pull(const PullProblem &P, double alpha, double tol, int max_iter, doubl
                  tn.hub_chunk_edges, w.hi_in, kInWave, kInChunks, w.hub_start_in,
                  w.chunk_hub_in, s, xs ? P.row_idx : nullptr, &xp);
   if (rc) return rc;
+  if ((rc = read_plan(w, xp, s))) return rc;
+  const int lg = item_lg(w, xp, B);
+  auto rank_w = lg ? k_rank_static<true, 4> : k_rank_static<true, 0>;
+  auto rank_u = lg ? k_rank_static<false, 4> : k_rank_static<false, 0>;
   Locality loc;
   if ((rc = locality(w, n, P.m, P.group_off, P.row_idx, tn, P.relabel, s, &loc,
                      xs ? w.xrs : nullptr, &xp, P.row_off,
@@ -599,14 +631,14 @@ int run_pull(const PullProblem &P, double alpha, double tol, int max_iter, doubl
   auto launch = [&](int it, bool prof, hipEvent_t after) -> int {
     const int a = it & 1, b = a ^ 1;
     if (weighted)
-      hipLaunchKernelGGL(k_rank_static<true>, dim3(B), dim3(kBlock), 0, s, P.row_off, loc.src,
+      hipLaunchKernelGGL(rank_w, dim3(B), dim3(kBlock), 0, s, P.row_off, loc.src,
                          P.w, P.deg_off, loc.pos, (const double *)X[a], (const double *)R[a],
                          R[b], X[b], (const int *)w.hi_in, (const int *)w.counts,
                          (const int *)w.hub_start_in, (const int *)w.chunk_hub_in, w.hub_part, CH,
                          n, t1, xp.items, xp.off, C0, alpha, P.tele, P.tscale, w.partials,
                          (const Ctrl *)w.ctrl);
     else
-      hipLaunchKernelGGL(k_rank_static<false>, dim3(B), dim3(kBlock), 0, s, P.row_off, loc.src,
+      hipLaunchKernelGGL(rank_u, dim3(B), dim3(kBlock), 0, s, P.row_off, loc.src,
                          (const double *)nullptr, P.deg_off, loc.pos, (const double *)X[a],
                          (const double *)R[a], R[b], X[b], (const int *)w.hi_in,
                          (const int *)w.counts, (const int *)w.hub_start_in,
@@ -664,7 +696,8 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
   int rc = get_ws((size_t)n, (size_t)g->m, tn.hub_chunk_edges, tn.grid_blocks, &wp);
   if (rc) return rc;
   Workspace &w = *wp;
-  const int B = prune ? grid_blocks(w, tn, k_rank_dfp<true>) : grid_blocks(w, tn, k_rank_dfp<false>);
+  const int B = prune ? grid_blocks(w, tn, k_rank_dfp<true, 4>)
+                      : grid_blocks(w, tn, k_rank_dfp<false, 4>);
   const int np = B + kHubFinalizeBlocks;
   CallTimer timer(w, s);
   const size_t fs = flag_stride((size_t)n);  // each flag array 256-byte aligned
@@ -685,6 +718,10 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
                  kInChunks, w.hub_start_in, w.chunk_hub_in, s, xs ? g->in_sources : nullptr,
                  &xp);
   if (rc) return rc;
+  if ((rc = read_plan(w, xp, s))) return rc;
+  const int lg = item_lg(w, xp, B);
+  auto rank_p = lg ? k_rank_dfp<true, 4> : k_rank_dfp<true, 0>;
+  auto rank_d = lg ? k_rank_dfp<false, 4> : k_rank_dfp<false, 0>;
   Locality loc;
   if ((rc = locality(w, n, g->m, g->out_offsets, g->in_sources, tn, true, s, &loc,
                      xs ? w.xrs : nullptr, &xp, g->in_offsets,
@@ -771,7 +808,7 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
   const double C0 = (1.0 - alpha) / (double)n;
   auto launch = [&](int it, bool prof, hipEvent_t after) -> int {
     if (prune) {
-      hipLaunchKernelGGL(k_rank_dfp<true>, dim3(B), dim3(kBlock), 0, s, g->in_offsets,
+      hipLaunchKernelGGL(rank_p, dim3(B), dim3(kBlock), 0, s, g->in_offsets,
                          loc.src, g->out_offsets, (const double *)X, (const double *)R, w.T, dV,
                          dN, cv,
                          (const int *)w.hi_in, (const int *)w.counts,
@@ -784,7 +821,7 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
                          (const double *)w.hub_part, g->out_offsets, (const double *)R, w.T, dV,
                          dN, cv, C0, alpha, tau_f, tau_p, w.partials + B, (const Ctrl *)w.ctrl);
     } else {
-      hipLaunchKernelGGL(k_rank_dfp<false>, dim3(B), dim3(kBlock), 0, s, g->in_offsets,
+      hipLaunchKernelGGL(rank_d, dim3(B), dim3(kBlock), 0, s, g->in_offsets,
                          loc.src, g->out_offsets, (const double *)X, (const double *)R, w.T, dV,
                          dN, cv,
                          (const int *)w.hi_in, (const int *)w.counts,
