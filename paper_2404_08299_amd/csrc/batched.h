@@ -92,6 +92,7 @@ __device__ __forceinline__ void flush_table(const unsigned long long *s, int G, 
 }
 
 // gpart: [gridDim.x (+ finalize blocks)][G] per-workgroup per-graph maxima.
+template <int LG>
 __global__ __launch_bounds__(kBlock) void k_rank_batched(
     const int *__restrict__ in_off, const int *__restrict__ in_src,
     const int *__restrict__ out_off, const int *__restrict__ pos, const double *__restrict__ X,
@@ -106,7 +107,7 @@ __global__ __launch_bounds__(kBlock) void k_rank_batched(
   extern __shared__ unsigned long long s_gmax[];
   clear_table(s_gmax, G);
   const BatchOut out{out_off, pos, gid, C0g, gdone, R, Rn, Xn, alpha, s_gmax};
-  rank_update<false, 4>(in_off, in_src, nullptr, X, hi, counts, hub_start, chunk_hub, hub_part, CH,
+  rank_update<false, LG>(in_off, in_src, nullptr, X, hi, counts, hub_start, chunk_hub, hub_part, CH,
                      n, t1, xitems, xoff, out, nullptr);
   flush_table(s_gmax, G, gpart + (size_t)blockIdx.x * G);
 }

@@ -1111,7 +1111,7 @@ int run_batched(const pr_csr *graphs, int G, double alpha, double tol, int max_i
   int rc = get_ws((size_t)n, (size_t)m, tn.hub_chunk_edges, tn.grid_blocks, &wp);
   if (rc) return rc;
   Workspace &w = *wp;
-  const int B = grid_blocks(w, tn, k_rank_batched);
+  const int B = grid_blocks(w, tn, k_rank_batched<4>);
   const int F = kHubFinalizeBlocks;
   if ((rc = batch_ws(w, (size_t)n, (size_t)m, (size_t)G, (size_t)(B + F)))) return rc;
   CallTimer timer(w, s);
@@ -1142,6 +1142,8 @@ int run_batched(const pr_csr *graphs, int G, double alpha, double tol, int max_i
   if (rc) return rc;
   Locality loc;
   if ((rc = locality(w, n, m, w.u_out_off, w.u_in_src, tn, true, s, &loc))) return rc;
+  if ((rc = read_plan(w, xp, s))) return rc;
+  auto rank_fn = item_lg(w, xp, B) ? k_rank_batched<4> : k_rank_batched<0>;
   double *R[2] = {w.T, w.R1};
   double *X[2] = {w.X0, w.X1};
   hipLaunchKernelGGL(k_batched_init, dim3(ub), dim3(kBlock), 0, s, n, G, (const int *)w.u_gid,
@@ -1157,7 +1159,7 @@ int run_batched(const pr_csr *graphs, int G, double alpha, double tol, int max_i
   HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
   for (int it = 0; it < 2; ++it) {
     const int a = it & 1, b = a ^ 1;
-    hipLaunchKernelGGL(k_rank_batched, dim3(B), dim3(kBlock), shm, cs, (const int *)w.u_in_off,
+    hipLaunchKernelGGL(rank_fn, dim3(B), dim3(kBlock), shm, cs, (const int *)w.u_in_off,
                        loc.src, (const int *)w.u_out_off, loc.pos, (const double *)X[a],
                        (const double *)R[a], R[b], X[b], (const int *)w.hi_in,
                        (const int *)w.counts, (const int *)w.hub_start_in,
