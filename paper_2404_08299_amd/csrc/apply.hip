@@ -204,17 +204,14 @@ __global__ __launch_bounds__(kBlock) void k_rows(const int *__restrict__ off, co
     bool special = false, lng = false;
     int o0 = 0, cnt = 0, no = 0, ne = 0;
     if (r < n) {
+      // all of the row's metadata in one round trip
       o0 = off[r];
-      const int o1 = off[r + 1];
+      const int o1 = off[r + 1], dc = dcnt[r], ic = icnt[r];
+      no = new_off[r];
+      ne = new_off[r + 1];
       lng = o1 - o0 > kLongRow;
-      if (!lng) {
-        special = dcnt[r] != 0 || icnt[r] != 0;
-        if (!special) {
-          cnt = o1 - o0;
-          no = new_off[r];
-          ne = new_off[r + 1];
-        }
-      }
+      special = !lng && (dc != 0 || ic != 0);
+      if (!lng && !special) cnt = o1 - o0;
     }
     if (__ballot(special || lng) == 0) {
       // no changed or long row among the 64: their entries are one run with
