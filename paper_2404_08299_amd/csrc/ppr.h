@@ -51,8 +51,9 @@ __global__ __launch_bounds__(kBlock) void k_ppr_rank(
     const int *__restrict__ counts, const int *__restrict__ hub_start,
     const int *__restrict__ chunk_hub, const uint8_t *__restrict__ deg_split, int CH, int n,
     int K, const double *__restrict__ X, const double *__restrict__ R, double *__restrict__ Rn,
-    double *__restrict__ Xn, const double *__restrict__ S, double *__restrict__ part,
-    const int *__restrict__ vdone, double alpha, double *__restrict__ pmax,
+    double *__restrict__ Xn, const double *__restrict__ S, const uint8_t *__restrict__ tnz,
+    double *__restrict__ part, const int *__restrict__ vdone, double alpha,
+    double *__restrict__ pmax,
     const int4 *__restrict__ xitems, const int *__restrict__ xoff,
     const Ctrl *__restrict__ ctrl) {
   if (ctrl->done) return;
@@ -97,7 +98,7 @@ __global__ __launch_bounds__(kBlock) void k_ppr_rank(
     for (int k = lane; k < K; k += kWave) {
       if (vdone[k]) continue;
       const double c = ppr_row_sum(in_src, X, K, k, e0, e1);
-      const double r = oma * S[pv + k] + alpha * c;
+      const double r = oma * (tnz[v] ? S[pv + k] : 0.0) + alpha * c;
       st_nt(Rn + pv + k, r);
       Xn[px + k] = r / d;
       s_max[wid * K + k] = fmax(s_max[wid * K + k], fabs(r - R[pv + k]));
@@ -117,8 +118,9 @@ __global__ __launch_bounds__(kBlock) void k_ppr_finalize(
     const int *__restrict__ out_off, const int *__restrict__ pos, const int *__restrict__ hi,
     const int *__restrict__ counts, const int *__restrict__ hub_start, int K,
     const double *__restrict__ part, const double *__restrict__ R, double *__restrict__ Rn,
-    double *__restrict__ Xn, const double *__restrict__ S, const int *__restrict__ vdone,
-    double alpha, double *__restrict__ pmax, const Ctrl *__restrict__ ctrl) {
+    double *__restrict__ Xn, const double *__restrict__ S, const uint8_t *__restrict__ tnz,
+    const int *__restrict__ vdone, double alpha, double *__restrict__ pmax,
+    const Ctrl *__restrict__ ctrl) {
   if (ctrl->done) return;
   extern __shared__ double s_max[];
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
@@ -145,7 +147,7 @@ __global__ __launch_bounds__(kBlock) void k_ppr_finalize(
         c = c + p3;
       }
       for (; q < q1; ++q) c = c + part[(size_t)q * K + k];
-      const double r = oma * S[pv + k] + alpha * c;
+      const double r = oma * (tnz[v] ? S[pv + k] : 0.0) + alpha * c;
       Rn[pv + k] = r;
       Xn[px + k] = r / d;
       s_max[wid * K + k] = fmax(s_max[wid * K + k], fabs(r - R[pv + k]));
@@ -240,6 +242,21 @@ __global__ __launch_bounds__(kBlock) void k_split_flags(const int *__restrict__ 
                                                         int CH, uint8_t *__restrict__ f) {
   for (int v = blockIdx.x * kBlock + threadIdx.x; v < n; v += gridDim.x * kBlock)
     f[v] = (in_off[v + 1] - in_off[v]) > CH;
+}
+
+// tnz[v] = 1 when any teleport entry of vertex v is non-zero (a wavefront per
+// vertex, lanes over the vectors): rows of all zeros need not be read, since
+// (1 - alpha) * 0 + alpha * c is exactly alpha * c.
+__global__ __launch_bounds__(kBlock) void k_tele_flags(const double *__restrict__ S, int n, int K,
+                                                       uint8_t *__restrict__ tnz) {
+  const int lane = threadIdx.x & (kWave - 1);
+  for (long long v = (long long)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; v < n;
+       v += (long long)gridDim.x * kWavesPerBlock) {
+    bool any = false;
+    for (int k = lane; k < K; k += kWave) any = any || S[v * K + k] != 0.0;
+    const bool nz = __ballot(any) != 0;
+    if (lane == 0) tnz[v] = nz ? 1 : 0;
+  }
 }
 
 // out[v][k] = buf[viters[k] & 1][v][k]: each vector's final iterate.

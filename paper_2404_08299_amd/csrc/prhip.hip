@@ -878,7 +878,7 @@ int ppr_ws(Workspace &w, size_t n, size_t m, size_t K, size_t B) {
         (e = hipMalloc(&w.ppr_vdelta, kk * sizeof(double))) != hipSuccess ||
         (e = hipMalloc(&w.ppr_vdone, kk * sizeof(int))) != hipSuccess ||
         (e = hipMalloc(&w.ppr_viters, kk * sizeof(int))) != hipSuccess ||
-        (e = hipMalloc(&w.ppr_split, nn)) != hipSuccess) {
+        (e = hipMalloc(&w.ppr_split, 2 * nn)) != hipSuccess) {  // split flags, teleport flags
       (void)hipGetLastError();
       free_ppr(w);
       return fail(e == hipErrorOutOfMemory ? PR_ENOMEM : PR_EHIP,
@@ -927,6 +927,9 @@ int run_ppr(const pr_csr *g, const double *teleport, int K, double alpha, double
                      Rb[0], Xb[0], w.ppr_vdone, w.ppr_viters);
   hipLaunchKernelGGL(k_split_flags, dim3(std::min(B, (n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
                      s, g->in_offsets, n, kPprChunk, w.ppr_split);
+  uint8_t *tnz = w.ppr_split + w.cap_ppr_n;
+  hipLaunchKernelGGL(k_tele_flags, dim3(std::min((n + kWavesPerBlock - 1) / kWavesPerBlock, 65536)),
+                     dim3(kBlock), 0, s, teleport, n, K, tnz);
   LAUNCH_TRY();
   const size_t shm = (size_t)kWavesPerBlock * K * sizeof(double);
   auto launch = [&](int it, bool prof, hipEvent_t after) -> int {
@@ -935,14 +938,14 @@ int run_ppr(const pr_csr *g, const double *teleport, int K, double alpha, double
                        g->out_offsets, loc.pos, (const int *)w.hi_in, (const int *)w.counts,
                        (const int *)w.hub_start_in, (const int *)w.chunk_hub_in,
                        (const uint8_t *)w.ppr_split, kPprChunk, n, K, (const double *)Xb[a],
-                       (const double *)Rb[a], Rb[b], Xb[b], teleport, w.ppr_part,
-                       (const int *)w.ppr_vdone, alpha, w.ppr_pmax, xp.items, xp.off,
+                       (const double *)Rb[a], Rb[b], Xb[b], teleport, (const uint8_t *)tnz,
+                       w.ppr_part, (const int *)w.ppr_vdone, alpha, w.ppr_pmax, xp.items, xp.off,
                        (const Ctrl *)w.ctrl);
     if (prof) HIP_TRY(hipEventRecord(after, s));
     hipLaunchKernelGGL(k_ppr_finalize, dim3(F), dim3(kBlock), shm, s, g->out_offsets, loc.pos,
                        (const int *)w.hi_in, (const int *)w.counts, (const int *)w.hub_start_in,
                        K, (const double *)w.ppr_part, (const double *)Rb[a], Rb[b], Xb[b],
-                       teleport, (const int *)w.ppr_vdone, alpha, w.ppr_pmax + (size_t)B * K,
+                       teleport, (const uint8_t *)tnz, (const int *)w.ppr_vdone, alpha, w.ppr_pmax + (size_t)B * K,
                        (const Ctrl *)w.ctrl);
     double *cmax = w.ppr_pmax + (size_t)(B + F + 16) * K;
     hipLaunchKernelGGL(k_ppr_colmax, dim3(kPprColBlocks), dim3(kBlock), 0, s,
