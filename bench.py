@@ -21,6 +21,10 @@ After the timed steps (a chain, so not part of a step), unless --temporal-batche
   temporal preferential-attachment stream, 2M vertices, 40M events: 90 % loaded, the
            rest in 100 batches (10 % deletions); DF-P chained batch to batch, beside
            pr_static on every G^t, errors against a tight Static every 10th batch.
+Also untimed (unless --no-compare): ND, DT and DF beside DF-P on the same batches;
+  pr_apply_batch per batch; an ablation of the rank kernel; and a sweep of
+  --sweep-batches random batches per decade (seeds 1..5 by default), each G^t built
+  on the device, DF-P against Static summarised by geometric means per decade.
 Inputs are resident in HBM before the timed region. `value` is the Static
 GTEPS per iteration (m * iterations / call time). Prints one JSON line on
 stdout; progress goes to stderr.
@@ -179,6 +183,9 @@ def main():
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the untimed comparison runs (single calls vs batched)")
     ap.add_argument("--cpu-iters", type=int, default=8)
+    ap.add_argument("--sweep-batches", type=int, default=5,
+                    help="batches per decade (seeds 1..N) in the untimed DF-P vs Static sweep; "
+                         "0 skips it")
     ap.add_argument("--temporal-batches", type=int, default=100)
     ap.add_argument("--temporal-n", type=int, default=2_000_000)
     ap.add_argument("--temporal-events", type=int, default=40_000_000)
@@ -487,6 +494,48 @@ def main():
             modes.append(item)
         out["dynamic_methods"] = modes
         log(f"methods: {modes}")
+
+    if not args.no_compare and "dfp" in legs and args.sweep_batches > 0:
+        # DF-P against Static over several random batches per decade (batch
+        # seeds 1 .. sweep_batches): each G^t is built on the device from
+        # G^{t-1} (pr_apply_batch), both methods run once untimed and once
+        # timed, and each decade is summarised by geometric means
+        t = time.time()
+        tmp_s = torch.empty(n, dtype=torch.float64, device="cuda")
+        tmp_d = torch.empty(n, dtype=torch.float64, device="cuda")
+
+        def gmean(x):
+            return float(np.exp(np.mean(np.log(x))))
+
+        sweep = []
+        for f in fracs:
+            sm, dm, sp, its, err = [], [], [], [], 0.0
+            for seed in range(1, args.sweep_batches + 1):
+                db = prhip.DeviceBatch.from_host(
+                    gg.random_batch(g0, gg.batch_size_for(g0, f), seed=seed))
+                dgt = prhip.apply_batch(dg0, db)
+                prhip.static(dgt, out=tmp_s)
+                prhip.dfp(dgt, db, prev, out=tmp_d)
+                _, ts = timed(lambda: prhip.static(dgt, out=tmp_s))
+                _, td = timed(lambda: prhip.dfp(dgt, db, prev, out=tmp_d))
+                its.append(prhip.last_stats()["iterations"])
+                err = max(err, float((tmp_d - tmp_s).abs().max()))
+                sm.append(ts)
+                dm.append(td)
+                sp.append(ts / td)
+                del dgt, db
+            sweep.append({"fraction": f, "batches": args.sweep_batches,
+                          "batch_seeds": f"1..{args.sweep_batches}",
+                          "static_ms_geomean": round(gmean(sm), 3),
+                          "dfp_ms_geomean": round(gmean(dm), 3),
+                          "dfp_speedup_geomean": round(gmean(sp), 2),
+                          "dfp_speedup_min": round(min(sp), 2),
+                          "dfp_speedup_max": round(max(sp), 2),
+                          "dfp_iters": its, "max_dfp_vs_static_linf": err})
+        out["batch_sweep"] = sweep
+        log(f"batch sweep ({time.time() - t:.1f} s): "
+            + ", ".join(f"{x['fraction']:g}: {x['dfp_speedup_geomean']}x "
+                        f"[{x['dfp_speedup_min']}, {x['dfp_speedup_max']}]" for x in sweep))
 
     if not args.no_compare and "static" in legs:
         # ablation of the rank kernel's design choices: rank-kernel time per
