@@ -310,9 +310,13 @@ def main():
     def step(s, record):
         j = s % len(fracs)
         if "static" in legs:
+            # HIP events around each rank-kernel launch (the live roofline
+            # figure) in the recorded steps only; the other calls run plain
+            prhip.set_profiling(record)
             t0 = time.perf_counter()
             prhip.static(dgs[j], out=static_out[j])
             t1 = time.perf_counter()
+            prhip.set_profiling(False)
             st = prhip.last_stats()
             if record:
                 r = rec[j]
@@ -361,14 +365,12 @@ def main():
     for s in range(args.warmup):
         step(s, False)
     log(f"warmup {args.warmup} steps done")
-    prhip.set_profiling(True)
     torch.cuda.synchronize()
     T0 = time.perf_counter()
     for s in range(args.steps):
         step(args.warmup + s, True)
     torch.cuda.synchronize()
     T1 = time.perf_counter()
-    prhip.set_profiling(False)
     ms_per_step = (T1 - T0) / args.steps * 1e3
     log(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step")
 
@@ -510,6 +512,7 @@ def main():
         sweep = []
         for f in fracs:
             sm, dm, sp, its, err = [], [], [], [], 0.0
+            a0, amax, edges, work = [], [], [], []
             for seed in range(1, args.sweep_batches + 1):
                 db = prhip.DeviceBatch.from_host(
                     gg.random_batch(g0, gg.batch_size_for(g0, f), seed=seed))
@@ -517,12 +520,22 @@ def main():
                 prhip.static(dgt, out=tmp_s)
                 prhip.dfp(dgt, db, prev, out=tmp_d)
                 _, ts = timed(lambda: prhip.static(dgt, out=tmp_s))
+                static_iters = prhip.last_stats()["iterations"]
                 _, td = timed(lambda: prhip.dfp(dgt, db, prev, out=tmp_d))
                 its.append(prhip.last_stats()["iterations"])
                 err = max(err, float((tmp_d - tmp_s).abs().max()))
                 sm.append(ts)
                 dm.append(td)
                 sp.append(ts / td)
+                # the affected-set counters, from one more (untimed) call
+                prhip.set_profiling(True)
+                prhip.dfp(dgt, db, prev, out=tmp_d)
+                st = prhip.last_stats()
+                prhip.set_profiling(False)
+                a0.append(st["affected_initial"])
+                amax.append(st["affected_max"])
+                edges.append(st["edges_processed"])
+                work.append(st["edges_processed"] / (dgt.m * static_iters))
                 del dgt, db
             sweep.append({"fraction": f, "batches": args.sweep_batches,
                           "batch_seeds": f"1..{args.sweep_batches}",
@@ -531,7 +544,10 @@ def main():
                           "dfp_speedup_geomean": round(gmean(sp), 2),
                           "dfp_speedup_min": round(min(sp), 2),
                           "dfp_speedup_max": round(max(sp), 2),
-                          "dfp_iters": its, "max_dfp_vs_static_linf": err})
+                          "dfp_iters": its, "max_dfp_vs_static_linf": err,
+                          "affected_initial": a0, "affected_max": amax,
+                          "in_edges_processed": edges,
+                          "work_vs_static_geomean": round(gmean(work), 5)})
         out["batch_sweep"] = sweep
         log(f"batch sweep ({time.time() - t:.1f} s): "
             + ", ".join(f"{x['fraction']:g}: {x['dfp_speedup_geomean']}x "
