@@ -138,6 +138,37 @@ def _bind_stream(lib, torch):
     lib.pr_set_stream(ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
 
 
+def _tensor(x, name, dtype, device, numel=None, shape=None):
+    """x as the C ABI receives it: a contiguous tensor of `dtype` on `device`
+    with the given size. Anything else raises here (TypeError for the kind,
+    ValueError for place, layout or size), before a pointer reaches a kernel."""
+    import torch
+    if not isinstance(x, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch tensor, got {type(x).__name__}")
+    if x.dtype != dtype:
+        raise TypeError(f"{name}: expected {dtype}, got {x.dtype}")
+    if x.device != device:
+        raise ValueError(f"{name}: expected a tensor on {device}, got one on {x.device}")
+    if not x.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if numel is not None and x.numel() != numel:
+        raise ValueError(f"{name}: expected {numel} elements, got {x.numel()}")
+    if shape is not None and tuple(x.shape) != tuple(shape):
+        raise ValueError(f"{name}: expected shape {tuple(shape)}, got {tuple(x.shape)}")
+    return x
+
+
+def _on_current_device(device, torch):
+    """The library allocates its workspace and launches on the current device
+    and stream, so the tensors must live there."""
+    if device.type != "cuda":
+        raise ValueError(f"graph tensors must be on a GPU, got {device}")
+    cur = torch.cuda.current_device()
+    if device.index is not None and device.index != cur:
+        raise ValueError(f"graph is on {device} but the current device is cuda:{cur}; "
+                         f"call under torch.cuda.device({device.index})")
+
+
 class DeviceGraph:
     """Both CSR views of a graph as int32 device tensors (torch storage)."""
 
@@ -156,7 +187,24 @@ class DeviceGraph:
         return DeviceGraph(g.n, g.m, t(g.in_offsets), t(g.in_sources), t(g.out_offsets),
                            t(g.out_targets))
 
+    @property
+    def device(self):
+        return self.in_offsets.device
+
     def csr(self) -> PrCsr:
+        """The pr_csr view, after checking that every present array is int32,
+        contiguous, on the graph's device and of its CSR size."""
+        import torch
+        if self.n < 0 or self.m < 0:
+            raise ValueError(f"graph sizes must be non-negative, got n={self.n} m={self.m}")
+        dev, i32 = self.device, torch.int32
+        _tensor(self.in_offsets, "in_offsets", i32, dev, numel=self.n + 1)
+        _tensor(self.in_sources, "in_sources", i32, dev, numel=self.m)
+        if self.out_offsets is not None:
+            _tensor(self.out_offsets, "out_offsets", i32, dev, numel=self.n + 1)
+        if self.out_targets is not None:
+            _tensor(self.out_targets, "out_targets", i32, dev, numel=self.m)
+
         def p(x):
             return None if x is None else x.data_ptr()
 
@@ -179,12 +227,21 @@ class DeviceBatch:
 
         return DeviceBatch(t(b.del_src), t(b.del_dst), t(b.ins_src), t(b.ins_dst))
 
-    def edges(self):
-        def e(s, d):
+    def edges(self, device=None):
+        """The two pr_edges views (deletions, insertions), after checking that
+        the arrays are int32, contiguous, on `device` (default: where del_src
+        is) and that each dst matches its src in length."""
+        import torch
+        dev = device if device is not None else self.del_src.device
+
+        def e(s, d, name):
+            _tensor(s, name + "_src", torch.int32, dev)
             n = int(s.numel())
+            if d is not None:
+                _tensor(d, name + "_dst", torch.int32, dev, numel=n)
             return PrEdges(s.data_ptr() if n else None, d.data_ptr() if (d is not None and n) else None, n)
 
-        return e(self.del_src, self.del_dst), e(self.ins_src, self.ins_dst)
+        return e(self.del_src, self.del_dst, "del"), e(self.ins_src, self.ins_dst, "ins")
 
 
 @dataclass
@@ -216,11 +273,12 @@ def static(g: DeviceGraph, alpha=ALPHA, tol=TOL, max_iter=MAX_ITERATIONS, out=No
     """Static PageRank (Alg. 1, Eq. 1) through pr_static."""
     torch = _torch()
     lib = load_library()
-    if out is None:
-        out = torch.empty(g.n, dtype=torch.float64, device=g.in_offsets.device)
-    assert out.dtype == torch.float64 and out.is_contiguous() and out.numel() == g.n
-    _bind_stream(lib, torch)
+    _on_current_device(g.device, torch)
     csr = g.csr()
+    if out is None:
+        out = torch.empty(g.n, dtype=torch.float64, device=g.device)
+    _tensor(out, "out", torch.float64, g.device, numel=g.n)
+    _bind_stream(lib, torch)
     rc = _check(lib.pr_static(ctypes.byref(csr), alpha, tol, max_iter, out.data_ptr()), lib)
     return _result(rc, out)
 
@@ -231,14 +289,20 @@ def dfp(g_new: DeviceGraph, batch: DeviceBatch, ranks_prev, alpha=ALPHA, tol=TOL
     """DF-P (default), DF, ND or DT update through pr_dfp / pr_dfp_ex."""
     torch = _torch()
     lib = load_library()
-    if out is None:
-        out = torch.empty(g_new.n, dtype=torch.float64, device=g_new.in_offsets.device)
-    assert ranks_prev.dtype == torch.float64 and ranks_prev.is_contiguous()
-    assert out.dtype == torch.float64 and out.is_contiguous() and out.numel() == g_new.n
-    _bind_stream(lib, torch)
+    if mode not in MODES:
+        raise ValueError(f"mode must be one of {sorted(MODES)}, got {mode!r}")
+    dev = g_new.device
+    _on_current_device(dev, torch)
     csr_new = g_new.csr()
     csr_old = g_old.csr() if g_old is not None else None
-    de, ie = batch.edges()
+    if g_old is not None and (g_old.device != dev or g_old.n != g_new.n):
+        raise ValueError("g_old must have g_new's vertex count and device")
+    de, ie = batch.edges(dev)
+    _tensor(ranks_prev, "ranks_prev", torch.float64, dev, numel=g_new.n)
+    if out is None:
+        out = torch.empty(g_new.n, dtype=torch.float64, device=dev)
+    _tensor(out, "out", torch.float64, dev, numel=g_new.n)
+    _bind_stream(lib, torch)
     if mode == "dfp" and max_iter == MAX_ITERATIONS:
         rc = lib.pr_dfp(ctypes.byref(csr_old) if csr_old else None, ctypes.byref(csr_new),
                         ctypes.byref(de), ctypes.byref(ie), ranks_prev.data_ptr(), alpha, tol,
@@ -257,17 +321,19 @@ def apply_batch(g_old: DeviceGraph, batch: DeviceBatch, out_view: bool = True) -
     targets. Returns a new DeviceGraph."""
     torch = _torch()
     lib = load_library()
-    nd, ni = int(batch.del_src.numel()), int(batch.ins_src.numel())
+    dev = g_old.device
+    _on_current_device(dev, torch)
+    csr_old = g_old.csr()
+    de, ie = batch.edges(dev)
+    nd, ni = de.count, ie.count
     m = g_old.m - nd + ni
-    dev = g_old.in_offsets.device
     e = lambda k: torch.empty(k, dtype=torch.int32, device=dev)
     io, isrc = e(g_old.n + 1), e(max(m, 1))
     oo, otg = (e(g_old.n + 1), e(max(m, 1))) if out_view else (None, None)
     p = lambda x: None if x is None else x.data_ptr()
     out = PrCsrOut(g_old.n, m, p(io), p(isrc), p(oo), p(otg))
     _bind_stream(lib, torch)
-    de, ie = batch.edges()
-    rc = lib.pr_apply_batch(ctypes.byref(g_old.csr()), ctypes.byref(de), ctypes.byref(ie),
+    rc = lib.pr_apply_batch(ctypes.byref(csr_old), ctypes.byref(de), ctypes.byref(ie),
                             ctypes.byref(out))
     _check(rc, lib)
     return DeviceGraph(g_old.n, m, io, isrc[:m], oo, otg[:m] if otg is not None else None)
@@ -279,17 +345,20 @@ def ppr(g: DeviceGraph, teleport, alpha=ALPHA, tol=TOL, max_iter=MAX_ITERATIONS,
     vector as a numpy array)."""
     torch = _torch()
     lib = load_library()
-    assert teleport.dtype == torch.float64 and teleport.is_contiguous()
+    _on_current_device(g.device, torch)
+    csr = g.csr()
+    _tensor(teleport, "teleport", torch.float64, g.device)
     if teleport.dim() == 1:
         teleport = teleport.view(-1, 1)
+    if teleport.dim() != 2 or teleport.shape[0] != g.n or teleport.shape[1] < 1:
+        raise ValueError(f"teleport: expected shape ({g.n}, k) with k >= 1, got "
+                         f"{tuple(teleport.shape)}")
     n, k = teleport.shape
-    assert n == g.n
     if out is None:
-        out = torch.empty((n, k), dtype=torch.float64, device=teleport.device)
-    assert out.dtype == torch.float64 and out.is_contiguous() and out.shape == (n, k)
+        out = torch.empty((n, k), dtype=torch.float64, device=g.device)
+    _tensor(out, "out", torch.float64, g.device, shape=(n, k))
     its = np.zeros(k, np.int32)
     _bind_stream(lib, torch)
-    csr = g.csr()
     rc = _check(lib.pr_ppr(ctypes.byref(csr), teleport.data_ptr(), k, alpha, tol, max_iter,
                            out.data_ptr(), its.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))),
                 lib)
@@ -306,9 +375,19 @@ def static_batched(graphs, alpha=ALPHA, tol=TOL, max_iter=MAX_ITERATIONS, outs=N
     torch = _torch()
     lib = load_library()
     G = len(graphs)
-    if outs is None:
-        outs = [torch.empty(g.n, dtype=torch.float64, device=g.in_offsets.device) for g in graphs]
+    if G < 1:
+        raise ValueError("static_batched needs at least one graph")
+    dev = graphs[0].device
+    _on_current_device(dev, torch)
+    if any(g.device != dev for g in graphs):
+        raise ValueError("all graphs of a batched call must be on one device")
     csrs = (PrCsr * G)(*[g.csr() for g in graphs])
+    if outs is None:
+        outs = [torch.empty(g.n, dtype=torch.float64, device=dev) for g in graphs]
+    if len(outs) != G:
+        raise ValueError(f"outs: expected {G} tensors, got {len(outs)}")
+    for i, (g, o) in enumerate(zip(graphs, outs)):
+        _tensor(o, f"outs[{i}]", torch.float64, dev, numel=g.n)
     ptrs = (ctypes.c_void_p * G)(*[o.data_ptr() for o in outs])
     its = np.zeros(G, np.int32)
     _bind_stream(lib, torch)
@@ -323,15 +402,15 @@ def weighted(g: DeviceGraph, in_weights, teleport=None, alpha=ALPHA, tol=TOL,
     in_weights: [m] float64 in in-CSR order; teleport: [n] or None (1/n)."""
     torch = _torch()
     lib = load_library()
-    assert in_weights.dtype == torch.float64 and in_weights.is_contiguous()
-    assert in_weights.numel() == g.m
-    if teleport is not None:
-        assert teleport.dtype == torch.float64 and teleport.is_contiguous()
-        assert teleport.numel() == g.n
-    if out is None:
-        out = torch.empty(g.n, dtype=torch.float64, device=in_weights.device)
-    _bind_stream(lib, torch)
+    _on_current_device(g.device, torch)
     csr = g.csr()
+    _tensor(in_weights, "in_weights", torch.float64, g.device, numel=g.m)
+    if teleport is not None:
+        _tensor(teleport, "teleport", torch.float64, g.device, numel=g.n)
+    if out is None:
+        out = torch.empty(g.n, dtype=torch.float64, device=g.device)
+    _tensor(out, "out", torch.float64, g.device, numel=g.n)
+    _bind_stream(lib, torch)
     rc = _check(lib.pr_weighted(ctypes.byref(csr), in_weights.data_ptr(), _ptr(teleport), alpha,
                                 tol, max_iter, out.data_ptr()), lib)
     return _result(rc, out)
@@ -343,14 +422,18 @@ def adjoint(g: DeviceGraph, in_weights, ranks, grad_ranks, alpha=ALPHA, tol=TOL,
     in-CSR order or None, grad_teleport [n] or None, lambda [n] or None)."""
     torch = _torch()
     lib = load_library()
-    for x in (in_weights, ranks, grad_ranks):
-        assert x.dtype == torch.float64 and x.is_contiguous()
-    dev = ranks.device
+    dev = g.device
+    _on_current_device(dev, torch)
+    csr = g.csr()
+    if g.out_offsets is None or g.out_targets is None:
+        raise ValueError("adjoint needs the graph's out-CSR view")
+    _tensor(in_weights, "in_weights", torch.float64, dev, numel=g.m)
+    _tensor(ranks, "ranks", torch.float64, dev, numel=g.n)
+    _tensor(grad_ranks, "grad_ranks", torch.float64, dev, numel=g.n)
     gw = torch.empty(g.m, dtype=torch.float64, device=dev) if want_weights else None
     gs = torch.empty(g.n, dtype=torch.float64, device=dev) if want_teleport else None
     lam = torch.empty(g.n, dtype=torch.float64, device=dev) if want_lambda else None
     _bind_stream(lib, torch)
-    csr = g.csr()
     _check(lib.pr_adjoint(ctypes.byref(csr), in_weights.data_ptr(), ranks.data_ptr(),
                           grad_ranks.data_ptr(), alpha, tol, max_iter, _ptr(gw), _ptr(gs),
                           _ptr(lam)), lib)
@@ -361,8 +444,9 @@ def validate(g: DeviceGraph) -> None:
     """Raises PrError(PR_EGRAPH) if the graph breaks the input contract."""
     torch = _torch()
     lib = load_library()
-    _bind_stream(lib, torch)
+    _on_current_device(g.device, torch)
     csr = g.csr()
+    _bind_stream(lib, torch)
     _check(lib.pr_validate_csr(ctypes.byref(csr)), lib)
 
 
