@@ -11,7 +11,9 @@
  *    torch tensor storage on the current HIP device). A call borrows them for
  *    its duration only. The library owns nothing but its internal workspace,
  *    which it allocates on first use per device, keeps for reuse, and frees
- *    in pr_release().
+ *    in pr_release(). Every array argument is checked before any work is
+ *    enqueued: host memory (pageable or pinned) or memory of another device
+ *    gives PR_EINVAL, and no kernel sees it.
  *  - Calls are synchronous with respect to the host: when a call returns,
  *    every output is complete on the stream given to pr_set_stream() (the
  *    default stream if none). Convergence is decided inside the call.

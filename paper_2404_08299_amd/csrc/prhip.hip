@@ -19,6 +19,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <initializer_list>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -330,6 +331,27 @@ hipEvent_t prof_event(Workspace &w, size_t i) {
   return w.prof_ev[i];
 }
 
+// A caller's array must be device (or managed) memory of the current
+// device: host memory handed to a kernel would fault the GPU, so it is
+// refused here. NULL passes (whether an array is required is checked by the
+// caller). Pageable host memory reads as unregistered, pinned host memory as
+// host memory; both are refused.
+int check_dev_ptr(const void *p, const char *name) {
+  if (!p) return PR_OK;
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(PR_EINVAL, std::string(name) + " is not device memory");
+  }
+  if (a.type != hipMemoryTypeDevice && a.type != hipMemoryTypeManaged)
+    return fail(PR_EINVAL, std::string(name) + " is not device memory");
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (a.type == hipMemoryTypeDevice && a.device != dev)
+    return fail(PR_EINVAL, std::string(name) + " is memory of another device");
+  return PR_OK;
+}
+
 int check_csr(const pr_csr *g, bool need_out_targets) {
   if (!g) return fail(PR_EINVAL, "csr is NULL");
   if (g->n <= 0) return fail(PR_EINVAL, "n must be > 0");
@@ -337,6 +359,28 @@ int check_csr(const pr_csr *g, bool need_out_targets) {
   if (!g->in_offsets || !g->in_sources || !g->out_offsets)
     return fail(PR_EINVAL, "in_offsets, in_sources and out_offsets are required");
   if (need_out_targets && !g->out_targets) return fail(PR_EINVAL, "out_targets is required");
+  return PR_OK;
+}
+
+// The graph's arrays, and then up to four more, on the current device. Entry
+// points call this after their scalar and structural checks, so those report
+// first.
+int on_device(const pr_csr *g, std::initializer_list<std::pair<const void *, const char *>> more) {
+  int rc;
+  if (g && ((rc = check_dev_ptr(g->in_offsets, "in_offsets")) ||
+            (rc = check_dev_ptr(g->in_sources, "in_sources")) ||
+            (rc = check_dev_ptr(g->out_offsets, "out_offsets")) ||
+            (rc = check_dev_ptr(g->out_targets, "out_targets"))))
+    return rc;
+  for (const auto &pm : more)
+    if ((rc = check_dev_ptr(pm.first, pm.second))) return rc;
+  return PR_OK;
+}
+
+int edges_on_device(const pr_edges *e, const char *src_name, const char *dst_name) {
+  if (!e || e->count <= 0) return PR_OK;
+  int rc;
+  if ((rc = check_dev_ptr(e->src, src_name)) || (rc = check_dev_ptr(e->dst, dst_name))) return rc;
   return PR_OK;
 }
 
@@ -1256,6 +1300,7 @@ int pr_static(const pr_csr *csr, double alpha, double tol, int max_iter, double 
   if (rc) return rc;
   if ((rc = check_params(alpha, tol, max_iter))) return rc;
   if (!ranks_out) return fail(PR_EINVAL, "ranks_out is NULL");
+  if ((rc = on_device(csr, {{ranks_out, "ranks_out"}}))) return rc;
   std::lock_guard<std::mutex> lock(g_mu);
   return run_static(csr, alpha, tol, max_iter, nullptr, ranks_out);
 }
@@ -1277,6 +1322,10 @@ int pr_dfp_ex(const pr_csr *csr_old, const pr_csr *csr_new, const pr_edges *dele
   if ((rc = check_edges(insertions, "insertions"))) return rc;
   if (deletions && deletions->count > 0 && !deletions->dst)
     return fail(PR_EINVAL, "deletions.dst is NULL");
+  if ((rc = on_device(csr_new, {{ranks_prev, "ranks_prev"}, {ranks_out, "ranks_out"}})) ||
+      (rc = edges_on_device(deletions, "deletions.src", "deletions.dst")) ||
+      (rc = edges_on_device(insertions, "insertions.src", "insertions.dst")))
+    return rc;
   std::lock_guard<std::mutex> lock(g_mu);
   if (mode == PR_MODE_ND) return run_static(csr_new, alpha, tol, max_iter, ranks_prev, ranks_out);
   return run_dynamic_frontier(csr_new, deletions, insertions, ranks_prev, alpha, tol,
@@ -1300,6 +1349,7 @@ int pr_ppr(const pr_csr *csr, const double *teleport, int k, double alpha, doubl
   if (!teleport || !ranks_out) return fail(PR_EINVAL, "teleport and ranks_out are required");
   if ((size_t)csr->n * (size_t)k > ((size_t)1 << 40))
     return fail(PR_EINVAL, "n * k too large");
+  if ((rc = on_device(csr, {{teleport, "teleport"}, {ranks_out, "ranks_out"}}))) return rc;
   std::lock_guard<std::mutex> lock(g_mu);
   return run_ppr(csr, teleport, k, alpha, tol, max_iter, ranks_out, iters_out);
 }
@@ -1316,6 +1366,8 @@ int pr_static_batched(const pr_csr *graphs, int num_graphs, double alpha, double
     if (!ranks_out[g]) return fail(PR_EINVAL, "ranks_out[g] is NULL");
   }
   if ((rc = check_params(alpha, tol, max_iter))) return rc;
+  for (int g = 0; g < num_graphs; ++g)
+    if ((rc = on_device(&graphs[g], {{ranks_out[g], "ranks_out[g]"}}))) return rc;
   std::lock_guard<std::mutex> lock(g_mu);
   return run_batched(graphs, num_graphs, alpha, tol, max_iter, ranks_out, iters_out);
 }
@@ -1327,6 +1379,9 @@ int pr_weighted(const pr_csr *csr, const double *in_weights, const double *telep
   if (rc) return rc;
   if ((rc = check_params(alpha, tol, max_iter))) return rc;
   if (!in_weights || !ranks_out) return fail(PR_EINVAL, "in_weights and ranks_out are required");
+  if ((rc = on_device(csr, {{in_weights, "in_weights"}, {teleport, "teleport"},
+                            {ranks_out, "ranks_out"}})))
+    return rc;
   std::lock_guard<std::mutex> lock(g_mu);
   return run_weighted(csr, in_weights, teleport, alpha, tol, max_iter, ranks_out);
 }
@@ -1342,6 +1397,11 @@ int pr_adjoint(const pr_csr *csr, const double *in_weights, const double *ranks,
     return fail(PR_EINVAL, "in_weights, ranks and grad_ranks are required");
   if (!grad_weights && !grad_teleport && !lambda_out)
     return fail(PR_EINVAL, "no output requested");
+  if ((rc = on_device(csr, {{in_weights, "in_weights"}, {ranks, "ranks"},
+                            {grad_ranks, "grad_ranks"}})) ||
+      (rc = on_device(nullptr, {{grad_weights, "grad_weights"}, {grad_teleport, "grad_teleport"},
+                                {lambda_out, "lambda_out"}})))
+    return rc;
   std::lock_guard<std::mutex> lock(g_mu);
   double *tmp = nullptr;
   if (!lambda_out) {
@@ -1377,6 +1437,13 @@ int pr_apply_batch(const pr_csr *old, const pr_edges *deletions, const pr_edges 
     return fail(PR_EINVAL, "deletions.dst and insertions.dst are required");
   if (out->n != old->n || (long long)out->m != (long long)old->m - nd + ni)
     return fail(PR_EINVAL, "out->n must equal old->n and out->m = old->m - deletions + insertions");
+  if ((rc = on_device(old, {{out->in_offsets, "out->in_offsets"},
+                            {out->in_sources, "out->in_sources"},
+                            {out->out_offsets, "out->out_offsets"},
+                            {out->out_targets, "out->out_targets"}})) ||
+      (rc = edges_on_device(deletions, "deletions.src", "deletions.dst")) ||
+      (rc = edges_on_device(insertions, "insertions.src", "insertions.dst")))
+    return rc;
   std::lock_guard<std::mutex> lock(g_mu);
   const int32_t *ds = nd ? deletions->src : nullptr, *dd = nd ? deletions->dst : nullptr;
   const int32_t *is = ni ? insertions->src : nullptr, *id = ni ? insertions->dst : nullptr;
@@ -1409,6 +1476,7 @@ int pr_validate_csr(const pr_csr *g) {
   reset_stats();
   int rc = check_csr(g, false);
   if (rc) return rc;
+  if ((rc = on_device(g, {}))) return rc;
   std::lock_guard<std::mutex> lock(g_mu);
   hipStream_t s = t_stream;
   Workspace *wp = nullptr;

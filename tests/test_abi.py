@@ -58,27 +58,36 @@ def test_argument_errors_before_hip(lib):
     csr = prhip.PrCsr(0, 0, None, None, None, None)
     assert lib.pr_static(ctypes.byref(csr), 0.85, 1e-10, 500, None) == prhip.PR_EINVAL
     csr = prhip.PrCsr(4, 4, 8, 8, 8, None)  # non-NULL fake pointers: never dereferenced
-    for alpha, tol, it in [(0.0, 1e-10, 5), (1.0, 1e-10, 5), (0.85, -1.0, 5), (0.85, 1e-10, 0),
-                           (float("nan"), 1e-10, 5)]:
+    # each refusal names its reason: scalar and structural checks come before
+    # the arrays' memory is examined
+    for alpha, tol, it, why in [(0.0, 1e-10, 5, b"alpha"), (1.0, 1e-10, 5, b"alpha"),
+                                (0.85, -1.0, 5, b"tol"), (0.85, 1e-10, 0, b"max_iter"),
+                                (float("nan"), 1e-10, 5, b"alpha")]:
         assert lib.pr_static(ctypes.byref(csr), alpha, tol, it, ctypes.c_void_p(8)) == prhip.PR_EINVAL
+        assert why in lib.pr_last_error()
     # pr_dfp needs out_targets
     assert lib.pr_dfp(None, ctypes.byref(csr), None, None, ctypes.c_void_p(8), 0.85, 1e-10, 1e-6,
                       1e-6, ctypes.c_void_p(8)) == prhip.PR_EINVAL
+    assert b"out_targets" in lib.pr_last_error()
     csr2 = prhip.PrCsr(4, 4, 8, 8, 8, 8)
     bad = prhip.PrEdges(None, None, 3)
     assert lib.pr_dfp(None, ctypes.byref(csr2), ctypes.byref(bad), None, ctypes.c_void_p(8), 0.85,
                       1e-10, 1e-6, 1e-6, ctypes.c_void_p(8)) == prhip.PR_EINVAL
+    assert b"src is NULL" in lib.pr_last_error()
     # pr_apply_batch: output sizes and required arrays are checked before any HIP call
     out = prhip.PrCsrOut(4, 5, 8, 8, None, None)  # m must be 4 - 0 + 0
     assert lib.pr_apply_batch(ctypes.byref(csr2), None, None, ctypes.byref(out)) == prhip.PR_EINVAL
+    assert b"out->m" in lib.pr_last_error()
     out = prhip.PrCsrOut(4, 5, 8, 8, None, None)
     ins = prhip.PrEdges(8, None, 1)  # insertion targets are required here
     assert lib.pr_apply_batch(ctypes.byref(csr2), None, ctypes.byref(ins),
                               ctypes.byref(out)) == prhip.PR_EINVAL
+    assert b"insertions.dst" in lib.pr_last_error()
     assert lib.pr_apply_batch(ctypes.byref(csr2), None, None, None) == prhip.PR_EINVAL
     for mode in (-1, 4, 7):  # PR_MODE_DFP, _DF, _ND, _DT are 0 .. 3
         assert lib.pr_dfp_ex(None, ctypes.byref(csr2), None, None, ctypes.c_void_p(8), 0.85,
                              1e-10, 1e-6, 1e-6, 500, mode, ctypes.c_void_p(8)) == prhip.PR_EINVAL
+        assert b"mode" in lib.pr_last_error()
     text = open(os.path.join(ROOT, "include", "prhip.h")).read()
     for name, val in prhip.MODES.items():
         assert re.search(r"#define PR_MODE_%s %d\b" % (name.upper(), val), text), name
@@ -155,3 +164,22 @@ def test_batched_argument_errors(lib):
     assert lib.pr_static_batched(csr, 0, 0.85, 1e-10, 10, outs, None) == prhip.PR_EINVAL
     assert lib.pr_static_batched(csr, 5000, 0.85, 1e-10, 10, outs, None) == prhip.PR_EINVAL
     assert lib.pr_static_batched(csr, 2, 0.85, 1e-10, 10, outs, None) == prhip.PR_EINVAL  # n = 0
+
+
+def test_host_memory_is_refused(lib):
+    """With valid scalars, arrays that are not device memory of the current
+    device (here host addresses; on a machine without a GPU nothing is) are
+    refused with PR_EINVAL before any work is enqueued."""
+    import numpy as np
+    off = np.array([0, 1, 2, 3, 4], np.int32)
+    src = np.array([0, 1, 2, 3], np.int32)
+    r = np.zeros(4)
+    p = lambda a: a.ctypes.data
+    csr = prhip.PrCsr(4, 4, p(off), p(src), p(off), p(src))
+    assert lib.pr_static(ctypes.byref(csr), 0.85, 1e-10, 5, ctypes.c_void_p(p(r))) == prhip.PR_EINVAL
+    assert b"not device memory" in lib.pr_last_error()
+    assert lib.pr_validate_csr(ctypes.byref(csr)) == prhip.PR_EINVAL
+    assert b"not device memory" in lib.pr_last_error()
+    assert lib.pr_dfp(None, ctypes.byref(csr), None, None, ctypes.c_void_p(p(r)), 0.85, 1e-10,
+                      1e-6, 1e-6, ctypes.c_void_p(p(r))) == prhip.PR_EINVAL
+    assert b"not device memory" in lib.pr_last_error()

@@ -114,3 +114,21 @@ def test_graph_arrays_are_checked(case):
                               dg.out_targets)
     with pytest.raises(ValueError, match="in_sources"):
         prhip.validate(mixed)
+
+
+def test_c_abi_refuses_host_outputs(case):
+    """Straight through the C ABI (no binding checks): a device graph with a
+    pageable or pinned host output array gets PR_EINVAL, and no kernel runs."""
+    import ctypes
+    g, dg, _, _ = case
+    lib = prhip.load_library()
+    csr = dg.csr()
+    host = np.zeros(g.n)
+    pinned = torch.zeros(g.n, dtype=torch.float64).pin_memory()
+    for addr in (host.ctypes.data, pinned.data_ptr()):
+        rc = lib.pr_static(ctypes.byref(csr), 0.85, 1e-10, 500, ctypes.c_void_p(addr))
+        assert rc == prhip.PR_EINVAL
+        assert b"ranks_out is not device memory" in lib.pr_last_error()
+    assert np.all(host == 0.0) and bool((pinned == 0).all())
+    # the library is still usable afterwards
+    assert prhip.static(dg).converged
