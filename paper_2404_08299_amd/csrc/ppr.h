@@ -89,19 +89,37 @@ __global__ __launch_bounds__(kBlock) void k_ppr_rank(
     for (int k = lane; k < K; k += kWave)
       if (!vdone[k]) part[(size_t)c * K + k] = ppr_row_sum(in_src, X, K, k, e0, e1);
   }
-  // other rows: full sums and the update
-  for (int v = gw; v < n; v += W) {
-    if (deg_split[v]) continue;
-    const int e0 = in_off[v], e1 = in_off[v + 1];
-    const double d = (double)(out_off[v + 1] - out_off[v]);
-    const size_t px = (size_t)xpos(pos, v) * K, pv = (size_t)v * K;
-    for (int k = lane; k < K; k += kWave) {
-      if (vdone[k]) continue;
-      const double c = ppr_row_sum(in_src, X, K, k, e0, e1);
-      const double r = oma * (tnz[v] ? S[pv + k] : 0.0) + alpha * c;
-      st_nt(Rn + pv + k, r);
-      Xn[px + k] = r / d;
-      s_max[wid * K + k] = fmax(s_max[wid * K + k], fabs(r - R[pv + k]));
+  // other rows: full sums and the update. Wavefront gw takes rows gw, gw + W,
+  // ... in that order; it loads the metadata of its next 64 rows (one per
+  // lane) in one round trip and then walks them one by one.
+  for (long long k0 = 0; gw + k0 * W < n; k0 += kWave) {
+    const long long vl = gw + (k0 + lane) * W;
+    int me0 = 0, me1 = 0, mdeg = 1, mpx = 0, mt = 0;
+    bool ok = false;
+    if (vl < n && !deg_split[vl]) {
+      ok = true;
+      me0 = in_off[vl];
+      me1 = in_off[vl + 1];
+      mdeg = out_off[vl + 1] - out_off[vl];
+      mpx = xpos(pos, (int)vl);
+      mt = tnz[vl];
+    }
+    unsigned long long mask = __ballot(ok);
+    while (mask) {
+      const int j = __ffsll(mask) - 1;
+      mask &= mask - 1;
+      const int v = (int)(gw + (k0 + j) * W);
+      const int e0 = __shfl(me0, j), e1 = __shfl(me1, j), t = __shfl(mt, j);
+      const double d = (double)__shfl(mdeg, j);
+      const size_t px = (size_t)__shfl(mpx, j) * K, pv = (size_t)v * K;
+      for (int k = lane; k < K; k += kWave) {
+        if (vdone[k]) continue;
+        const double c = ppr_row_sum(in_src, X, K, k, e0, e1);
+        const double r = oma * (t ? S[pv + k] : 0.0) + alpha * c;
+        st_nt(Rn + pv + k, r);
+        Xn[px + k] = r / d;
+        s_max[wid * K + k] = fmax(s_max[wid * K + k], fabs(r - R[pv + k]));
+      }
     }
   }
   __syncthreads();
