@@ -34,21 +34,51 @@ __device__ __forceinline__ int find_base(const int *__restrict__ base, int G, in
 }
 
 // Union CSR: offsets and sources shifted by the graph's bases; gid[v] = g.
+// Vertices and edges are taken in runs of kUnionRun consecutive elements per
+// workgroup: the graph of a run's first element is found once (binary search
+// over the bases), and each thread steps to the next graph only when its
+// element crosses that graph's base, so the copy streams instead of
+// searching per element.
+constexpr int kUnionRun = 16 * kBlock;
 __global__ __launch_bounds__(kBlock) void k_union_build(
     const BatchDesc *__restrict__ d, const int *__restrict__ vbase, const int *__restrict__ ebase,
     int G, int N, int M, int *__restrict__ in_off, int *__restrict__ in_src,
     int *__restrict__ out_off, int *__restrict__ gid) {
-  const int stride = gridDim.x * kBlock;
-  for (int v = blockIdx.x * kBlock + threadIdx.x; v < N; v += stride) {
-    const int g = find_base(vbase, G, v);
-    const int lv = v - d[g].vb;
-    in_off[v] = d[g].eb + d[g].in_off[lv];
-    out_off[v] = d[g].eb + d[g].out_off[lv];
-    gid[v] = g;
+  const long long rstride = (long long)gridDim.x * kUnionRun;
+  for (long long r0 = (long long)blockIdx.x * kUnionRun; r0 < N; r0 += rstride) {
+    const int r1 = (int)min((long long)N, r0 + kUnionRun);
+    int g = find_base(vbase, G, (int)r0);
+    int next = vbase[g + 1], vb = d[g].vb, eb = d[g].eb;
+    const int *io = d[g].in_off, *oo = d[g].out_off;
+    for (int v = (int)r0 + threadIdx.x; v < r1; v += kBlock) {
+      while (v >= next) {
+        ++g;
+        next = vbase[g + 1];
+        vb = d[g].vb;
+        eb = d[g].eb;
+        io = d[g].in_off;
+        oo = d[g].out_off;
+      }
+      in_off[v] = eb + io[v - vb];
+      out_off[v] = eb + oo[v - vb];
+      gid[v] = g;
+    }
   }
-  for (int e = blockIdx.x * kBlock + threadIdx.x; e < M; e += stride) {
-    const int g = find_base(ebase, G, e);
-    in_src[e] = d[g].vb + d[g].in_src[e - d[g].eb];
+  for (long long r0 = (long long)blockIdx.x * kUnionRun; r0 < M; r0 += rstride) {
+    const int r1 = (int)min((long long)M, r0 + kUnionRun);
+    int g = find_base(ebase, G, (int)r0);
+    int next = ebase[g + 1], vb = d[g].vb, eb = d[g].eb;
+    const int *src = d[g].in_src;
+    for (int e = (int)r0 + threadIdx.x; e < r1; e += kBlock) {
+      while (e >= next) {
+        ++g;
+        next = ebase[g + 1];
+        vb = d[g].vb;
+        eb = d[g].eb;
+        src = d[g].in_src;
+      }
+      in_src[e] = vb + src[e - eb];
+    }
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     in_off[N] = M;
