@@ -231,6 +231,54 @@ def pin_pull_rows_weighted_and_ppr_dense(lib):
     assert np.abs(got - ref[rows]).max() <= 1e-14 * np.abs(ref).max()
 
 
+def _in_star_recurrence(k, x, y, tol, a=ALPHA, max_iter=100000):
+    """Eq. 1 iterates of the in-star from leaf value x and center value y:
+    x' = C0 + a x/2, y' = C0 + a (y + k x/2). Returns [(x_i, y_i)] for
+    i = 1 .. the first iteration whose L-infinity change is <= tol."""
+    n = k + 1
+    C0 = (1 - a) / n
+    out = []
+    for _ in range(max_iter):
+        x2 = C0 + a * (x / 2)
+        y2 = C0 + a * (y + k * (x / 2))
+        delta = max(abs(x2 - x), abs(y2 - y))
+        x, y = x2, y2
+        out.append((x, y))
+        if delta <= tol:
+            break
+    return out
+
+
+def _check_star_iterate(ranks, xy, k):
+    x, y = xy
+    assert abs(ranks[0] - y) <= 1e-15 and np.abs(ranks[1:k + 1] - x).max() <= 1e-15, (
+        ranks[:3], x, y)
+
+
+def pin_nd_start_vector(lib):
+    """Naive-dynamic (Sec. 3.4.1) is Alg. 1 started from the previous ranks.
+    From a non-uniform start on the in-star, the first iterate and the
+    iteration counts at two tolerances follow the Eq. 1 recurrence started
+    from that vector (a run from 1/N gives other iterates and counts)."""
+    k = 9
+    n = k + 1
+    g = in_star(k)
+    s, d = g.edges()
+    x0 = 0.02
+    init = np.full(n, x0)
+    init[0] = 1.0 - k * x0
+    seq = _in_star_recurrence(k, x0, init[0], tol=0.0, max_iter=1)
+    res = oracle.static(n, s, d, tol=0.0, max_iter=1, init=init, lib=lib)
+    assert res.status == oracle.NOT_CONVERGED and res.iters == 1
+    _check_star_iterate(res.ranks, seq[0], k)
+    for tol in (1e-6, 1e-10):
+        seq = _in_star_recurrence(k, x0, init[0], tol)
+        res = oracle.static(n, s, d, tol=tol, init=init, lib=lib)
+        assert res.status == oracle.OK and res.iters == len(seq), (tol, res.iters, len(seq))
+        _check_star_iterate(res.ranks, seq[-1], k)
+    assert res.iters != oracle.static(n, s, d, tol=1e-10, lib=lib).iters
+
+
 # ---------------------------------------------------------------- DF-P pins
 def _affected_all(n):
     """A marking-only batch whose insertion sources are every vertex:
@@ -356,6 +404,79 @@ def pin_dfp_eq2_one_step(lib):
     assert abs(res.ranks[0] - rc) <= 4e-16 * rc
     assert res.trace[0].tolist() == [1, 1] + [0] * (k - 1)
     assert res.trace[1].tolist() == [1, 1] + [0] * (k - 1)
+
+
+def pin_df_eq1_iterate(lib):
+    """DF (Sec. 4.3) updates affected vertices with Eq. 1 and never prunes.
+    With every vertex affected (a marking batch whose sources are all
+    vertices) its iterates from R^{t-1} are the plain Eq. 1 iterates: on the
+    in-star they follow the two-variable recurrence, with the same iteration
+    count at each tolerance. Eq. 2 would put a leaf (its only in-edge is its
+    self-loop) on its fixed point in one step, so its iterates differ."""
+    k = 9
+    n = k + 1
+    g = in_star(k)
+    s, d = g.edges()
+    x0 = 0.03
+    prev = np.full(n, x0)
+    prev[0] = 1.0 - k * x0
+    seq = _in_star_recurrence(k, x0, prev[0], tol=0.0, max_iter=1)
+    res = oracle.dfp(n, s, d, _affected_all(n), prev, tol=0.0, tau_f=-1.0, max_iter=1,
+                     prune=False, lib=lib)
+    assert res.iters == 1
+    _check_star_iterate(res.ranks, seq[0], k)
+    for tol in (1e-6, 1e-10):
+        seq = _in_star_recurrence(k, x0, prev[0], tol)
+        res = oracle.dfp(n, s, d, _affected_all(n), prev, tol=tol, tau_f=-1.0, prune=False,
+                         lib=lib)
+        assert res.status == oracle.OK and res.iters == len(seq), (tol, res.iters, len(seq))
+        _check_star_iterate(res.ranks, seq[-1], k)
+        # every vertex is updated in every iteration: in-edges processed = m
+        # per iteration, and the affected set is all of V throughout
+        assert res.stats["edges_processed"] == res.iters * g.m
+        assert res.stats["affected_max"] == n and res.stats["affected_ever"] == n
+
+
+def _counters_from_trace(g, trace, iters):
+    """The affected-set statistics recounted from the per-iteration affected
+    flags: initial size, largest size, in-edges of the affected vertices
+    summed over the iterations, and the union's size."""
+    indeg = g.in_degree().astype(np.int64)
+    rows = trace[:iters].astype(bool)
+    sizes = rows.sum(axis=1)
+    return dict(affected_initial=int(trace[0].sum()), affected_max=int(sizes.max()),
+                edges_processed=int(sum(indeg[r].sum() for r in rows)),
+                affected_ever=int(rows.any(axis=0).sum()))
+
+
+def pin_dfp_counters_brute_force(lib):
+    """The affected-set counters of DF/DF-P (in-edges processed, largest
+    affected set, Sec. 5 measurement) against a recount over the affected
+    flags of every iteration. Two cases where the affected set grows after
+    the initial marking: frontier reachability on a small graph (tau_f =
+    tau_p = -1; the flags themselves are pinned by breadth-first search
+    above), and DF-P and DF on an R-MAT graph with a random batch."""
+    n = 12
+    es = [(0, 1), (1, 2), (2, 3), (3, 4), (4, 5), (6, 7), (7, 8), (8, 6), (9, 10), (5, 11)]
+    g = gg.from_edges(n, [e[0] for e in es], [e[1] for e in es])
+    s, d = g.edges()
+    batch = gg.Batch(np.array([6], np.int32), np.array([9], np.int32),
+                     np.array([0], np.int32), np.array([3], np.int32))
+    res = oracle.dfp(n, s, d, batch, np.full(n, 1.0 / n), tol=0.0, tau_f=-1.0, tau_p=-1.0,
+                     max_iter=5, trace=True, lib=lib)
+    expect = _counters_from_trace(g, res.trace, res.iters)
+    assert res.stats == expect, (res.stats, expect)
+    assert expect["affected_max"] > expect["affected_initial"]
+    g0 = gg.rmat_graph(9, 8, seed=13)
+    prev = oracle.static(g0.n, *g0.edges(), lib=lib).ranks
+    b = gg.random_batch(g0, 12, seed=5)
+    g1 = gg.apply_batch(g0, b)
+    s1, d1 = g1.edges()
+    for prune in (True, False):
+        res = oracle.dfp(g1.n, s1, d1, b, prev, prune=prune, trace=True, lib=lib)
+        expect = _counters_from_trace(g1, res.trace, res.iters)
+        assert res.stats == expect, (prune, res.stats, expect)
+        assert expect["affected_max"] > expect["affected_initial"], expect
 
 
 def pin_dfp_csr_input(lib):
@@ -486,6 +607,49 @@ def pin_weighted_dense(lib):
     assert np.abs(res2.ranks - dense_solve(g.n, s, d, s=tele2, w=P)).max() <= 1e-13
 
 
+def pin_weighted_start_vector(lib):
+    """The weighted forward from a given start vector: on the in-star with
+    leaf self-loop weight p, leaf-to-center weight 1 - p and center self-loop
+    weight 1, the iterates follow x' = (1-a) s_l + a p x and
+    y' = (1-a) s_c + a (y + sum over leaves of (1-p) x) from that vector
+    (first iterate and iteration count). The teleport differs per leaf, so
+    the leaf values form a vector."""
+    k = 7
+    n = k + 1
+    a = ALPHA
+    p = 0.3
+    g = in_star(k)
+    s, d = g.edges()
+    w = np.where(s == d, np.where(s == 0, 1.0, p), 1.0 - p)
+    tele = np.linspace(1.0, 2.0, n)
+    tele /= tele.sum()
+    x0, y0 = 0.05, 1.0 - k * 0.05
+    init = np.full(n, x0)
+    init[0] = y0
+
+    def step(x, y):
+        return (1 - a) * tele[1:] + a * (p * x), (1 - a) * tele[0] + a * (y + ((1 - p) * x).sum())
+
+    x, y = np.full(k, x0), y0
+    res = oracle.weighted(n, s, d, w, tele, tol=0.0, max_iter=1, init=init, lib=lib)
+    x1, y1 = step(x, y)
+    assert res.status == oracle.NOT_CONVERGED
+    assert abs(res.ranks[0] - y1) <= 1e-15 and np.abs(res.ranks[1:] - x1).max() <= 1e-15
+    for tol in (1e-8, 1e-12):
+        x, y = np.full(k, x0), y0
+        it = 0
+        while True:
+            x2, y2 = step(x, y)
+            it += 1
+            delta = max(np.abs(x2 - x).max(), abs(y2 - y))
+            x, y = x2, y2
+            if delta <= tol:
+                break
+        res = oracle.weighted(n, s, d, w, tele, tol=tol, init=init, lib=lib)
+        assert res.status == oracle.OK and res.iters == it, (tol, res.iters, it)
+        assert abs(res.ranks[0] - y) <= 1e-15 and np.abs(res.ranks[1:] - x).max() <= 1e-15
+
+
 def pin_adjoint_dense_and_fd(lib):
     """lambda = (I - a A^T)^{-1} g by LU; gradients against central finite
     differences (h = 1e-6) of a dense forward solve of the loss
@@ -523,6 +687,8 @@ ALL_PINS = [
     pin_static_dense, pin_static_cycle, pin_static_single_vertex, pin_static_in_star,
     pin_static_out_star, pin_static_local_closed_form, pin_static_invariants,
     pin_static_contraction, pin_static_rows_dense, pin_pull_rows_weighted_and_ppr_dense,
+    pin_nd_start_vector, pin_df_eq1_iterate, pin_dfp_counters_brute_force,
+    pin_weighted_start_vector,
     pin_dfp_empty_batch, pin_dfp_eq2_fixed_point,
     pin_dfp_frontier_reachability, pin_dfp_initial_marking, pin_dfp_eq2_one_step,
     pin_dfp_csr_input,

@@ -45,6 +45,16 @@ MUTANTS = {
                                    "(1.0 - alpha) * s[(size_t)j * (size_t)n + (size_t)v] : C0;"),
     "rows_weight_ignored": ("if (w) c = c + w[e] * x;", "if (w) c = c + x;"),
     "dt_deletion_target_unmarked": ("{ dV[del_dst[i]] = 1; dN[del_src[i]] = 1; }", "{ dN[del_src[i]] = 1; }"),
+    "df_uses_eq2": ("else r = C0 + alpha * c;",
+                    "else r = 1.0 / (1.0 - alpha / dv) * (C0 + alpha * (c - R[v] / dv));"),
+    "nd_ignores_start_vector": ("R[v] = Rn[v] = init ? init[v] : 1.0 / (double)n;\n  const double C0",
+                                "R[v] = Rn[v] = 1.0 / (double)n;\n  const double C0"),
+    "weighted_ignores_start_vector": ("R[v] = Rn[v] = init ? init[v] : 1.0 / (double)n;\n  int32_t it",
+                                      "R[v] = Rn[v] = 1.0 / (double)n;\n  int32_t it"),
+    "edges_processed_doubled": ("edges += a.in_off[v + 1] - a.in_off[v];",
+                                "edges += 2 * (a.in_off[v + 1] - a.in_off[v]);"),
+    "affected_max_frozen_at_initial": ("if (aff > affmax) affmax = aff;", "affmax = aff0;"),
+    "affected_ever_initial_only": ("if (dV[v]) ever[v] = 1;", "if (dV[v] && it == 0) ever[v] = 1;"),
 }
 
 
