@@ -45,6 +45,9 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_rank_static_rmat24.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2404_08299_amd", "csrc", f)
                   for f in ("kernels.h", "wave.h")]
+PPR_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_ppr_rmat20_k64.txt")
+PPR_SOURCES = [os.path.join(ROOT, "paper_2404_08299_amd", "csrc", f)
+               for f in ("ppr.h", "kernels.h", "wave.h")]
 ALL_LEGS = ("static", "dfp", "ppr", "batched", "adjoint")
 
 
@@ -52,9 +55,9 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_hash():
+def kernel_hash(sources=None):
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in sources or KERNEL_SOURCES:
         h.update(open(p, "rb").read())
     return h.hexdigest()[:16]
 
@@ -66,22 +69,49 @@ def algorithmic_bytes(n, m):
     return 4 * m + 28 * n
 
 
-def read_traffic():
-    """Measured HBM bytes per rank-kernel launch from the committed
-    rocprofv3 PMC summary, if it was taken on the current kernel source."""
-    if not os.path.exists(TRAFFIC_FILE):
+def read_traffic(path=None, sources=None):
+    """Measured HBM bytes per launch from a committed rocprofv3 PMC summary
+    (default: the Static rank kernel's), if it was taken on the current
+    kernel source (else None)."""
+    path = path or TRAFFIC_FILE
+    if not os.path.exists(path):
         return None
     vals = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("kernel_sha256") != kernel_hash():
+    if vals.get("kernel_sha256") != kernel_hash(sources):
         return None
     try:
         return float(vals["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def ppr_algorithmic_bytes(n, m, k):
+    """Compulsory bytes of one personalised-PageRank launch over k active
+    vectors: 4m in_sources + 8kn contributions gathered once + 8kn new ranks
+    written (the teleport rows are sparse and the offsets negligible)."""
+    return 4 * m + 16 * k * n
+
+
+def cpu_info():
+    """Host CPU model, logical CPUs and the CPUs this process may run on."""
+    model, mhz = None, None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if model is None and line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+            if mhz is None and line.startswith("cpu MHz"):
+                mhz = float(line.split(":", 1)[1])
+    except OSError:
+        pass
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except AttributeError:
+        aff = None
+    return {"cpu_model": model, "cpu_mhz": mhz, "nproc": os.cpu_count(), "affinity_cpus": aff}
 
 
 def copy_probe(gib=1.0, reps=5):
@@ -127,24 +157,33 @@ def temporal_leg(args, gg, prhip, torch, np):
     log(f"temporal: n={g0.n} m0={g0.m} m_end={dgs[-1].m}, {len(dgs)} batches "
         f"({time.time() - t:.1f} s)")
     prev = prhip.static(prhip.DeviceGraph.from_host(g0)).ranks
+    prev_df = prev.clone()
     outs = [torch.empty(g0.n, dtype=torch.float64, device="cuda") for _ in range(2)]
+    outs_df = [torch.empty(g0.n, dtype=torch.float64, device="cuda") for _ in range(2)]
     st_out = torch.empty(g0.n, dtype=torch.float64, device="cuda")
     ref = torch.empty(g0.n, dtype=torch.float64, device="cuda")
-    dfp_ms, st_ms, dfp_it, errs = [], [], [], []
+    dfp_ms, df_ms, st_ms, dfp_it, df_it, errs = [], [], [], [], [], []
     for k, (dg, db) in enumerate(zip(dgs, dbs)):
-        out = outs[k & 1]
+        # DF-P and DF (no pruning, the paper's accuracy fallback) each chained
+        # over the stream, and Static on G^t
+        out, out_df = outs[k & 1], outs_df[k & 1]
         _, ms_d = timed(lambda: prhip.dfp(dg, db, prev, out=out))
         dfp_it.append(prhip.last_stats()["iterations"])
+        _, ms_f = timed(lambda: prhip.dfp(dg, db, prev_df, mode="df", out=out_df))
+        df_it.append(prhip.last_stats()["iterations"])
         _, ms_s = timed(lambda: prhip.static(dg, out=st_out))
         dfp_ms.append(ms_d)
+        df_ms.append(ms_f)
         st_ms.append(ms_s)
-        prev = out
+        prev, prev_df = out, out_df
         if k % 10 == 9 or k == len(dgs) - 1:
             with warnings.catch_warnings():
                 warnings.simplefilter("ignore")
                 prhip.static(dg, tol=0.0, max_iter=500, out=ref)
             d = (out - ref).abs()
+            d_df = (out_df - ref).abs()
             errs.append({"batch": k + 1, "dfp_linf": float(d.max()), "dfp_l1": float(d.sum()),
+                         "df_linf": float(d_df.max()), "df_l1": float(d_df.sum()),
                          "static_linf": float((st_out - ref).abs().max()),
                          "max_rank": float(ref.max())})
     gm = lambda a: float(np.exp(np.mean(np.log(a))))
@@ -156,9 +195,46 @@ def temporal_leg(args, gg, prhip, torch, np):
            "dfp_ms_geomean": round(gm(dfp_ms), 3), "static_ms_geomean": round(gm(st_ms), 3),
            "dfp_speedup_geomean": round(gm(np.array(st_ms) / np.array(dfp_ms)), 2),
            "dfp_iters_mean": round(float(np.mean(dfp_it)), 2),
-           "max_dfp_linf": max(e["dfp_linf"] for e in errs), "errors": errs}
-    log(f"temporal: DF-P {res['dfp_ms_geomean']} ms vs Static {res['static_ms_geomean']} ms "
-        f"per batch (geomean), max DF-P L-inf {res['max_dfp_linf']:.2e}")
+           "df_ms_geomean": round(gm(df_ms), 3),
+           "df_speedup_geomean": round(gm(np.array(st_ms) / np.array(df_ms)), 2),
+           "df_iters_mean": round(float(np.mean(df_it)), 2),
+           "max_dfp_linf": max(e["dfp_linf"] for e in errs),
+           "max_df_linf": max(e["df_linf"] for e in errs), "errors": errs}
+    log(f"temporal: DF-P {res['dfp_ms_geomean']} ms, DF {res['df_ms_geomean']} ms vs Static "
+        f"{res['static_ms_geomean']} ms per batch (geomean), max L-inf DF-P "
+        f"{res['max_dfp_linf']:.2e}, DF {res['max_df_linf']:.2e}")
+    return res
+
+
+def small_leg(gg, prhip, torch, np, calls=30):
+    """The small configuration: R-MAT scale 14, edge factor 8, seed 1, Static
+    at tol 1e-10. About 1 MB of data per iteration, resident in L2: a latency
+    figure (microseconds per iteration), not a bandwidth one. Each iteration
+    launches three kernels (rank update, long-row finalize, L-infinity final)
+    and copies the 64-byte control block to the host."""
+    g = gg.rmat_graph(14, 8, seed=1)
+    dg = prhip.DeviceGraph.from_host(g)
+    out = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        prhip.static(dg, out=out)
+    times = []
+    for _ in range(calls):
+        _, ms = timed(lambda: prhip.static(dg, out=out))
+        times.append(ms)
+    iters = prhip.last_stats()["iterations"]
+    prhip.set_profiling(True, counters=False)
+    prhip.static(dg, out=out)
+    st = prhip.last_stats()
+    prhip.set_profiling(False)
+    med = float(np.median(times))
+    res = {"workload": "rmat14_ef8_static", "n": g.n, "m": g.m, "iters": iters, "calls": calls,
+           "call_us_median": round(med * 1e3, 1), "call_us_min": round(min(times) * 1e3, 1),
+           "us_per_iteration": round(med * 1e3 / iters, 2),
+           "gteps_per_iteration": round(g.m * iters / (med / 1e3) / 1e9, 3),
+           "rank_kernel_us": round(st["rank_kernel_ms"] / st["rank_kernel_launches"] * 1e3, 2),
+           "device_us_per_call": round(st["total_ms"] * 1e3, 1),
+           "launches_per_iteration": 3, "host_copies_per_iteration": 1}
+    log(f"small graph: {res}")
     return res
 
 
@@ -304,19 +380,20 @@ def main():
     dfp_out = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in fracs]
     rec = {j: {"static_ms": [], "dfp_ms": [], "static_iters": [], "dfp_iters": [],
                "rank_ms": [], "rank_launches": []} for j in range(len(fracs))}
-    other = {"ppr_ms": [], "ppr_iters": [], "batched_ms": [], "batched_iters": [],
+    other = {"ppr_ms": [], "ppr_iters": [], "ppr_vec_iters": [], "ppr_rank_ms": [],
+             "ppr_launches": [], "batched_ms": [], "batched_iters": [],
              "fw_ms": [], "fw_iters": [], "adj_ms": [], "adj_iters": []}
 
     def step(s, record):
         j = s % len(fracs)
+        # recorded steps: HIP events around every call and every rank-kernel
+        # launch (the live roofline figures), for every leg alike; no
+        # affected-set counting passes
+        prhip.set_profiling(record, counters=False)
         if "static" in legs:
-            # HIP events around each rank-kernel launch (the live roofline
-            # figure) in the recorded steps only; the other calls run plain
-            prhip.set_profiling(record)
             t0 = time.perf_counter()
             prhip.static(dgs[j], out=static_out[j])
             t1 = time.perf_counter()
-            prhip.set_profiling(False)
             st = prhip.last_stats()
             if record:
                 r = rec[j]
@@ -336,8 +413,12 @@ def main():
             _, its = prhip.ppr(aux["dg"], aux["tele"], out=aux["ppr_out"])
             t1 = time.perf_counter()
             if record:
+                st = prhip.last_stats()
                 other["ppr_ms"].append((t1 - t0) * 1e3)
                 other["ppr_iters"].append(int(its.max()))
+                other["ppr_vec_iters"].append(int(its.sum()))
+                other["ppr_rank_ms"].append(st["rank_kernel_ms"])
+                other["ppr_launches"].append(st["rank_kernel_launches"])
         if "batched" in legs:
             prhip.set_tuning(**aux["btune"])
             t0 = time.perf_counter()
@@ -361,6 +442,7 @@ def main():
                 other["fw_iters"].append(fr.iterations)
                 other["adj_ms"].append((t3 - t2) * 1e3)
                 other["adj_iters"].append(prhip.last_stats()["iterations"])
+        prhip.set_profiling(False)
 
     for s in range(args.warmup):
         step(s, False)
@@ -439,6 +521,26 @@ def main():
                       "m": ga.m, "k": args.ppr_k, "ms": round(pm, 3),
                       "iters": other["ppr_iters"][0],
                       "vector_gteps": round(ga.m * args.ppr_k * other["ppr_iters"][0] / pm / 1e6, 2)}
+        # roofline of k_ppr_rank: a launch over k active vectors moves
+        # 4m + 16kn algorithmic bytes; a vector that met the tolerance is
+        # frozen (its lanes neither read nor write), so over a call the bytes
+        # are launches * 4m + 16n * (sum of the vectors' iteration counts)
+        p_launch = sum(other["ppr_launches"])
+        p_ms = sum(other["ppr_rank_ms"])
+        p_bytes = sum(L * 4 * ga.m + 16 * ga.n * vi
+                      for L, vi in zip(other["ppr_launches"], other["ppr_vec_iters"]))
+        if p_ms > 0 and p_launch > 0:
+            p_ach = p_bytes / (p_ms / 1e3) / 1e9
+            p_traffic = read_traffic(PPR_TRAFFIC_FILE, PPR_SOURCES)
+            p_alg_full = ppr_algorithmic_bytes(ga.n, ga.m, args.ppr_k)
+            out["ppr"]["roofline"] = {
+                "bound": "hbm", "kernel": "k_ppr_rank", "achieved": round(p_ach, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(p_ach / HBM_PEAK_GBS, 4),
+                "traffic": p_traffic,
+                "traffic_over_algorithmic": round(p_traffic / p_alg_full, 2) if p_traffic else None,
+                "avg_launch_us": round(p_ms / p_launch * 1e3, 2),
+                "algorithmic_bytes_per_launch_all_active": p_alg_full,
+                "algorithmic_bytes_per_launch_mean": round(p_bytes / p_launch)}
     if "batched" in legs:
         bm = float(np.mean(other["batched_ms"]))
         out["batched"] = {"graphs": len(aux["bgs"]), "n": sum(g.n for g in aux["bgs"]),
@@ -600,6 +702,9 @@ def main():
         out["accuracy"] = acc
         log(f"accuracy: max DF-P vs Static L-inf {max(a['dfp_vs_static_linf'] for a in acc):.3e}")
 
+    if not args.no_compare and "static" in legs:
+        out["small_graph"] = small_leg(gg, prhip, torch, np)
+
     if args.temporal_batches > 0:
         out["temporal"] = temporal_leg(args, gg, prhip, torch, np)
 
@@ -614,7 +719,7 @@ def main():
         res, sec = oracle.static_csr(n, g0.in_offsets, g0.in_sources, g0.out_offsets, tol=0.0,
                                      max_iter=args.cpu_iters)
         cpu = {"value": round(g0.m * res.iters / sec / 1e9, 5), "unit": "GTEPS", "cores": 1,
-               "kind": "oracle",
+               "kind": "oracle", **cpu_info(),
                "sample": f"{res.iters} Static iterations (Alg. 1) of the sequential FP64 oracle on "
                          f"the scale-{args.scale} graph G^(t-1), iteration loop only "
                          f"({sec:.1f} s)"}

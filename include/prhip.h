@@ -300,7 +300,7 @@ int pr_get_tuning(pr_tuning *t);
  *   converged          1 if the tolerance was met
  *   final_delta        L-infinity change of the last iteration
  *   affected_initial   DF-P: affected vertices after the initial marking
- *                      (only with profiling on, else -1)
+ *                      (only at profiling level 2, else -1)
  *   rank_kernel_ms     with profiling on: summed device time of the fused
  *                      rank-update launches of the performed iterations
  *   rank_kernel_launches  number of those launches
@@ -315,7 +315,7 @@ typedef struct pr_stats {
   int32_t rank_kernel_launches;
   int32_t reserved0;
   double total_ms;
-  int64_t affected_max;      /* DF/DF-P/DT, with profiling: largest affected set */
+  int64_t affected_max;      /* DF/DF-P/DT, profiling level 2: largest affected set */
   int64_t edges_processed;   /* of an iteration, and the in-edges of the affected */
                              /* vertices summed over the iterations (-1: n/a)    */
   double reserved[2];
@@ -323,8 +323,12 @@ typedef struct pr_stats {
 
 int pr_last_stats(pr_stats *out);
 
-/* Turn per-launch HIP event timing on (1) or off (0) for this thread. */
-int pr_set_profiling(int enable);
+/* Profiling of this thread's calls: 0 off; 1 HIP events around the call and
+ * around every rank-update launch (rank_kernel_ms, total_ms); 2 as 1, plus
+ * the affected-set counters of DF/DF-P/DT (affected_initial, affected_max,
+ * edges_processed), which add a counting pass per iteration. PR_EINVAL for
+ * other levels. */
+int pr_set_profiling(int level);
 
 /* Stream for this thread's subsequent calls (a hipStream_t; NULL = default). */
 void pr_set_stream(void *hip_stream);

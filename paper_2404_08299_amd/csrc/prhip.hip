@@ -843,7 +843,8 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
                        g->in_offsets, n, w.ctrl);
     hipLaunchKernelGGL(k_affected_fold, dim3(1), dim3(64), 0, s, w.ctrl);
   };
-  if (t_profiling) {
+  const bool counters = t_profiling >= 2;
+  if (counters) {
     hipLaunchKernelGGL(k_count_flags, dim3(cgrid), dim3(kBlock), 0, s, (const uint8_t *)dV, n,
                        w.ctrl, 0);
     count_affected();
@@ -881,7 +882,7 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
     hipLaunchKernelGGL(k_linf_final, dim3(1), dim3(kFinalBlock), 0, s,
                        (const double *)w.partials, np, w.ctrl, tol, it);
     apply_expand(it, !dt);  // DT: the affected set stays fixed
-    if (t_profiling) count_affected();
+    if (counters) count_affected();
     LAUNCH_TRY();
     return PR_OK;
   };
@@ -892,7 +893,7 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
   HIP_TRY(hipStreamSynchronize(s));
   const Ctrl &last = w.host_ctrl[(launched - 1) % kRing];
   if (last.err) return fail(PR_EBATCH, "batch vertex ID outside [0, n)");
-  if (t_profiling) {
+  if (counters) {
     t_stats.affected_initial = last.aux[0];
     t_stats.affected_max = last.aux[5];
     t_stats.edges_processed = last.aux[6];
@@ -1544,8 +1545,9 @@ int pr_last_stats(pr_stats *out) {
   return PR_OK;
 }
 
-int pr_set_profiling(int enable) {
-  t_profiling = enable ? 1 : 0;
+int pr_set_profiling(int level) {
+  if (level < 0 || level > 2) return fail(PR_EINVAL, "profiling level must be 0, 1 or 2");
+  t_profiling = level;
   return PR_OK;
 }
 

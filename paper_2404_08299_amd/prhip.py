@@ -473,8 +473,11 @@ def set_tuning(**kw) -> None:
     _check(lib.pr_set_tuning(ctypes.byref(t)), lib)
 
 
-def set_profiling(enable: bool) -> None:
-    load_library().pr_set_profiling(1 if enable else 0)
+def set_profiling(enable: bool, counters: bool = True) -> None:
+    """Per-launch event timing on or off; with `counters` (the default) also
+    the affected-set counters of the dynamic variants (profiling level 2)."""
+    lib = load_library()
+    _check(lib.pr_set_profiling((2 if counters else 1) if enable else 0), lib)
 
 
 def release() -> None:

@@ -35,6 +35,16 @@ def test_algorithmic_bytes():
     assert b.algorithmic_bytes(n, m) == 4 * m + 28 * n
 
 
+def test_ppr_algorithmic_bytes_and_cpu_info():
+    b = load_bench()
+    # in_sources 4m, k contributions gathered once 8kn, k new ranks 8kn
+    assert b.ppr_algorithmic_bytes(10, 100, 3) == 4 * 100 + 16 * 3 * 10
+    n, m = 1 << 20, 17_134_700
+    assert abs(b.ppr_algorithmic_bytes(n, m, 64) - 1.142e9) < 1e6
+    info = b.cpu_info()
+    assert info["nproc"] == os.cpu_count() and info["affinity_cpus"] >= 1
+
+
 def test_traffic_only_for_the_current_kernel_source(tmp_path, monkeypatch):
     b = load_bench()
     good = tmp_path / "traffic.txt"
