@@ -158,6 +158,7 @@ def temporal_leg(args, gg, prhip, torch, np):
         f"({time.time() - t:.1f} s)")
     prev = prhip.static(prhip.DeviceGraph.from_host(g0)).ranks
     prev_df = prev.clone()
+    abl_cases = []
     outs = [torch.empty(g0.n, dtype=torch.float64, device="cuda") for _ in range(2)]
     outs_df = [torch.empty(g0.n, dtype=torch.float64, device="cuda") for _ in range(2)]
     st_out = torch.empty(g0.n, dtype=torch.float64, device="cuda")
@@ -167,6 +168,8 @@ def temporal_leg(args, gg, prhip, torch, np):
         # DF-P and DF (no pruning, the paper's accuracy fallback) each chained
         # over the stream, and Static on G^t
         out, out_df = outs[k & 1], outs_df[k & 1]
+        if k < args.ablation_batches:
+            abl_cases.append((dg, db, prev.clone()))
         _, ms_d = timed(lambda: prhip.dfp(dg, db, prev, out=out))
         dfp_it.append(prhip.last_stats()["iterations"])
         _, ms_f = timed(lambda: prhip.dfp(dg, db, prev_df, mode="df", out=out_df))
@@ -203,6 +206,60 @@ def temporal_leg(args, gg, prhip, torch, np):
     log(f"temporal: DF-P {res['dfp_ms_geomean']} ms, DF {res['df_ms_geomean']} ms vs Static "
         f"{res['static_ms_geomean']} ms per batch (geomean), max L-inf DF-P "
         f"{res['max_dfp_linf']:.2e}, DF {res['max_df_linf']:.2e}")
+    if abl_cases and not args.no_compare:
+        # Sec. 4.4's partitioning study on the first batches of the stream,
+        # each from the DF-P chain's R^{t-1}
+        abl = partition_ablation(prhip, torch, abl_cases)
+        res["partition_ablation"] = {
+            "batches": len(abl_cases),
+            **{k: {"ms_geomean": round(gm(v["ms"]), 3), "iters_mean":
+                   round(float(np.mean(v["iters"])), 2), "linf_vs_default": v["linf_vs_default"]}
+               for k, v in abl.items()}}
+        log(f"temporal partition ablation: "
+            + ", ".join(f"{k} {v['ms_geomean']} ms" for k, v in res["partition_ablation"].items()
+                        if isinstance(v, dict)))
+    return res
+
+
+# The partitioning study of Sec. 4.4 for DF and DF-P: no partitioning (one
+# lane per vertex in the rank update and in expandAffected), partitioning of
+# G' only (the rank update's in-degree classes; marking one lane per vertex),
+# and partitioning of both G' and G (the default: in-degree classes for the
+# rank update, out-degree classes for the marking).
+PARTITION_STRATEGIES = {
+    "none": dict(lane_max_degree=1 << 30, wave_max_degree=1 << 30,
+                 expand_lane_max_degree=1 << 30, xcd_split_degree=0),
+    "in_only": dict(wave_max_degree=1 << 30, expand_lane_max_degree=1 << 30),
+    "in_and_out": {},
+}
+
+
+def partition_ablation(prhip, torch, cases):
+    """DF-P and DF under each partitioning strategy on `cases`, a list of
+    (G^t, batch, R^{t-1}): one untimed and one timed call each. Returns per
+    strategy and mode the times (ms), the iteration counts and the largest
+    L-infinity distance to the default strategy's ranks (the strategies
+    change only the order of floating-point summation)."""
+    n = cases[0][0].n
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    ref = {}
+    res = {}
+    for name in ("in_and_out", "in_only", "none"):
+        prhip.set_tuning()
+        prhip.set_tuning(**PARTITION_STRATEGIES[name])
+        for mode in ("dfp", "df"):
+            ms, its, dev = [], [], 0.0
+            for i, (dg, db, prev) in enumerate(cases):
+                prhip.dfp(dg, db, prev, mode=mode, out=out)
+                _, t = timed(lambda: prhip.dfp(dg, db, prev, mode=mode, out=out))
+                ms.append(round(t, 3))
+                its.append(prhip.last_stats()["iterations"])
+                if name == "in_and_out":
+                    ref[(mode, i)] = out.clone()
+                else:
+                    dev = max(dev, float((out - ref[(mode, i)]).abs().max()))
+            res[f"{mode}_{name}"] = {"ms": ms, "iters": its, "linf_vs_default": dev}
+    prhip.set_tuning()
     return res
 
 
@@ -263,6 +320,8 @@ def main():
                     help="batches per decade (seeds 1..N) in the untimed DF-P vs Static sweep; "
                          "0 skips it")
     ap.add_argument("--temporal-batches", type=int, default=100)
+    ap.add_argument("--ablation-batches", type=int, default=10,
+                    help="temporal batches in the partitioning study (Sec. 4.4)")
     ap.add_argument("--temporal-n", type=int, default=2_000_000)
     ap.add_argument("--temporal-events", type=int, default=40_000_000)
     ap.add_argument("--order", default="scrambled", choices=["scrambled", "natural", "degree"],
@@ -598,6 +657,20 @@ def main():
             modes.append(item)
         out["dynamic_methods"] = modes
         log(f"methods: {modes}")
+
+    if not args.no_compare and "dfp" in legs:
+        # Sec. 4.4's partitioning study for DF and DF-P, one batch per decade
+        # (the timed steps' batches, from R^{t-1} = Static on G^{t-1})
+        abl = partition_ablation(prhip, torch, [(dgs[j], dbs[j], prev) for j in range(len(fracs))])
+        out["partition_ablation"] = {
+            "strategies": PARTITION_STRATEGIES,
+            "decades": [{"fraction": f, **{k: {"ms": v["ms"][j], "iters": v["iters"][j]}
+                                           for k, v in abl.items()}}
+                        for j, f in enumerate(fracs)],
+            "linf_vs_default": {k: v["linf_vs_default"] for k, v in abl.items()}}
+        log("partition ablation (ms per call, DF-P: none / G' / G' and G): "
+            + ", ".join(f"{f:g}: {abl['dfp_none']['ms'][j]} / {abl['dfp_in_only']['ms'][j]} / "
+                        f"{abl['dfp_in_and_out']['ms'][j]}" for j, f in enumerate(fracs)))
 
     if not args.no_compare and "dfp" in legs and args.sweep_batches > 0:
         # DF-P against Static over several random batches per decade (batch

@@ -139,20 +139,31 @@ int pr_ppr(const pr_csr *csr, const double *teleport, int k, double alpha, doubl
            int max_iter, double *ranks_out, int32_t *iters_out);
 
 /*
- * Static PageRank (as pr_static) on num_graphs independent graphs in one
+ * Static or personalised PageRank (Alg. 1 with Eq. 1's teleport term, or the
+ * personalised term of pr_ppr) on num_graphs independent graphs in one
  * batched computation: the graphs are joined into one block-diagonal union,
- * every graph keeps its own teleport term (1 - alpha)/n_g and its own
- * L-infinity stop (a converged graph is no longer updated), and the
- * iterations run as replays of one captured hipGraph. Each graph's result
- * equals pr_static on that graph with the same tuning.
+ * every graph keeps its own teleport term and its own L-infinity stop (a
+ * converged graph is no longer updated), and the iterations run as replays
+ * of one captured hipGraph (several iterations per replay; the instantiated
+ * graph is kept and updated in place by the next call of the same shape).
+ * Many personalised vectors of one graph are run by passing that graph once
+ * per vector. A graph with a uniform teleport gives the same bits as
+ * pr_static on it with the same tuning; one with teleport s_g gives
+ *   R[v] = alpha * sum_{u in in(v)} R[u] / |out(u)| + (1 - alpha) * s_g[v]
+ * from R = 1/n_g (as pr_ppr with k = 1, up to the order of summation).
  *   graphs       [num_graphs] host array of graphs (device pointers inside;
  *                out_targets not read); total vertices and edges < 2^31
  *   num_graphs   1 .. 4096
+ *   teleport     [num_graphs] host array of device pointers, [n_g] each
+ *                (s_g; not normalised by the library), or NULL entries for
+ *                the uniform term (1 - alpha)/n_g; the array itself may be
+ *                NULL (every graph uniform)
  *   ranks_out    [num_graphs] host array of device pointers, [n_g] each
  *   iters_out    [num_graphs] host array for the iteration counts, or NULL
  */
-int pr_static_batched(const pr_csr *graphs, int num_graphs, double alpha, double tol,
-                      int max_iter, double *const *ranks_out, int32_t *iters_out);
+int pr_static_batched(const pr_csr *graphs, int num_graphs, const double *const *teleport,
+                      double alpha, double tol, int max_iter, double *const *ranks_out,
+                      int32_t *iters_out);
 
 /*
  * Weighted forward (PageRank with given transition weights and teleport):

@@ -3,7 +3,8 @@
 // The graphs are concatenated into one union CSR (vertex and edge bases per
 // graph, block-diagonal), so the fixed-grid rank update, its partition and
 // its locality renumbering run once over all of them. Each vertex carries its
-// graph id: the teleport term is (1 - alpha) / n_g of its own graph, its
+// graph id: the teleport term is (1 - alpha) / n_g of its own graph (or
+// (1 - alpha) s_g[v] with the graph's own personalised teleport vector), its
 // |change| goes into its graph's maximum (workgroup tables in LDS, then one
 // row per workgroup), and once graph g meets the tolerance its vertices are
 // no longer updated, so every graph stops exactly where pr_static on it alone
@@ -86,19 +87,26 @@ __global__ __launch_bounds__(kBlock) void k_union_build(
   }
 }
 
-// Output policy of the batched update (see rank_update in kernels.h).
+// Output policy of the batched update (see rank_update in kernels.h). The
+// teleport term of graph g is (1 - alpha)/n_g (C0g[g]) unless tele[g] is set:
+// then it is (1 - alpha) * tele[g][v - vb[g]], personalised PageRank on that
+// graph (the form of pr_ppr and pr_weighted: the product first, then + alpha c).
 struct BatchOut {
   const int *out_off;
   const int *pos;
   const int *gid;
   const double *C0g;
+  const double *const *tele;  // [G] device pointers (null entries: uniform), or null
+  const int *vb;              // [G + 1] first vertex of each graph
   const int *gdone;
   const double *R;
   double *Rn, *Xn;
   double alpha;
   unsigned long long *s_gmax;  // LDS: per-graph maximum |change| (bit patterns)
   __device__ __forceinline__ double finish(int v, double c) const {
-    const double r = C0g[gid[v]] + alpha * c;
+    const int g = gid[v];
+    const double *t = tele ? tele[g] : nullptr;
+    const double r = t ? (1.0 - alpha) * t[v - vb[g]] + alpha * c : C0g[g] + alpha * c;
     st_nt(Rn + v, r);
     Xn[xpos(pos, v)] = r / (double)(ld_nt(out_off + v + 1) - ld_nt(out_off + v));
     return fabs(r - ld_nt(R + v));
@@ -131,12 +139,13 @@ __global__ __launch_bounds__(kBlock) void k_rank_batched(
     const int *__restrict__ hub_start, const int *__restrict__ chunk_hub,
     double *__restrict__ hub_part, int CH, int n, int t1, const int4 *__restrict__ xitems,
     const int *__restrict__ xoff, const int *__restrict__ gid, const double *__restrict__ C0g,
+    const double *const *__restrict__ tele, const int *__restrict__ vb,
     const int *__restrict__ gdone, int G, double alpha, double *__restrict__ gpart,
     const Ctrl *__restrict__ ctrl) {
   if (ctrl->done) return;
   extern __shared__ unsigned long long s_gmax[];
   clear_table(s_gmax, G);
-  const BatchOut out{out_off, pos, gid, C0g, gdone, R, Rn, Xn, alpha, s_gmax};
+  const BatchOut out{out_off, pos, gid, C0g, tele, vb, gdone, R, Rn, Xn, alpha, s_gmax};
   rank_update<false, LG>(in_off, in_src, nullptr, X, hi, counts, hub_start, chunk_hub, hub_part, CH,
                      n, t1, xitems, xoff, out, nullptr);
   flush_table(s_gmax, G, gpart + (size_t)blockIdx.x * G);
@@ -147,12 +156,13 @@ __global__ __launch_bounds__(kBlock) void k_hub_finalize_batched(
     const double *__restrict__ hub_part, const int *__restrict__ out_off,
     const int *__restrict__ pos, const double *__restrict__ R, double *__restrict__ Rn,
     double *__restrict__ Xn, const int *__restrict__ gid, const double *__restrict__ C0g,
+    const double *const *__restrict__ tele, const int *__restrict__ vb,
     const int *__restrict__ gdone, int G, double alpha, double *__restrict__ gpart,
     const Ctrl *__restrict__ ctrl) {
   if (ctrl->done) return;
   extern __shared__ unsigned long long s_gmax[];
   clear_table(s_gmax, G);
-  const BatchOut out{out_off, pos, gid, C0g, gdone, R, Rn, Xn, alpha, s_gmax};
+  const BatchOut out{out_off, pos, gid, C0g, tele, vb, gdone, R, Rn, Xn, alpha, s_gmax};
   hub_finalize(hi, counts, hub_start, hub_part, out, nullptr);
   flush_table(s_gmax, G, gpart + (size_t)blockIdx.x * G);
 }

@@ -97,6 +97,9 @@ struct Workspace {
   double *b_c0 = nullptr, *b_gdelta = nullptr, *b_gpart = nullptr;
   BatchDesc *b_desc = nullptr;
   double **b_outs = nullptr;
+  const double **b_tele = nullptr;  // [G] per-graph teleport vectors (null: uniform)
+  hipGraphExec_t b_exec = nullptr;  // instantiated iteration graph, updated per call
+  long long b_exec_key[4] = {};     // its launch shapes: graphs, grid, item dealing, kernel
   int *b_xrs = nullptr;  // [G][kXcds + 1] die-split ranges per graph
   size_t cap_b_g = 0, cap_b_part = 0;
   hipStream_t cap_stream = nullptr;
@@ -165,8 +168,11 @@ void free_batch(Workspace &w) {
   (void)hipFree(w.u_gid); (void)hipFree(w.b_vbase); (void)hipFree(w.b_ebase);
   (void)hipFree(w.b_gdone); (void)hipFree(w.b_giters); (void)hipFree(w.b_c0);
   (void)hipFree(w.b_gdelta); (void)hipFree(w.b_gpart); (void)hipFree(w.b_desc);
-  (void)hipFree(w.b_outs); (void)hipFree(w.b_xrs);
+  (void)hipFree(w.b_outs); (void)hipFree(w.b_xrs); (void)hipFree(w.b_tele);
   w.b_xrs = nullptr;
+  w.b_tele = nullptr;
+  if (w.b_exec) (void)hipGraphExecDestroy(w.b_exec);
+  w.b_exec = nullptr;
   w.u_in_off = w.u_in_src = w.u_out_off = w.u_gid = nullptr;
   w.b_vbase = w.b_ebase = w.b_gdone = w.b_giters = nullptr;
   w.b_c0 = w.b_gdelta = w.b_gpart = nullptr;
@@ -1112,6 +1118,7 @@ int batch_ws(Workspace &w, size_t N, size_t M, size_t G, size_t part_rows) {
         (e = hipMalloc(&w.b_gpart, pp * sizeof(double))) != hipSuccess ||
         (e = hipMalloc(&w.b_desc, gg * sizeof(BatchDesc))) != hipSuccess ||
         (e = hipMalloc(&w.b_outs, gg * sizeof(double *))) != hipSuccess ||
+        (e = hipMalloc(&w.b_tele, gg * sizeof(double *))) != hipSuccess ||
         (e = hipMalloc(&w.b_xrs, gg * (kXcds + 1) * sizeof(int))) != hipSuccess) {
       (void)hipGetLastError();
       free_batch(w);
@@ -1130,11 +1137,18 @@ int batch_ws(Workspace &w, size_t N, size_t M, size_t G, size_t part_rows) {
   return PR_OK;
 }
 
+// Iterations captured in the hipGraph of a batched call (even: the buffers
+// swap back at its end). Iterations enqueued after every graph converged exit
+// at once on the device, so a replay wastes at most a few microseconds each.
+constexpr int kReplayIters = 4;
+
 // Static PageRank (Alg. 1) on G graphs at once: union CSR, one partition and
-// renumbering, per-graph teleport and convergence; the iterations run as
-// replays of one captured hipGraph holding an even and an odd iteration.
-int run_batched(const pr_csr *graphs, int G, double alpha, double tol, int max_iter,
-                double *const *outs, int32_t *iters_out) {
+// renumbering, per-graph teleport (uniform or a personalised vector) and
+// convergence; the iterations run as replays of one captured hipGraph of
+// kReplayIters iterations, whose instantiation is kept and updated in place
+// by the next call.
+int run_batched(const pr_csr *graphs, int G, const double *const *tele, double alpha, double tol,
+                int max_iter, double *const *outs, int32_t *iters_out) {
   hipStream_t s = t_stream;
   const pr_tuning tn = g_tuning;
   std::vector<int> vbase(G + 1), ebase(G + 1);
@@ -1168,6 +1182,11 @@ int run_batched(const pr_csr *graphs, int G, double alpha, double tol, int max_i
   HIP_TRY(hipMemcpyAsync(w.b_ebase, ebase.data(), (G + 1) * sizeof(int), hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(w.b_c0, c0.data(), G * sizeof(double), hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(w.b_outs, outs, G * sizeof(double *), hipMemcpyHostToDevice, s));
+  bool any_tele = false;
+  for (int g = 0; tele && g < G; ++g) any_tele = any_tele || tele[g] != nullptr;
+  if (any_tele)
+    HIP_TRY(hipMemcpyAsync(w.b_tele, tele, G * sizeof(double *), hipMemcpyHostToDevice, s));
+  const double *const *dtele = any_tele ? (const double *const *)w.b_tele : nullptr;
   hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, s, w.ctrl);
   const int ub = std::min((std::max(n, m) + kBlock - 1) / kBlock, 32 * std::max(1, w.num_cus));
   hipLaunchKernelGGL(k_union_build, dim3(ub), dim3(kBlock), 0, s, (const BatchDesc *)w.b_desc,
@@ -1191,36 +1210,38 @@ int run_batched(const pr_csr *graphs, int G, double alpha, double tol, int max_i
   Locality loc;
   if ((rc = locality(w, n, m, w.u_out_off, w.u_in_src, tn, true, s, &loc))) return rc;
   if ((rc = read_plan(w, xp, s))) return rc;
-  auto rank_fn = item_lg(w, xp, B) ? k_rank_batched<4> : k_rank_batched<0>;
+  const int lg = item_lg(w, xp, B);
+  auto rank_fn = lg ? k_rank_batched<4> : k_rank_batched<0>;
   double *R[2] = {w.T, w.R1};
   double *X[2] = {w.X0, w.X1};
   hipLaunchKernelGGL(k_batched_init, dim3(ub), dim3(kBlock), 0, s, n, G, (const int *)w.u_gid,
                      (const int *)w.b_vbase, (const int *)w.u_out_off, loc.pos, R[0], X[0],
                      w.b_gdone, w.b_giters);
   LAUNCH_TRY();
-  // iteration pair captured on the library stream, after the work above
+  // kReplayIters iterations captured on the library stream, after the work above
   hipStream_t cs = w.cap_stream;
   HIP_TRY(hipEventRecord(w.cap_ev[0], s));
   HIP_TRY(hipStreamWaitEvent(cs, w.cap_ev[0], 0));
   const size_t shm = (size_t)G * sizeof(unsigned long long);
   const int t1 = tn.lane_max_degree, CH = tn.hub_chunk_edges;
   HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-  for (int it = 0; it < 2; ++it) {
+  for (int it = 0; it < kReplayIters; ++it) {
     const int a = it & 1, b = a ^ 1;
     hipLaunchKernelGGL(rank_fn, dim3(B), dim3(kBlock), shm, cs, (const int *)w.u_in_off,
                        loc.src, (const int *)w.u_out_off, loc.pos, (const double *)X[a],
                        (const double *)R[a], R[b], X[b], (const int *)w.hi_in,
                        (const int *)w.counts, (const int *)w.hub_start_in,
                        (const int *)w.chunk_hub_in, w.hub_part, CH, n, t1, xp.items, xp.off,
-                       (const int *)w.u_gid,
-                       (const double *)w.b_c0, (const int *)w.b_gdone, G, alpha, w.b_gpart,
+                       (const int *)w.u_gid, (const double *)w.b_c0, dtele,
+                       (const int *)w.b_vbase, (const int *)w.b_gdone, G, alpha, w.b_gpart,
                        (const Ctrl *)w.ctrl);
     hipLaunchKernelGGL(k_hub_finalize_batched, dim3(F), dim3(kBlock), shm, cs,
                        (const int *)w.hi_in, (const int *)w.counts, (const int *)w.hub_start_in,
                        (const double *)w.hub_part, (const int *)w.u_out_off, loc.pos,
                        (const double *)R[a], R[b], X[b], (const int *)w.u_gid,
-                       (const double *)w.b_c0, (const int *)w.b_gdone, G, alpha,
-                       w.b_gpart + (size_t)B * G, (const Ctrl *)w.ctrl);
+                       (const double *)w.b_c0, dtele, (const int *)w.b_vbase,
+                       (const int *)w.b_gdone, G, alpha, w.b_gpart + (size_t)B * G,
+                       (const Ctrl *)w.ctrl);
     hipLaunchKernelGGL(k_batched_final, dim3(G), dim3(kBlock), 0, cs, (const double *)w.b_gpart,
                        B + F, G, w.b_gdone, w.b_giters, w.b_gdelta, (const Ctrl *)w.ctrl, tol);
     hipLaunchKernelGGL(k_batched_done, dim3(1), dim3(kBlock), 0, cs, (const int *)w.b_gdone, G,
@@ -1229,13 +1250,37 @@ int run_batched(const pr_csr *graphs, int G, double alpha, double tol, int max_i
   hipGraph_t graph = nullptr;
   hipError_t ce = hipStreamEndCapture(cs, &graph);
   if (ce != hipSuccess) return fail(PR_EHIP, std::string("graph capture: ") + hipGetErrorString(ce));
-  hipGraphExec_t exec = nullptr;
-  ce = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  // the previous call's instantiation takes this call's kernel arguments in
+  // place when every launch has the same shape (grids, LDS size and kernels
+  // depend only on the key); otherwise it is rebuilt
+  const long long key[4] = {G, B, lg, tn.lane_max_degree};
+  if (w.b_exec && !std::equal(key, key + 4, w.b_exec_key)) {
+    (void)hipGraphExecDestroy(w.b_exec);
+    w.b_exec = nullptr;
+  }
+  if (w.b_exec) {
+    hipGraphNode_t bad = nullptr;
+    hipGraphExecUpdateResult res = hipGraphExecUpdateError;
+    if (hipGraphExecUpdate(w.b_exec, graph, &bad, &res) != hipSuccess ||
+        res != hipGraphExecUpdateSuccess) {
+      (void)hipGetLastError();
+      (void)hipGraphExecDestroy(w.b_exec);
+      w.b_exec = nullptr;
+    }
+  }
+  if (!w.b_exec) {
+    ce = hipGraphInstantiate(&w.b_exec, graph, nullptr, nullptr, 0);
+    if (ce != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      w.b_exec = nullptr;
+      return fail(PR_EHIP, std::string("graph instantiate: ") + hipGetErrorString(ce));
+    }
+    std::copy(key, key + 4, w.b_exec_key);
+  }
   (void)hipGraphDestroy(graph);
-  if (ce != hipSuccess)
-    return fail(PR_EHIP, std::string("graph instantiate: ") + hipGetErrorString(ce));
+  hipGraphExec_t exec = w.b_exec;
   const int K = std::max(1, std::min(g_tuning.iters_per_sync, kRing - 1));
-  const int replays = (max_iter + 1) / 2;
+  const int replays = (max_iter + kReplayIters - 1) / kReplayIters;
   int r = 0;
   bool done = false;
   int err = PR_OK;
@@ -1259,7 +1304,6 @@ int run_batched(const pr_csr *graphs, int G, double alpha, double tol, int max_i
     }
   }
   (void)hipStreamSynchronize(cs);
-  (void)hipGraphExecDestroy(exec);
   if (err) return err;
   HIP_TRY(hipEventRecord(w.cap_ev[1], cs));
   HIP_TRY(hipStreamWaitEvent(s, w.cap_ev[1], 0));
@@ -1355,8 +1399,9 @@ int pr_ppr(const pr_csr *csr, const double *teleport, int k, double alpha, doubl
   return run_ppr(csr, teleport, k, alpha, tol, max_iter, ranks_out, iters_out);
 }
 
-int pr_static_batched(const pr_csr *graphs, int num_graphs, double alpha, double tol,
-                      int max_iter, double *const *ranks_out, int32_t *iters_out) {
+int pr_static_batched(const pr_csr *graphs, int num_graphs, const double *const *teleport,
+                      double alpha, double tol, int max_iter, double *const *ranks_out,
+                      int32_t *iters_out) {
   reset_stats();
   if (!graphs || !ranks_out) return fail(PR_EINVAL, "graphs and ranks_out are required");
   if (num_graphs <= 0 || num_graphs > kMaxBatchGraphs)
@@ -1368,9 +1413,11 @@ int pr_static_batched(const pr_csr *graphs, int num_graphs, double alpha, double
   }
   if ((rc = check_params(alpha, tol, max_iter))) return rc;
   for (int g = 0; g < num_graphs; ++g)
-    if ((rc = on_device(&graphs[g], {{ranks_out[g], "ranks_out[g]"}}))) return rc;
+    if ((rc = on_device(&graphs[g], {{ranks_out[g], "ranks_out[g]"},
+                                     {teleport ? teleport[g] : nullptr, "teleport[g]"}})))
+      return rc;
   std::lock_guard<std::mutex> lock(g_mu);
-  return run_batched(graphs, num_graphs, alpha, tol, max_iter, ranks_out, iters_out);
+  return run_batched(graphs, num_graphs, teleport, alpha, tol, max_iter, ranks_out, iters_out);
 }
 
 int pr_weighted(const pr_csr *csr, const double *in_weights, const double *teleport,

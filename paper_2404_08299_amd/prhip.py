@@ -93,7 +93,7 @@ def load_library(path: str = SO_PATH):
     lib.pr_dfp_ex.argtypes = [P(PrCsr), P(PrCsr), P(PrEdges), P(PrEdges), vp, d, d, d, d, i, i,
                               vp]
     lib.pr_ppr.argtypes = [P(PrCsr), vp, i, d, d, i, vp, P(ctypes.c_int32)]
-    lib.pr_static_batched.argtypes = [P(PrCsr), i, d, d, i, P(vp), P(ctypes.c_int32)]
+    lib.pr_static_batched.argtypes = [P(PrCsr), i, P(vp), d, d, i, P(vp), P(ctypes.c_int32)]
     lib.pr_weighted.argtypes = [P(PrCsr), vp, vp, d, d, i, vp]
     lib.pr_adjoint.argtypes = [P(PrCsr), vp, vp, vp, d, d, i, vp, vp, vp]
     lib.pr_validate_csr.argtypes = [P(PrCsr)]
@@ -369,8 +369,12 @@ def _ptr(x):
     return None if x is None else x.data_ptr()
 
 
-def static_batched(graphs, alpha=ALPHA, tol=TOL, max_iter=MAX_ITERATIONS, outs=None):
+def static_batched(graphs, alpha=ALPHA, tol=TOL, max_iter=MAX_ITERATIONS, outs=None,
+                   teleports=None):
     """Static PageRank on many graphs in one batched call (pr_static_batched).
+    teleports: None (every graph uniform) or a list with, per graph, None
+    (uniform) or an [n_g] float64 device tensor s_g (personalised PageRank
+    on that graph). A graph may appear several times, once per vector.
     Returns (Result with ranks = list of [n_g] tensors, iterations per graph)."""
     torch = _torch()
     lib = load_library()
@@ -389,9 +393,17 @@ def static_batched(graphs, alpha=ALPHA, tol=TOL, max_iter=MAX_ITERATIONS, outs=N
     for i, (g, o) in enumerate(zip(graphs, outs)):
         _tensor(o, f"outs[{i}]", torch.float64, dev, numel=g.n)
     ptrs = (ctypes.c_void_p * G)(*[o.data_ptr() for o in outs])
+    tptrs = None
+    if teleports is not None:
+        if len(teleports) != G:
+            raise ValueError(f"teleports: expected {G} entries, got {len(teleports)}")
+        for i, (g, t) in enumerate(zip(graphs, teleports)):
+            if t is not None:
+                _tensor(t, f"teleports[{i}]", torch.float64, dev, numel=g.n)
+        tptrs = (ctypes.c_void_p * G)(*[_ptr(t) for t in teleports])
     its = np.zeros(G, np.int32)
     _bind_stream(lib, torch)
-    rc = _check(lib.pr_static_batched(csrs, G, alpha, tol, max_iter, ptrs,
+    rc = _check(lib.pr_static_batched(csrs, G, tptrs, alpha, tol, max_iter, ptrs,
                                       its.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))), lib)
     return _result(rc, outs), its
 

@@ -161,9 +161,9 @@ def test_weighted_adjoint_argument_errors(lib):
 def test_batched_argument_errors(lib):
     csr = (prhip.PrCsr * 2)(prhip.PrCsr(4, 4, 8, 8, 8, None), prhip.PrCsr(0, 4, 8, 8, 8, None))
     outs = (ctypes.c_void_p * 2)(8, 8)
-    assert lib.pr_static_batched(csr, 0, 0.85, 1e-10, 10, outs, None) == prhip.PR_EINVAL
-    assert lib.pr_static_batched(csr, 5000, 0.85, 1e-10, 10, outs, None) == prhip.PR_EINVAL
-    assert lib.pr_static_batched(csr, 2, 0.85, 1e-10, 10, outs, None) == prhip.PR_EINVAL  # n = 0
+    assert lib.pr_static_batched(csr, 0, None, 0.85, 1e-10, 10, outs, None) == prhip.PR_EINVAL
+    assert lib.pr_static_batched(csr, 5000, None, 0.85, 1e-10, 10, outs, None) == prhip.PR_EINVAL
+    assert lib.pr_static_batched(csr, 2, None, 0.85, 1e-10, 10, outs, None) == prhip.PR_EINVAL  # n = 0
 
 
 def test_host_memory_is_refused(lib):

@@ -2,8 +2,9 @@
 (n = 16,777,216, m = 280,209,285), with the default tuning and launch shape
 the benchmark times.
 
-The oracle's whole Static run at this size (about 61 x 2.8e8 edge steps) does
-not fit a test, so Static is checked one step at a time on samples: the GPU
+Static is compared element by element with the oracle's whole run (Alg. 1,
+about 61 x 2.8e8 edge steps, a minute or two on one host core). It is also
+checked one step at a time on samples: the GPU
 iterate R_k (a run stopped after k iterations) fed to the oracle's Eq. 1 for
 a sample of rows (every degree class, the largest hubs, random rows) must give
 the GPU's R_{k+1} on those rows within the rounding bound of a sum of
@@ -89,6 +90,23 @@ def test_static_full_size_sampled_steps(full):
         print(f"step {k - 1} -> {k}: {rows.size} rows, max rel diff {rel.max():.2e}, "
               f"max rel/bound {(rel / bound).max():.3f}", flush=True)
         assert (rel <= bound).all(), rows[np.argmax(rel / bound)]
+
+
+def test_static_full_size_whole_run_vs_oracle(full):
+    """The converged Static vector against the oracle's whole Static run over
+    the same in-CSR (Alg. 1, Eq. 1, tol 1e-10): L-infinity <= 1e-9 and the
+    same iteration count up to one (Delta can land within rounding of tol)."""
+    g, _, res = full
+    print("oracle Static over the scale-24 CSR (one host core) ...", flush=True)
+    o, sec = oracle.static_csr(g.n, g.in_offsets, g.in_sources, g.out_offsets)
+    r = res.ranks.cpu().numpy()
+    err = float(np.abs(r - o.ranks).max())
+    rel = float((np.abs(r - o.ranks) / o.ranks).max())
+    print(f"Static whole run: gpu iters {res.iterations} oracle iters {o.iters} "
+          f"({sec:.1f} s), Linf {err:.2e}, max rel {rel:.2e}", flush=True)
+    assert o.status == oracle.OK
+    assert err <= 1e-9
+    assert abs(res.iterations - o.iters) <= 1
 
 
 def test_static_full_size_invariants(full):

@@ -186,6 +186,59 @@ def test_adjoint_full_size(weighted_case):
     assert abs(fd_s - an_s) <= 1e-6 * abs(an_s)
 
 
+def test_adjoint_full_size_per_edge_fd(weighted_case):
+    """The workload's own gradient check: central differences (h = 1e-6) of
+    the loss on 100 random edges, half of them in-edges of the 1024 target
+    rows (where the gradient is largest) and half drawn from all edges. Each
+    difference perturbs one entry of P on the device and runs both forward
+    solves to the floating-point fixed point (tol 0), so the solves' own
+    stopping error does not swamp a change of the loss of about 1e-18. The
+    difference divides by the perturbation actually applied (P_e + h minus
+    P_e - h in FP64). Bound: |g_adj - g_fd| <= 1e-4 |g_fd| + 1e-6 max|g_adj|."""
+    g, dg, src, dst, P, s, targets = weighted_case
+    Pd, sd = torch.from_numpy(P).cuda(), torch.from_numpy(s).cuda()
+    tol = 1e-15
+    r = prhip.weighted(dg, Pd, sd, tol=tol, max_iter=3000).ranks
+    rh = r.cpu().numpy()
+    gvec = np.zeros(g.n)
+    gvec[targets] = 2 * rh[targets]
+    gw, _, _ = prhip.adjoint(dg, Pd, r, torch.from_numpy(gvec).cuda(), tol=tol, max_iter=3000,
+                             want_lambda=True)
+    gw = gw.cpu().numpy()
+    rng = np.random.default_rng(3)
+    into_targets = np.flatnonzero(np.isin(dst, targets))
+    edges = np.concatenate([rng.choice(into_targets, 50, replace=False),
+                            rng.choice(g.m, 50, replace=False)])
+    tg = torch.from_numpy(targets).cuda()
+    h = 1e-6
+
+    def loss(Pv):
+        rr = quiet(prhip.weighted, dg, Pv, sd, tol=0.0, max_iter=1500).ranks
+        return math.fsum((rr[tg] ** 2).cpu().numpy())
+
+    errs, scale = [], float(np.abs(gw).max())
+    Pw = Pd.clone()
+    for e in edges.tolist():
+        p0 = float(P[e])
+        hi_, lo_ = p0 + h, p0 - h
+        Pw[e] = hi_
+        lp = loss(Pw)
+        Pw[e] = lo_
+        lm = loss(Pw)
+        Pw[e] = p0
+        fd = (lp - lm) / (hi_ - lo_)
+        err = abs(gw[e] - fd)
+        errs.append((err, fd, gw[e]))
+        assert err <= 1e-4 * abs(fd) + 1e-6 * scale, (e, fd, gw[e])
+    a = np.array(errs)
+    rel = a[:, 0] / np.maximum(np.abs(a[:, 1]), 1e-300)
+    print(f"per-edge FD on {len(edges)} edges (h = {h:g}): |g| {np.abs(a[:, 2]).min():.2e} .. "
+          f"{np.abs(a[:, 2]).max():.2e}; relative error median {np.median(rel[:50]):.2e}, "
+          f"max {rel[:50].max():.2e} (target in-edges), median {np.median(rel[50:]):.2e}, "
+          f"max {rel[50:].max():.2e} (random edges); max abs error {a[:, 0].max():.2e}",
+          flush=True)
+
+
 def test_batched_full_size():
     prhip.set_tuning()
     rng = np.random.default_rng(7)
