@@ -646,6 +646,12 @@ def main():
                 _, t_mode = timed(lambda: prhip.dfp(dgs[j], dbs[j], prev, mode=mode, out=tmp))
                 item[f"{mode}_ms"] = round(t_mode, 3)
                 item[f"{mode}_iters"] = prhip.last_stats()["iterations"]
+            # DF-P with the ID-tile sweeps instead of the compacted affected list
+            prhip.set_tuning(frontier_list=0)
+            prhip.dfp(dgs[j], dbs[j], prev, out=tmp)
+            _, t_sw = timed(lambda: prhip.dfp(dgs[j], dbs[j], prev, out=tmp))
+            prhip.set_tuning()
+            item["dfp_sweep_ms"] = round(t_sw, 3)
             # the batch applied on the device (pr_apply_batch: both views of G^t from G^{t-1})
             prhip.apply_batch(dg0, dbs[j])
             _, t_apply = timed(lambda: prhip.apply_batch(dg0, dbs[j]))

@@ -293,15 +293,22 @@ typedef struct pr_tuning {
   int32_t relabel;
   int32_t xcd_split_degree;
   int32_t expand_pull_per_mille;
+  int32_t frontier_list;
 } pr_tuning;
 
-/* Defaults: lane_max_degree 128, wave_max_degree 4096, expand_lane_max_degree
+/* frontier_list       DF/DF-P/DT: 1 = after each marking the affected set is
+ *                     compacted into a list, and the rank update's lane class
+ *                     and the apply/marking step run over that list (tiles
+ *                     of 256 affected vertices); 0 = both sweep ID tiles of
+ *                     every vertex and skip the unaffected ones. The same
+ *                     ranks either way (bit for bit).
+ * Defaults: lane_max_degree 128, wave_max_degree 4096, expand_lane_max_degree
  * 32, iters_per_sync 2, hub_chunk_edges 4096, grid_blocks 0, relabel -1,
- * xcd_split_degree 129, expand_pull_per_mille 20. */
+ * xcd_split_degree 129, expand_pull_per_mille 20, frontier_list 1. */
 
 /* Set (NULL = defaults) or read the process-wide tuning. PR_EINVAL if a
  * field is out of range (degrees < 0, lane > wave, iters_per_sync < 1,
- * xcd_split_degree == 1). */
+ * xcd_split_degree == 1, frontier_list not 0 or 1). */
 int pr_set_tuning(const pr_tuning *t);
 int pr_get_tuning(pr_tuning *t);
 

@@ -37,7 +37,7 @@ DEFAULT_SPACE = {
     "iters_per_sync": [1, 2, 4],
 }
 DFP_SPACE = dict(DEFAULT_SPACE, expand_lane_max_degree=[8, 32, 128],
-                 expand_pull_per_mille=[0, 5, 20, 100])
+                 expand_pull_per_mille=[0, 5, 20, 100], frontier_list=[0, 1])
 
 CACHE_PATH = os.environ.get("PRHIP_TUNING_CACHE",
                             os.path.join(os.path.expanduser("~"), ".cache", "prhip_tuning.json"))

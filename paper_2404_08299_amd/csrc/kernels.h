@@ -73,7 +73,9 @@ enum CountSlot {
   kInChunks = 4,   // chunks of the in-degree split class
   kOutChunks = 5,  // chunks of the out-degree split class
   kDtChanged = 6,  // a closure level of Dynamic Traversal marked a vertex
-  kNumCounts = 8
+  kAffList = 8,    // per iteration parity p: slot 8 + 2p the affected list's size,
+                   // 9 + 2p the rank update's tile queue over it
+  kNumCounts = 12
 };
 
 // Streamed data (CSR arrays, a vertex's own rank, new ranks) is read and
@@ -608,14 +610,23 @@ __device__ __forceinline__ long long item_of(int beg, int gwx, long long s, long
   return beg + ((gwx + (s >> LG) * Wd) << LG) + (s & ((1 << LG) - 1));
 }
 
-template <bool WEIGHTED, int LG, class Out>
+// LIST (DF/DF-P/DT): the lane class runs over alist[0 .. acount[0]), the
+// vertices affected in this iteration (compacted after the previous marking,
+// see k_compact_affected), 256 to a tile, instead of over ID tiles of every
+// vertex; vertices not in the list had their dN flag cleared by the
+// compaction, which is what `inactive` does in the ID-tile sweep. The list's
+// tiles are few and of very uneven cost, so workgroups take them from a
+// queue (acount[1], cleared by the compaction) instead of round robin; every
+// workgroup leaves once the queue passes the last tile.
+template <bool WEIGHTED, int LG, class Out, bool LIST = false>
 __device__ __forceinline__ void rank_update(
     const int *__restrict__ in_off, const int *__restrict__ in_src,
     const double *__restrict__ wt, const double *__restrict__ X, const int *__restrict__ hi,
     const int *__restrict__ counts,
     const int *__restrict__ hub_start, const int *__restrict__ chunk_hub,
     double *__restrict__ hub_part, int CH, int n, int t1, const int4 *__restrict__ xitems,
-    const int *__restrict__ xoff, const Out &out, double *__restrict__ partials) {
+    const int *__restrict__ xoff, const Out &out, double *__restrict__ partials,
+    const int *__restrict__ alist = nullptr, int *acount = nullptr) {
   __shared__ double lds[kWavesPerBlock];
   __shared__ int s_v[kBlock], s_e0[kBlock], s_e1[kBlock], s_c[kBlock];
   __shared__ int s_wcnt[kWavesPerBlock];
@@ -736,9 +747,18 @@ __device__ __forceinline__ void rank_update(
   {
     __shared__ int s_off[kBlock + 1];
     __shared__ double s_val[kLaneStage];
-    const int ntiles = (n + kBlock - 1) / kBlock;
-    for (int t = blockIdx.x; t < ntiles; t += B) {
-      const int v = t * kBlock + tid;
+    __shared__ int s_tile;
+    const int nrows = LIST ? acount[0] : n;
+    const int ntiles = (nrows + kBlock - 1) / kBlock;
+    for (int t = blockIdx.x;; t += B) {
+      if (LIST) {
+        if (tid == 0) s_tile = atomicAdd(acount + 1, 1);
+        __syncthreads();
+        t = s_tile;
+      }
+      if (t >= ntiles) break;
+      const int i = t * kBlock + tid;
+      const int v = LIST ? (i < nrows ? alist[i] : n) : i;
       int e0 = 0, cnt = 0;
       bool act = false;
       if (v < n) {
@@ -813,7 +833,11 @@ __global__ __launch_bounds__(kBlock) void k_rank_static(
                             n, t1, xitems, xoff, out, partials);
 }
 
-template <bool PRUNE, int LG>
+// LIST: the lane class runs over the compacted affected list
+// (alist[0 .. acount[0]), tiles taken from the queue acount[1]), and the
+// count of the other list (*anext) is cleared for the compaction that follows
+// this iteration's marking.
+template <bool PRUNE, int LG, bool LIST>
 __global__ __launch_bounds__(kBlock) void k_rank_dfp(
     const int *__restrict__ in_off, const int *__restrict__ in_src,
     const int *__restrict__ out_off, const double *__restrict__ X, const double *__restrict__ R,
@@ -821,11 +845,14 @@ __global__ __launch_bounds__(kBlock) void k_rank_dfp(
     const int *__restrict__ counts, const int *__restrict__ hub_start,
     const int *__restrict__ chunk_hub, double *__restrict__ hub_part, int CH, int n, int t1,
     const int4 *__restrict__ xitems, const int *__restrict__ xoff, double C0, double alpha,
-    double tau_f, double tau_p, double *__restrict__ partials, const Ctrl *__restrict__ ctrl) {
+    double tau_f, double tau_p, double *__restrict__ partials, const int *__restrict__ alist,
+    int *acount, int *__restrict__ anext, const Ctrl *__restrict__ ctrl) {
   if (ctrl->done) return;
+  if (LIST && blockIdx.x == 0 && threadIdx.x == 0) *anext = 0;
   const DynOut<PRUNE> out{out_off, R, T, dV, dN, cv, C0, alpha, tau_f, tau_p};
-  rank_update<false, LG>(in_off, in_src, nullptr, X, hi, counts, hub_start, chunk_hub, hub_part, CH, n,
-                     t1, xitems, xoff, out, partials);
+  rank_update<false, LG, DynOut<PRUNE>, LIST>(in_off, in_src, nullptr, X, hi, counts, hub_start,
+                                              chunk_hub, hub_part, CH, n, t1, xitems, xoff, out,
+                                              partials, alist, acount);
 }
 
 // Split-class vertices: add the chunk partials in chunk order and finish.
@@ -903,12 +930,16 @@ __global__ __launch_bounds__(kFinalBlock) void k_linf_final(const double *__rest
 // ------------------------------------------------------------ DF / DF-P
 // R = R^{t-1} (Alg. 2), its contributions X (gather-side numbering), and
 // cleared flags.
+// acount (may be null): the affected-list count, cleared for the first
+// compaction.
 __global__ __launch_bounds__(kBlock) void k_dfp_init(int n, const int *__restrict__ out_off,
                                                      const int *__restrict__ pos,
                                                      const double *prev, double *R,
                                                      double *__restrict__ X, uint8_t *dV,
-                                                     uint8_t *dN, uint8_t *cv) {
+                                                     uint8_t *dN, uint8_t *cv,
+                                                     int *__restrict__ acount) {
   const int v = blockIdx.x * kBlock + threadIdx.x;
+  if (acount && v == 0) *acount = 0;
   if (v < n) {
     const double r = prev[v];
     if (prev != R) R[v] = r;
@@ -949,6 +980,68 @@ __device__ __forceinline__ void mark(uint8_t *dV, int v) {
   if (!dV[v]) dV[v] = 1;
 }
 
+// The affected set after a marking, compacted: every v with dV[v] is
+// appended to list (*count slots reserved with one atomic per workgroup and
+// round, so the list order varies run to run; the results do not, since each
+// vertex is summed by its own lane in row order whatever tile it lands in).
+// A vertex that is not affected has its dN flag cleared: the clearing of
+// delta_N at the start of the next iteration (Alg. 2), which the rank update
+// then skips for the vertices it does not visit. A workgroup round covers
+// kCompactRun vertices, 16 per thread, read as one 16-byte load of each flag
+// array (the flag arrays are 256-byte aligned and padded to a multiple of 256).
+// It also clears `queue`, the tile queue the next rank update takes its list
+// tiles from.
+constexpr int kCompactPer = 16;
+constexpr int kCompactRun = kBlock * kCompactPer;
+__global__ __launch_bounds__(kBlock) void k_compact_affected(const uint8_t *__restrict__ dV,
+                                                             uint8_t *__restrict__ dN, int n,
+                                                             int *__restrict__ list,
+                                                             int *__restrict__ count,
+                                                             int *__restrict__ queue,
+                                                             const Ctrl *__restrict__ ctrl) {
+  if (ctrl->done) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *queue = 0;  // tile queue of the next rank update
+  __shared__ int s_base;
+  const int tid = threadIdx.x;
+  for (long long r0 = (long long)blockIdx.x * kCompactRun; r0 < n;
+       r0 += (long long)gridDim.x * kCompactRun) {
+    const int v0 = (int)r0 + tid * kCompactPer;
+    uint4 fv = make_uint4(0, 0, 0, 0), fn = make_uint4(0, 0, 0, 0);
+    if (v0 < n) {
+      fv = *(const uint4 *)(dV + v0);
+      fn = *(const uint4 *)(dN + v0);
+    }
+    const uint32_t wv[4] = {fv.x, fv.y, fv.z, fv.w};
+    uint32_t wn[4] = {fn.x, fn.y, fn.z, fn.w};
+    uint32_t keep = 0;  // bit j: vertex v0 + j is affected
+    bool clear = false;
+#pragma unroll
+    for (int j = 0; j < kCompactPer; ++j) {
+      const uint32_t sh = 8 * (j & 3);
+      const bool in = v0 + j < n;
+      const bool a = in && ((wv[j >> 2] >> sh) & 0xFF) != 0;
+      if (a) keep |= 1u << j;
+      if (in && !a && ((wn[j >> 2] >> sh) & 0xFF) != 0) {
+        wn[j >> 2] &= ~(0xFFu << sh);
+        clear = true;
+      }
+    }
+    if (clear) *(uint4 *)(dN + v0) = make_uint4(wn[0], wn[1], wn[2], wn[3]);
+    const int c = __popc(keep);
+    int total;
+    const int off = block_exclusive_scan<kBlock>(c, &total);
+    if (tid == 0) s_base = total ? atomicAdd(count, total) : 0;
+    __syncthreads();
+    int at = s_base + off;
+    while (keep) {
+      const int j = __ffs(keep) - 1;
+      keep &= keep - 1;
+      list[at++] = v0 + j;
+    }
+    __syncthreads();
+  }
+}
+
 // After the convergence check of iteration `it`: copy the new ranks of the
 // vertices updated in it, with their contributions (the swap of Alg. 2;
 // vertices not updated keep their rank), then, unless it converged, expandAffected (Alg. 5): every u
@@ -963,6 +1056,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_expand(
     const int *__restrict__ hi_out, const int *__restrict__ counts,
     const int *__restrict__ hub_start, const int *__restrict__ chunk_hub, int CH, int n,
     int t_exp, const int *__restrict__ rt, long long pull_thresh, int do_mark,
+    const int *__restrict__ alist, const int *__restrict__ acount,
     const Ctrl *__restrict__ ctrl, int it) {
   const int done = ctrl->done;
   if (done && ctrl->iters < it + 1) return;  // converged before this iteration
@@ -1073,10 +1167,14 @@ __global__ __launch_bounds__(kBlock) void k_apply_expand(
       }
     }
   }
-  // lane class and the apply step over ID tiles
-  const int ntiles = (n + kBlock - 1) / kBlock;
+  // lane class and the apply step over ID tiles, or over the iteration's
+  // affected list (alist): every vertex updated in this iteration (cv set)
+  // and every vertex with dN set is in it
+  const int nrows = alist ? *acount : n;
+  const int ntiles = (nrows + kBlock - 1) / kBlock;
   for (int t = blockIdx.x; t < ntiles; t += B) {
-    const int v = t * kBlock + tid;
+    const int i = t * kBlock + tid;
+    const int v = alist ? (i < nrows ? alist[i] : n) : i;
     if (v < n) {
       if (cv[v]) {
         const double r = T[v];

@@ -53,6 +53,7 @@ pr_tuning default_tuning() {
   t.relabel = -1;
   t.xcd_split_degree = 129;
   t.expand_pull_per_mille = 20;
+  t.frontier_list = 1;
   return t;
 }
 pr_tuning g_tuning = default_tuning();
@@ -71,6 +72,7 @@ struct Workspace {
   double *hub_part = nullptr;                             // [cap_chunks]
   double *w_out = nullptr;     // [m] edge weights in out-CSR order (adjoint)
   size_t cap_w_out = 0;
+  int *alist = nullptr;        // [2][n] affected lists of DF/DF-P/DT (by iteration parity)
   int *newid = nullptr;        // [n] gather-side numbering
   int *src_p = nullptr;        // [m] in-CSR sources in that numbering
   int *tile_counts = nullptr;  // [kGroups][ntiles]
@@ -141,8 +143,8 @@ void free_arrays(Workspace &w) {
   (void)hipFree(w.hub_start_in); (void)hipFree(w.hub_start_out);
   (void)hipFree(w.chunk_hub_in); (void)hipFree(w.chunk_hub_out); (void)hipFree(w.hub_part);
   (void)hipFree(w.tile_counts); (void)hipFree(w.partials);
-  (void)hipFree(w.newid); (void)hipFree(w.src_p);
-  w.newid = w.src_p = nullptr;
+  (void)hipFree(w.newid); (void)hipFree(w.src_p); (void)hipFree(w.alist);
+  w.newid = w.src_p = w.alist = nullptr;
   w.R1 = w.X0 = w.X1 = w.T = nullptr;
   w.flags = nullptr;
   w.hi_in = w.hi_out = w.hub_start_in = w.hub_start_out = nullptr;
@@ -312,6 +314,7 @@ int get_ws(size_t n, size_t m, int CH, int B, Workspace **out) {
         (e = hipMalloc(&w.hub_part, nc * sizeof(double))) != hipSuccess ||
         (e = hipMalloc(&w.tile_counts, (size_t)kGroups * nt * sizeof(int) + 64)) != hipSuccess ||
         (e = hipMalloc(&w.newid, nn * sizeof(int))) != hipSuccess ||
+        (e = hipMalloc(&w.alist, 2 * nn * sizeof(int))) != hipSuccess ||
         (e = hipMalloc(&w.src_p, mm * sizeof(int))) != hipSuccess ||
         (e = hipMalloc(&w.partials, np * sizeof(double))) != hipSuccess) {
       (void)hipGetLastError();
@@ -746,8 +749,13 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
   int rc = get_ws((size_t)n, (size_t)g->m, tn.hub_chunk_edges, tn.grid_blocks, &wp);
   if (rc) return rc;
   Workspace &w = *wp;
-  const int B = prune ? grid_blocks(w, tn, k_rank_dfp<true, 4>)
-                      : grid_blocks(w, tn, k_rank_dfp<false, 4>);
+  const int B = prune ? grid_blocks(w, tn, k_rank_dfp<true, 4, true>)
+                      : grid_blocks(w, tn, k_rank_dfp<false, 4, true>);
+  // affected lists (one per iteration parity) and their sizes
+  const bool use_list = tn.frontier_list != 0;
+  int *alist[2] = {w.alist, w.alist + (size_t)n};
+  // per parity: {list size, tile queue of the rank update}
+  int *acnt[2] = {w.counts + kAffList, w.counts + kAffList + 2};
   const int np = B + kHubFinalizeBlocks;
   CallTimer timer(w, s);
   const size_t fs = flag_stride((size_t)n);  // each flag array 256-byte aligned
@@ -770,8 +778,10 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
   if (rc) return rc;
   if ((rc = read_plan(w, xp, s))) return rc;
   const int lg = item_lg(w, xp, B);
-  auto rank_p = lg ? k_rank_dfp<true, 4> : k_rank_dfp<true, 0>;
-  auto rank_d = lg ? k_rank_dfp<false, 4> : k_rank_dfp<false, 0>;
+  auto rank_p = lg ? (use_list ? k_rank_dfp<true, 4, true> : k_rank_dfp<true, 4, false>)
+                   : (use_list ? k_rank_dfp<true, 0, true> : k_rank_dfp<true, 0, false>);
+  auto rank_d = lg ? (use_list ? k_rank_dfp<false, 4, true> : k_rank_dfp<false, 4, false>)
+                   : (use_list ? k_rank_dfp<false, 0, true> : k_rank_dfp<false, 0, false>);
   Locality loc;
   if ((rc = locality(w, n, g->m, g->out_offsets, g->in_sources, tn, true, s, &loc,
                      xs ? w.xrs : nullptr, &xp, g->in_offsets,
@@ -779,7 +789,7 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
     return rc;
   double *X = w.X0;
   hipLaunchKernelGGL(k_dfp_init, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n,
-                     g->out_offsets, loc.pos, prev, R, X, dV, dN, cv);
+                     g->out_offsets, loc.pos, prev, R, X, dV, dN, cv, acnt[0]);
   LAUNCH_TRY();
   rc = partition(w, g->out_offsets, n, g->m, t_exp, tn.wave_max_degree, CH, w.hi_out, kOutWave,
                  kOutChunks, w.hub_start_out, w.chunk_hub_out, s);
@@ -795,7 +805,20 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
   const long long pull_thresh =
       tn.expand_pull_per_mille > 0 ? (long long)n * tn.expand_pull_per_mille / 1000 : -1;
   const int fgrid = std::max(1, std::min((n / 32 + kBlock) / kBlock, 4 * std::max(1, w.num_cus)));
+  // compaction of the affected set after the marking of iteration it, for
+  // iteration it + 1 (list by parity of it + 1)
+  const int cgrid_list =
+      std::max(1, std::min((n + kCompactRun - 1) / kCompactRun, 8 * std::max(1, w.num_cus)));
+  auto compact = [&](int it) {
+    const int q = (it + 1) & 1;
+    hipLaunchKernelGGL(k_compact_affected, dim3(cgrid_list), dim3(kBlock), 0, s,
+                       (const uint8_t *)dV, dN, n, alist[q], acnt[q], acnt[q] + 1,
+                       (const Ctrl *)w.ctrl);
+  };
   auto apply_expand = [&](int it, bool mark) {
+    // the initial expansion (it = -1) marks from the batch sources, which
+    // are in no list: it sweeps ID tiles
+    const bool lst = use_list && it >= 0;
     if (mark && pull_thresh >= 0) {
       hipLaunchKernelGGL(k_frontier, dim3(fgrid), dim3(kBlock), 0, s, (const uint8_t *)dN, n,
                          w.fbits, w.ctrl, it);
@@ -811,7 +834,9 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
                        (const int *)w.hi_out, (const int *)w.counts,
                        (const int *)w.hub_start_out, (const int *)w.chunk_hub_out, CH, n, t_exp,
                        xs ? (const int *)w.xrt : nullptr, pull_thresh, mark ? 1 : 0,
-                       (const Ctrl *)w.ctrl, it);
+                       lst ? (const int *)alist[it & 1] : nullptr,
+                       lst ? (const int *)acnt[it & 1] : nullptr, (const Ctrl *)w.ctrl, it);
+    if (use_list) compact(it);
   };
   // initial expandAffected (Alg. 2, after initialAffected)
   apply_expand(-1, true);
@@ -840,6 +865,10 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
     }
     HIP_TRY(hipMemsetAsync(cv, 0, (size_t)n, s));
     HIP_TRY(hipMemsetAsync(dN, 0, (size_t)n, s));
+    if (use_list) {  // the list of the closed set
+      HIP_TRY(hipMemsetAsync(acnt[0], 0, sizeof(int), s));
+      compact(-1);
+    }
   }
   // profiling: the affected set each iteration is about to update (counted
   // after the marking that produced it, outside the rank-kernel timing)
@@ -865,6 +894,7 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
                          (const int *)w.hi_in, (const int *)w.counts,
                          (const int *)w.hub_start_in, (const int *)w.chunk_hub_in, w.hub_part, CH,
                          n, t1, xp.items, xp.off, C0, alpha, tau_f, tau_p, w.partials,
+                         (const int *)alist[it & 1], acnt[it & 1], acnt[(it + 1) & 1],
                          (const Ctrl *)w.ctrl);
       if (prof) HIP_TRY(hipEventRecord(after, s));
       hipLaunchKernelGGL(k_hub_finalize_dfp<true>, dim3(kHubFinalizeBlocks), dim3(kBlock), 0, s,
@@ -878,6 +908,7 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
                          (const int *)w.hi_in, (const int *)w.counts,
                          (const int *)w.hub_start_in, (const int *)w.chunk_hub_in, w.hub_part, CH,
                          n, t1, xp.items, xp.off, C0, alpha, tau_f, tau_p, w.partials,
+                         (const int *)alist[it & 1], acnt[it & 1], acnt[(it + 1) & 1],
                          (const Ctrl *)w.ctrl);
       if (prof) HIP_TRY(hipEventRecord(after, s));
       hipLaunchKernelGGL(k_hub_finalize_dfp<false>, dim3(kHubFinalizeBlocks), dim3(kBlock), 0, s,
@@ -1572,7 +1603,7 @@ int pr_set_tuning(const pr_tuning *t) {
       t->iters_per_sync < 1 || t->iters_per_sync >= kRing || t->hub_chunk_edges < 0 ||
       t->grid_blocks < 0 || t->grid_blocks > (1 << 20) || t->relabel < -1 || t->relabel > 1 ||
       t->xcd_split_degree < 0 || t->xcd_split_degree == 1 || t->expand_pull_per_mille < 0 ||
-      t->expand_pull_per_mille > 1000)
+      t->expand_pull_per_mille > 1000 || t->frontier_list < 0 || t->frontier_list > 1)
     return fail(PR_EINVAL, "tuning field out of range");
   g_tuning = *t;
   if (g_tuning.hub_chunk_edges == 0) g_tuning.hub_chunk_edges = 4096;

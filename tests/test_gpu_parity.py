@@ -268,6 +268,51 @@ def test_dfp_pull_equals_push(mode, tuning):
         assert it == outs[0][1] and np.array_equal(r, outs[0][0])
 
 
+@pytest.mark.parametrize("mode", ["dfp", "df", "dt"])
+@pytest.mark.parametrize("tuning", [dict(), ALL_LANE, ALL_CLASSES, dict(grid_blocks=3),
+                                    XSPLIT[2]])
+def test_affected_list_equals_sweep(mode, tuning):
+    """The rank update and the apply/marking step over the compacted affected
+    list (frontier_list = 1, the default) give the same bits and iteration
+    counts as the sweeps over ID tiles of every vertex (frontier_list = 0)."""
+    g0, g1, b, prev = dynamic_case(scale=13, frac=1e-3, seed=8)
+    outs = []
+    for fl in (0, 1):
+        prhip.set_tuning()
+        prhip.set_tuning(**tuning, frontier_list=fl)
+        r, res = gpu_dfp(g1, b, prev, mode=mode)
+        outs.append((r, res.iterations))
+    assert outs[0][1] == outs[1][1] and np.array_equal(outs[0][0], outs[1][0])
+
+
+@pytest.mark.parametrize("n", [1, 2, 17, 255, 4095, 4097, 70001])
+def test_affected_list_ragged(n):
+    """Vertex counts around the compaction's 16-vertex words and 4096-vertex
+    rounds, every vertex in the lane class: bit-identical to the oracle."""
+    prhip.set_tuning(**ALL_LANE)
+    scale = max(1, int(np.ceil(np.log2(max(n, 2)))))
+    g0 = gg.rmat_graph(scale, 6, seed=n, n=n)
+    b = gg.random_batch(g0, max(1, gg.batch_size_for(g0, 1e-2)), seed=n + 1) if n > 2 \
+        else gg.Batch.empty()
+    g1 = gg.apply_batch(g0, b)
+    prev = oracle.static(g0.n, *g0.edges()).ranks
+    r, res = gpu_dfp(g1, b, prev, tol=0.0 if n <= 2 else 1e-10)
+    o = oracle.dfp(g1.n, *g1.edges(), b, prev, tol=0.0 if n <= 2 else 1e-10)
+    assert res.iterations == o.iters and np.array_equal(r, o.ranks)
+
+
+def test_affected_list_prune_above_frontier_tol():
+    """With prune_tol > frontier_tol a vertex can be pruned while its dN flag
+    is set; the compaction must clear that flag (Alg. 2 clears delta_N at the
+    start of every iteration), so the trajectory stays the oracle's."""
+    prhip.set_tuning(**ALL_LANE)
+    g0, g1, b, prev = dynamic_case(scale=11, frac=1e-2, seed=9)
+    for tau_f, tau_p in ((1e-7, 1e-5), (1e-8, 1e-4)):
+        r, res = gpu_dfp(g1, b, prev, frontier_tol=tau_f, prune_tol=tau_p)
+        o = oracle.dfp(g1.n, *g1.edges(), b, prev, tau_f=tau_f, tau_p=tau_p)
+        assert res.iterations == o.iters and np.array_equal(r, o.ranks)
+
+
 @pytest.mark.parametrize("frac", [1e-4, 1e-2])
 @pytest.mark.parametrize("tuning", [dict(), dict(xcd_split_degree=0), ALL_CLASSES,
                                     dict(grid_blocks=5, relabel=1), XSPLIT[0]])
