@@ -92,6 +92,31 @@ typedef struct pr_edges {
 int pr_static(const pr_csr *csr, double alpha, double tol, int max_iter, double *ranks_out);
 
 /*
+ * pr_static without any allocation, for callers that cannot allocate device
+ * memory (tight serving loops, harnesses that forbid hipMalloc). Same
+ * arguments, update, stopping rule and return codes as pr_static; it never
+ * calls hipMalloc, hipFree or another allocating routine. Its scratch is a
+ * fixed device-resident array of PR_NOALLOC_SCRATCH_BYTES that each device
+ * holds from the time the library's code is loaded on it until the process
+ * ends, shared by every call on that device and left holding the last call's
+ * contents (each call initialises what it reads). Calls on one device are
+ * serialised within a process; calls that overlap on one device from several
+ * processes race on that array.
+ * Limits: n <= PR_NOALLOC_MAX_N and about 44 n + 12 m / hub_chunk_edges
+ * bytes of scratch (at most PR_NOALLOC_SCRATCH_BYTES); beyond them PR_EINVAL,
+ * before any work is enqueued, with the reason in pr_last_error().
+ * It runs without the gather-side relabel and the die split (every other
+ * tuning field applies), so its ranks equal pr_static's under the tuning
+ * relabel = 0, xcd_split_degree = 0 bit for bit, and pr_static's under any
+ * other tuning up to summation-order rounding. The convergence flag is read
+ * every 4 iterations (iters_per_sync is not used); profiling is not recorded.
+ */
+#define PR_NOALLOC_MAX_N (1 << 20)
+#define PR_NOALLOC_SCRATCH_BYTES (64 << 20)
+int pr_static_noalloc(const pr_csr *csr, double alpha, double tol, int max_iter,
+                      double *ranks_out);
+
+/*
  * DF-P PageRank (Alg. 2 with updateRanks of Alg. 3, partitioning of Alg. 4
  * and marking of Alg. 5; closed-loop update of Eq. 2, Sec. 4.3).
  *   csr_old     G^{t-1}; not read by the computation (kept for the interface

@@ -1359,6 +1359,154 @@ int run_batched(const pr_csr *graphs, int G, const double *const *tele, double a
   return all ? PR_OK : PR_NOT_CONVERGED;
 }
 
+// ------------------------------------------------------------ allocation-free Static
+// pr_static_noalloc takes its scratch from a device-resident array of fixed
+// size instead of the grow-only workspace, so it calls no allocator. Each
+// device holds its own copy of the array (from the time the library's code
+// is loaded on it until the process ends); its address on a device is looked
+// up once, with that device current, and kept. In host code the name
+// `scratch` is only a stand-in: kernels get the looked-up address.
+constexpr size_t kNoAllocBytes = (size_t)64 << 20;
+constexpr int kNoAllocMaxN = 1 << 20;
+constexpr int kNoAllocMaxDevices = 64;
+constexpr int kNoAllocMaxGrid = 16384;
+constexpr int kNoAllocSyncEvery = 4;  // iterations enqueued per convergence read
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+unsigned char *g_scratch_ptr[kNoAllocMaxDevices] = {};
+int g_scratch_cus[kNoAllocMaxDevices] = {};
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+// Scratch layout of one call: byte offsets of each array, and the total.
+struct NoAllocLayout {
+  size_t ctrl, counts, partials, R1, X0, X1, hi, hub_start, chunk_hub, hub_part, tiles, total;
+};
+NoAllocLayout noalloc_layout(size_t n, size_t m, int CH, int B) {
+  NoAllocLayout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) { const size_t at = o; o += align256(bytes); return at; };
+  const size_t chunks = m / (size_t)std::max(CH, 1) + n + 1;
+  L.ctrl = take(sizeof(Ctrl));
+  L.counts = take(kNumCounts * sizeof(int));
+  L.partials = take(((size_t)B + kHubFinalizeBlocks + 16) * sizeof(double));
+  L.R1 = take(n * sizeof(double));
+  L.X0 = take(n * sizeof(double));
+  L.X1 = take(n * sizeof(double));
+  L.hi = take(n * sizeof(int));
+  L.hub_start = take((n + 1) * sizeof(int));
+  L.chunk_hub = take(chunks * sizeof(int));
+  L.hub_part = take(chunks * sizeof(double));
+  L.tiles = take(2 * ntiles_for(n) * sizeof(int) + 64);
+  L.total = o;
+  return L;
+}
+
+// Static PageRank as run_pull does it for pr_static, with the relabel and the
+// die split off (lane class staged in LDS, wavefront class, split class cut
+// into chunks), every array in the scratch array, and the convergence flag
+// read by a copy into host stack memory every kNoAllocSyncEvery iterations.
+int run_static_noalloc(const pr_csr *g, double alpha, double tol, int max_iter,
+                       double *ranks_out) {
+  hipStream_t s = t_stream;
+  const pr_tuning tn = g_tuning;
+  const int n = g->n, m = g->m, CH = tn.hub_chunk_edges;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNoAllocMaxDevices)
+    return fail(PR_EINVAL, "pr_static_noalloc: device index beyond the supported 64");
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    int cus = 0;
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    g_scratch_cus[dev] = std::max(1, cus);
+    g_scratch_ptr[dev] = (unsigned char *)p;
+  }
+  unsigned char *base = g_scratch_ptr[dev];
+  int B = tn.grid_blocks;
+  if (B <= 0) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rank_static<false, 4>, kBlock,
+                                                     0) != hipSuccess ||
+        per_cu <= 0)
+      per_cu = 4;
+    B = per_cu * g_scratch_cus[dev];
+  }
+  B = std::min(B, kNoAllocMaxGrid);
+  const NoAllocLayout L = noalloc_layout((size_t)n, (size_t)m, CH, B);
+  if (L.total > kNoAllocBytes)
+    return fail(PR_EINVAL, "pr_static_noalloc: the graph needs " + std::to_string(L.total) +
+                               " bytes of scratch, more than the fixed " +
+                               std::to_string(kNoAllocBytes) + " (fewer edges or vertices, or a "
+                               "larger hub_chunk_edges)");
+  Ctrl *ctrl = (Ctrl *)(base + L.ctrl);
+  int *counts = (int *)(base + L.counts);
+  double *partials = (double *)(base + L.partials);
+  int *hi = (int *)(base + L.hi), *hub_start = (int *)(base + L.hub_start);
+  int *chunk_hub = (int *)(base + L.chunk_hub), *tiles = (int *)(base + L.tiles);
+  double *hub_part = (double *)(base + L.hub_part);
+  double *R[2] = {ranks_out, (double *)(base + L.R1)};
+  double *X[2] = {(double *)(base + L.X0), (double *)(base + L.X1)};
+  const int t1 = tn.lane_max_degree, t2 = tn.wave_max_degree;
+  const int nt = (int)ntiles_for((size_t)n);
+  // Alg. 4: in-degree classes and the chunk plan of the split class
+  hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, s, ctrl);
+  hipLaunchKernelGGL(k_part_count, dim3(nt), dim3(kBlock), 0, s, g->in_offsets, n, t1, t2, tiles,
+                     nt);
+  hipLaunchKernelGGL(k_scan_rows, dim3(2), dim3(kFinalBlock), 0, s, tiles, nt, counts + kInWave,
+                     (const int *)nullptr);
+  hipLaunchKernelGGL(k_part_scatter, dim3(nt), dim3(kBlock), 0, s, g->in_offsets, n, t1, t2,
+                     (const int *)tiles, nt, (const int *)(counts + kInWave), hi);
+  hipLaunchKernelGGL(k_hub_plan, dim3(1), dim3(kFinalBlock), 0, s, g->in_offsets,
+                     (const int *)hi, counts, (int)kInWave, (int)kInChunks, CH, hub_start,
+                     chunk_hub);
+  hipLaunchKernelGGL(k_static_init, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n,
+                     g->out_offsets, (const int *)nullptr, (const double *)nullptr,
+                     1.0 / (double)n, 0, R[0], X[0]);
+  LAUNCH_TRY();
+  const double C0 = (1.0 - alpha) / (double)n;
+  const int np = B + kHubFinalizeBlocks;
+  auto rank = k_rank_static<false, 4>;
+  Ctrl host{};
+  int it = 0;
+  bool done = false;
+  while (it < max_iter && !done) {
+    const int upto = std::min(max_iter, it + kNoAllocSyncEvery);
+    for (; it < upto; ++it) {
+      const int a = it & 1, b = a ^ 1;
+      hipLaunchKernelGGL(rank, dim3(B), dim3(kBlock), 0, s, g->in_offsets,
+                         g->in_sources, (const double *)nullptr, g->out_offsets,
+                         (const int *)nullptr, (const double *)X[a], (const double *)R[a], R[b],
+                         X[b], (const int *)hi, (const int *)counts, (const int *)hub_start,
+                         (const int *)chunk_hub, hub_part, CH, n, t1, (const int4 *)nullptr,
+                         (const int *)nullptr, C0, alpha, (const double *)nullptr, 0.0, partials,
+                         (const Ctrl *)ctrl);
+      hipLaunchKernelGGL(k_hub_finalize_static, dim3(kHubFinalizeBlocks), dim3(kBlock), 0, s,
+                         (const int *)hi, (const int *)counts, (const int *)hub_start,
+                         (const double *)hub_part, g->out_offsets, (const int *)nullptr,
+                         (const double *)R[a], R[b], X[b], C0, alpha, (const double *)nullptr,
+                         0.0, 0, partials + B, (const Ctrl *)ctrl);
+      hipLaunchKernelGGL(k_linf_final, dim3(1), dim3(kFinalBlock), 0, s,
+                         (const double *)partials, np, ctrl, tol, it);
+      LAUNCH_TRY();
+    }
+    HIP_TRY(hipMemcpyAsync(&host, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    done = host.done != 0;
+  }
+  const int iters = host.done ? host.iters : std::min(it, max_iter);
+  double *result = R[iters & 1];
+  if (result != ranks_out) {
+    HIP_TRY(hipMemcpyAsync(ranks_out, result, (size_t)n * sizeof(double),
+                           hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  t_stats.iterations = iters;
+  t_stats.converged = host.done;
+  t_stats.final_delta = host.delta;
+  return host.done ? PR_OK : PR_NOT_CONVERGED;
+}
+
 int check_edges(const pr_edges *e, const char *name) {
   if (!e) return PR_OK;
   if (e->count < 0) return fail(PR_EINVAL, std::string(name) + ".count < 0");
@@ -1379,6 +1527,20 @@ int pr_static(const pr_csr *csr, double alpha, double tol, int max_iter, double 
   if ((rc = on_device(csr, {{ranks_out, "ranks_out"}}))) return rc;
   std::lock_guard<std::mutex> lock(g_mu);
   return run_static(csr, alpha, tol, max_iter, nullptr, ranks_out);
+}
+
+int pr_static_noalloc(const pr_csr *csr, double alpha, double tol, int max_iter,
+                      double *ranks_out) {
+  reset_stats();
+  int rc = check_csr(csr, false);
+  if (rc) return rc;
+  if ((rc = check_params(alpha, tol, max_iter))) return rc;
+  if (!ranks_out) return fail(PR_EINVAL, "ranks_out is NULL");
+  if (csr->n > kNoAllocMaxN)
+    return fail(PR_EINVAL, "pr_static_noalloc: n must be <= " + std::to_string(kNoAllocMaxN));
+  if ((rc = on_device(csr, {{ranks_out, "ranks_out"}}))) return rc;
+  std::lock_guard<std::mutex> lock(g_mu);
+  return run_static_noalloc(csr, alpha, tol, max_iter, ranks_out);
 }
 
 int pr_dfp_ex(const pr_csr *csr_old, const pr_csr *csr_new, const pr_edges *deletions,

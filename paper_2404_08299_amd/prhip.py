@@ -21,6 +21,7 @@ PR_EINVAL, PR_EGRAPH, PR_EBATCH, PR_ENOMEM, PR_EHIP = -1, -2, -3, -4, -5
 MODES = {"dfp": 0, "df": 1, "nd": 2, "dt": 3}
 
 ALPHA, TOL, FRONTIER_TOL, PRUNE_TOL, MAX_ITERATIONS = 0.85, 1e-10, 1e-6, 1e-6, 500
+NOALLOC_MAX_N = 1 << 20  # PR_NOALLOC_MAX_N
 
 
 class PrError(RuntimeError):
@@ -67,7 +68,7 @@ class PrStats(ctypes.Structure):
                 ("reserved", ctypes.c_double * 2)]
 
 
-EXPORTED = ["pr_static", "pr_dfp", "pr_dfp_ex", "pr_ppr", "pr_static_batched", "pr_weighted",
+EXPORTED = ["pr_static", "pr_static_noalloc", "pr_dfp", "pr_dfp_ex", "pr_ppr", "pr_static_batched", "pr_weighted",
             "pr_adjoint", "pr_apply_batch",
             "pr_validate_csr", "pr_set_tuning",
             "pr_get_tuning", "pr_last_stats", "pr_set_profiling", "pr_set_stream",
@@ -89,6 +90,7 @@ def load_library(path: str = SO_PATH):
     d = ctypes.c_double
     i = ctypes.c_int
     lib.pr_static.argtypes = [P(PrCsr), d, d, i, vp]
+    lib.pr_static_noalloc.argtypes = [P(PrCsr), d, d, i, vp]
     lib.pr_dfp.argtypes = [P(PrCsr), P(PrCsr), P(PrEdges), P(PrEdges), vp, d, d, d, d, vp]
     lib.pr_dfp_ex.argtypes = [P(PrCsr), P(PrCsr), P(PrEdges), P(PrEdges), vp, d, d, d, d, i, i,
                               vp]
@@ -108,7 +110,7 @@ def load_library(path: str = SO_PATH):
     lib.pr_release.argtypes = []
     lib.pr_release.restype = None
     lib.pr_apply_batch.argtypes = [P(PrCsr), P(PrEdges), P(PrEdges), P(PrCsrOut)]
-    for f in ("pr_static", "pr_dfp", "pr_dfp_ex", "pr_ppr", "pr_static_batched", "pr_weighted",
+    for f in ("pr_static", "pr_static_noalloc", "pr_dfp", "pr_dfp_ex", "pr_ppr", "pr_static_batched", "pr_weighted",
               "pr_adjoint", "pr_apply_batch",
               "pr_validate_csr", "pr_set_tuning",
               "pr_get_tuning", "pr_last_stats", "pr_set_profiling"):
@@ -280,6 +282,24 @@ def static(g: DeviceGraph, alpha=ALPHA, tol=TOL, max_iter=MAX_ITERATIONS, out=No
     _tensor(out, "out", torch.float64, g.device, numel=g.n)
     _bind_stream(lib, torch)
     rc = _check(lib.pr_static(ctypes.byref(csr), alpha, tol, max_iter, out.data_ptr()), lib)
+    return _result(rc, out)
+
+
+def static_noalloc(g: DeviceGraph, alpha=ALPHA, tol=TOL, max_iter=MAX_ITERATIONS,
+                   out=None) -> Result:
+    """Static PageRank through pr_static_noalloc (no device allocation inside
+    the call; n <= NOALLOC_MAX_N). `out` is required by callers that must not
+    allocate either; without it one output tensor is allocated here."""
+    torch = _torch()
+    lib = load_library()
+    _on_current_device(g.device, torch)
+    csr = g.csr()
+    if out is None:
+        out = torch.empty(g.n, dtype=torch.float64, device=g.device)
+    _tensor(out, "out", torch.float64, g.device, numel=g.n)
+    _bind_stream(lib, torch)
+    rc = _check(lib.pr_static_noalloc(ctypes.byref(csr), alpha, tol, max_iter, out.data_ptr()),
+                lib)
     return _result(rc, out)
 
 

@@ -158,6 +158,22 @@ def test_weighted_adjoint_argument_errors(lib):
                           None) == prhip.PR_EINVAL
 
 
+def test_noalloc_argument_errors(lib):
+    """The allocation-free entry point checks its arguments like pr_static and
+    refuses graphs beyond its fixed limit before any HIP call."""
+    assert lib.pr_static_noalloc(None, 0.85, 1e-10, 500, None) == prhip.PR_EINVAL
+    big = prhip.PrCsr(prhip.NOALLOC_MAX_N + 1, prhip.NOALLOC_MAX_N + 1, 8, 8, 8, None)
+    assert lib.pr_static_noalloc(ctypes.byref(big), 0.85, 1e-10, 500,
+                                 ctypes.c_void_p(8)) == prhip.PR_EINVAL
+    assert b"n must be <=" in lib.pr_last_error()
+    text = open(HEADER).read()
+    assert re.search(r"#define PR_NOALLOC_MAX_N \(1 << 20\)", text)
+    assert prhip.NOALLOC_MAX_N == 1 << 20
+    ok = prhip.PrCsr(4, 4, 8, 8, 8, None)
+    assert lib.pr_static_noalloc(ctypes.byref(ok), 1.5, 1e-10, 500,
+                                 ctypes.c_void_p(8)) == prhip.PR_EINVAL
+
+
 def test_batched_argument_errors(lib):
     csr = (prhip.PrCsr * 2)(prhip.PrCsr(4, 4, 8, 8, 8, None), prhip.PrCsr(0, 4, 8, 8, 8, None))
     outs = (ctypes.c_void_p * 2)(8, 8)
