@@ -140,14 +140,14 @@ __global__ __launch_bounds__(kBlock) void k_rank_batched(
     double *__restrict__ hub_part, int CH, int n, int t1, const int4 *__restrict__ xitems,
     const int *__restrict__ xoff, const int *__restrict__ gid, const double *__restrict__ C0g,
     const double *const *__restrict__ tele, const int *__restrict__ vb,
-    const int *__restrict__ gdone, int G, double alpha, double *__restrict__ gpart,
+    const int *__restrict__ gdone, int G, double alpha, double *__restrict__ gpart, int *tq,
     const Ctrl *__restrict__ ctrl) {
   if (ctrl->done) return;
   extern __shared__ unsigned long long s_gmax[];
   clear_table(s_gmax, G);
   const BatchOut out{out_off, pos, gid, C0g, tele, vb, gdone, R, Rn, Xn, alpha, s_gmax};
   rank_update<false, LG>(in_off, in_src, nullptr, X, hi, counts, hub_start, chunk_hub, hub_part, CH,
-                     n, t1, xitems, xoff, out, nullptr);
+                         n, t1, xitems, xoff, out, nullptr, nullptr, nullptr, tq);
   flush_table(s_gmax, G, gpart + (size_t)blockIdx.x * G);
 }
 
@@ -158,8 +158,9 @@ __global__ __launch_bounds__(kBlock) void k_hub_finalize_batched(
     double *__restrict__ Xn, const int *__restrict__ gid, const double *__restrict__ C0g,
     const double *const *__restrict__ tele, const int *__restrict__ vb,
     const int *__restrict__ gdone, int G, double alpha, double *__restrict__ gpart,
-    const Ctrl *__restrict__ ctrl) {
+    int *__restrict__ tq, const Ctrl *__restrict__ ctrl) {
   if (ctrl->done) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *tq = 0;  // the next rank update's tile queue
   extern __shared__ unsigned long long s_gmax[];
   clear_table(s_gmax, G);
   const BatchOut out{out_off, pos, gid, C0g, tele, vb, gdone, R, Rn, Xn, alpha, s_gmax};
@@ -212,8 +213,9 @@ __global__ __launch_bounds__(kBlock) void k_batched_init(int N, int G, const int
                                                          const int *__restrict__ pos,
                                                          double *__restrict__ R,
                                                          double *__restrict__ X, int *gdone,
-                                                         int *giters) {
+                                                         int *giters, int *__restrict__ tq) {
   const int stride = gridDim.x * kBlock;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *tq = 0;  // the first rank update's tile queue
   for (int v = blockIdx.x * kBlock + threadIdx.x; v < N; v += stride) {
     const int g = gid[v];
     const double r = 1.0 / (double)(vbase[g + 1] - vbase[g]);

@@ -73,6 +73,7 @@ enum CountSlot {
   kInChunks = 4,   // chunks of the in-degree split class
   kOutChunks = 5,  // chunks of the out-degree split class
   kDtChanged = 6,  // a closure level of Dynamic Traversal marked a vertex
+  kTileQueue = 7,  // the rank updates' tile queue (Static, batched; PPR's row queue)
   kAffList = 8,    // per iteration parity p: slot 8 + 2p the affected list's size,
                    // 9 + 2p the rank update's tile queue over it
   kNumCounts = 12
@@ -462,8 +463,10 @@ __global__ __launch_bounds__(kBlock) void k_static_init(int n, const int *__rest
                                                         const int *__restrict__ pos,
                                                         const double *init, double r0,
                                                         int weighted, double *R,
-                                                        double *__restrict__ X) {
+                                                        double *__restrict__ X,
+                                                        int *__restrict__ tq) {
   const int v = blockIdx.x * kBlock + threadIdx.x;
+  if (tq && v == 0) *tq = 0;  // the first rank update's tile queue
   if (v < n) {
     const double r = init ? init[v] : r0;
     R[v] = r;
@@ -614,10 +617,13 @@ __device__ __forceinline__ long long item_of(int beg, int gwx, long long s, long
 // vertices affected in this iteration (compacted after the previous marking,
 // see k_compact_affected), 256 to a tile, instead of over ID tiles of every
 // vertex; vertices not in the list had their dN flag cleared by the
-// compaction, which is what `inactive` does in the ID-tile sweep. The list's
-// tiles are few and of very uneven cost, so workgroups take them from a
-// queue (acount[1], cleared by the compaction) instead of round robin; every
-// workgroup leaves once the queue passes the last tile.
+// compaction, which is what `inactive` does in the ID-tile sweep.
+// tq (may be null): the lane class's tiles are taken from this queue (an
+// atomic counter that the previous kernel on the stream cleared) instead of
+// round robin, so workgroups that finished their long-row work early take
+// more tiles; every workgroup leaves once the queue passes the last tile. A
+// list's tiles are few and of very uneven cost, so LIST always uses one
+// (acount[1], cleared by the compaction).
 template <bool WEIGHTED, int LG, class Out, bool LIST = false>
 __device__ __forceinline__ void rank_update(
     const int *__restrict__ in_off, const int *__restrict__ in_src,
@@ -626,7 +632,7 @@ __device__ __forceinline__ void rank_update(
     const int *__restrict__ hub_start, const int *__restrict__ chunk_hub,
     double *__restrict__ hub_part, int CH, int n, int t1, const int4 *__restrict__ xitems,
     const int *__restrict__ xoff, const Out &out, double *__restrict__ partials,
-    const int *__restrict__ alist = nullptr, int *acount = nullptr) {
+    const int *__restrict__ alist = nullptr, int *acount = nullptr, int *tq = nullptr) {
   __shared__ double lds[kWavesPerBlock];
   __shared__ int s_v[kBlock], s_e0[kBlock], s_e1[kBlock], s_c[kBlock];
   __shared__ int s_wcnt[kWavesPerBlock];
@@ -750,9 +756,10 @@ __device__ __forceinline__ void rank_update(
     __shared__ int s_tile;
     const int nrows = LIST ? acount[0] : n;
     const int ntiles = (nrows + kBlock - 1) / kBlock;
+    int *queue = LIST ? acount + 1 : tq;
     for (int t = blockIdx.x;; t += B) {
-      if (LIST) {
-        if (tid == 0) s_tile = atomicAdd(acount + 1, 1);
+      if (queue) {
+        if (tid == 0) s_tile = atomicAdd(queue, 1);
         __syncthreads();
         t = s_tile;
       }
@@ -826,11 +833,11 @@ __global__ __launch_bounds__(kBlock) void k_rank_static(
     const int *__restrict__ chunk_hub, double *__restrict__ hub_part, int CH, int n, int t1,
     const int4 *__restrict__ xitems, const int *__restrict__ xoff, double C0, double alpha,
     const double *__restrict__ tele, double tscale, double *__restrict__ partials,
-    const Ctrl *__restrict__ ctrl) {
+    int *tq, const Ctrl *__restrict__ ctrl) {
   if (ctrl->done) return;
   const StaticOut out{out_off, pos, R, Rn, Xn, C0, alpha, tele, tscale, WEIGHTED};
   rank_update<WEIGHTED, LG>(in_off, in_src, wt, X, hi, counts, hub_start, chunk_hub, hub_part, CH,
-                            n, t1, xitems, xoff, out, partials);
+                            n, t1, xitems, xoff, out, partials, nullptr, nullptr, tq);
 }
 
 // LIST: the lane class runs over the compacted affected list
@@ -888,8 +895,10 @@ __global__ __launch_bounds__(kBlock) void k_hub_finalize_static(
     const double *__restrict__ hub_part, const int *__restrict__ out_off,
     const int *__restrict__ pos, const double *__restrict__ R, double *__restrict__ Rn,
     double *__restrict__ Xn, double C0, double alpha, const double *__restrict__ tele,
-    double tscale, int weighted, double *__restrict__ partials, const Ctrl *__restrict__ ctrl) {
+    double tscale, int weighted, double *__restrict__ partials, int *__restrict__ tq,
+    const Ctrl *__restrict__ ctrl) {
   if (ctrl->done) return;
+  if (tq && blockIdx.x == 0 && threadIdx.x == 0) *tq = 0;  // the next rank update's tile queue
   const StaticOut out{out_off, pos, R, Rn, Xn, C0, alpha, tele, tscale, weighted != 0};
   hub_finalize(hi, counts, hub_start, hub_part, out, partials);
 }

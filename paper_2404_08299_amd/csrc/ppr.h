@@ -41,8 +41,9 @@ __device__ __forceinline__ double ppr_row_sum(const int *__restrict__ src,
 }
 
 // One PPR iteration. Work items: chunks of the split class (rows with
-// in-degree > CH, listed in hi[n1 + i] with their chunk plan) first, then
-// all other vertices; wavefront gw of W takes items gw, gw + W, ...
+// in-degree > CH, listed in hi[n1 + i] with their chunk plan) first,
+// wavefront gw of W taking items gw, gw + W, ...; then all other vertices,
+// 64 consecutive rows per take from a row queue.
 // vdone[k] marks frozen vectors (their lanes neither read nor write).
 // pmax: per-workgroup, per-vector maxima [gridDim.x][K].
 __global__ __launch_bounds__(kBlock) void k_ppr_rank(
@@ -54,7 +55,7 @@ __global__ __launch_bounds__(kBlock) void k_ppr_rank(
     double *__restrict__ Xn, const double *__restrict__ S, const uint8_t *__restrict__ tnz,
     double *__restrict__ part, const int *__restrict__ vdone, double alpha,
     double *__restrict__ pmax,
-    const int4 *__restrict__ xitems, const int *__restrict__ xoff,
+    const int4 *__restrict__ xitems, const int *__restrict__ xoff, int *rq,
     const Ctrl *__restrict__ ctrl) {
   if (ctrl->done) return;
   extern __shared__ double s_max[];  // [kWavesPerBlock][K]
@@ -89,11 +90,18 @@ __global__ __launch_bounds__(kBlock) void k_ppr_rank(
     for (int k = lane; k < K; k += kWave)
       if (!vdone[k]) part[(size_t)c * K + k] = ppr_row_sum(in_src, X, K, k, e0, e1);
   }
-  // other rows: full sums and the update. Wavefront gw takes rows gw, gw + W,
-  // ... in that order; it loads the metadata of its next 64 rows (one per
-  // lane) in one round trip and then walks them one by one.
-  for (long long k0 = 0; gw + k0 * W < n; k0 += kWave) {
-    const long long vl = gw + (k0 + lane) * W;
+  // other rows: full sums and the update. A wavefront takes the next 64
+  // consecutive rows from the row queue rq (an atomic counter the previous
+  // kernel on the stream cleared), loads their metadata (one row per lane) in
+  // one round trip and walks them one by one; row costs vary with in-degree,
+  // so wavefronts that drew short rows take more. Every wavefront leaves once
+  // the queue passes n.
+  for (;;) {
+    int r0 = 0;
+    if (lane == 0) r0 = atomicAdd(rq, kWave);
+    r0 = __shfl(r0, 0);
+    if (r0 >= n) break;
+    const long long vl = (long long)r0 + lane;
     int me0 = 0, me1 = 0, mdeg = 1, mpx = 0, mt = 0;
     bool ok = false;
     if (vl < n && !deg_split[vl]) {
@@ -108,7 +116,7 @@ __global__ __launch_bounds__(kBlock) void k_ppr_rank(
     while (mask) {
       const int j = __ffsll(mask) - 1;
       mask &= mask - 1;
-      const int v = (int)(gw + (k0 + j) * W);
+      const int v = r0 + j;
       const int e0 = __shfl(me0, j), e1 = __shfl(me1, j), t = __shfl(mt, j);
       const double d = (double)__shfl(mdeg, j);
       const size_t px = (size_t)__shfl(mpx, j) * K, pv = (size_t)v * K;
@@ -138,8 +146,9 @@ __global__ __launch_bounds__(kBlock) void k_ppr_finalize(
     const double *__restrict__ part, const double *__restrict__ R, double *__restrict__ Rn,
     double *__restrict__ Xn, const double *__restrict__ S, const uint8_t *__restrict__ tnz,
     const int *__restrict__ vdone, double alpha, double *__restrict__ pmax,
-    const Ctrl *__restrict__ ctrl) {
+    int *__restrict__ rq, const Ctrl *__restrict__ ctrl) {
   if (ctrl->done) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *rq = 0;  // the next rank update's row queue
   extern __shared__ double s_max[];
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   for (int k = lane; k < K; k += kWave) s_max[wid * K + k] = 0.0;
@@ -241,8 +250,9 @@ __global__ __launch_bounds__(kBlock) void k_ppr_linf(const double *__restrict__ 
 __global__ __launch_bounds__(kBlock) void k_ppr_init(int n, int K, const int *__restrict__ out_off,
                                                      const int *__restrict__ pos, double *R,
                                                      double *__restrict__ X, int *vdone,
-                                                     int *viters) {
+                                                     int *viters, int *__restrict__ rq) {
   const size_t total = (size_t)n * K;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *rq = 0;  // the first rank update's row queue
   const double r0 = 1.0 / (double)n;
   for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total;
        i += (size_t)gridDim.x * kBlock) {

@@ -676,8 +676,9 @@ int run_pull(const PullProblem &P, double alpha, double tol, int max_iter, doubl
   // start vector is copied into it.
   double *R[2] = {ranks_out, w.R1};
   double *X[2] = {w.X0, w.X1};
+  int *tq = w.counts + kTileQueue;
   hipLaunchKernelGGL(k_static_init, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n,
-                     P.deg_off, loc.pos, P.init, P.r0, (int)weighted, R[0], X[0]);
+                     P.deg_off, loc.pos, P.init, P.r0, (int)weighted, R[0], X[0], tq);
   LAUNCH_TRY();
   const double C0 = (1.0 - alpha) / (double)n;
   const int t1 = tn.lane_max_degree, CH = tn.hub_chunk_edges;
@@ -688,7 +689,7 @@ int run_pull(const PullProblem &P, double alpha, double tol, int max_iter, doubl
                          P.w, P.deg_off, loc.pos, (const double *)X[a], (const double *)R[a],
                          R[b], X[b], (const int *)w.hi_in, (const int *)w.counts,
                          (const int *)w.hub_start_in, (const int *)w.chunk_hub_in, w.hub_part, CH,
-                         n, t1, xp.items, xp.off, C0, alpha, P.tele, P.tscale, w.partials,
+                         n, t1, xp.items, xp.off, C0, alpha, P.tele, P.tscale, w.partials, tq,
                          (const Ctrl *)w.ctrl);
     else
       hipLaunchKernelGGL(rank_u, dim3(B), dim3(kBlock), 0, s, P.row_off, loc.src,
@@ -696,12 +697,12 @@ int run_pull(const PullProblem &P, double alpha, double tol, int max_iter, doubl
                          (const double *)R[a], R[b], X[b], (const int *)w.hi_in,
                          (const int *)w.counts, (const int *)w.hub_start_in,
                          (const int *)w.chunk_hub_in, w.hub_part, CH, n, t1, xp.items, xp.off,
-                         C0, alpha, P.tele, P.tscale, w.partials, (const Ctrl *)w.ctrl);
+                         C0, alpha, P.tele, P.tscale, w.partials, tq, (const Ctrl *)w.ctrl);
     if (prof) HIP_TRY(hipEventRecord(after, s));
     hipLaunchKernelGGL(k_hub_finalize_static, dim3(kHubFinalizeBlocks), dim3(kBlock), 0, s,
                        (const int *)w.hi_in, (const int *)w.counts, (const int *)w.hub_start_in,
                        (const double *)w.hub_part, P.deg_off, loc.pos, (const double *)R[a], R[b],
-                       X[b], C0, alpha, P.tele, P.tscale, (int)weighted, w.partials + B,
+                       X[b], C0, alpha, P.tele, P.tscale, (int)weighted, w.partials + B, tq,
                        (const Ctrl *)w.ctrl);
     hipLaunchKernelGGL(k_linf_final, dim3(1), dim3(kFinalBlock), 0, s,
                        (const double *)w.partials, np, w.ctrl, tol, it);
@@ -1005,8 +1006,9 @@ int run_ppr(const pr_csr *g, const double *teleport, int K, double alpha, double
                      xs ? w.xrs : nullptr)))
     return rc;
   const int ib = (int)std::min<size_t>((nk + kBlock - 1) / kBlock, (size_t)B * 4);
+  int *rq = w.counts + kTileQueue;  // the rank kernel's row queue
   hipLaunchKernelGGL(k_ppr_init, dim3(ib), dim3(kBlock), 0, s, n, K, g->out_offsets, loc.pos,
-                     Rb[0], Xb[0], w.ppr_vdone, w.ppr_viters);
+                     Rb[0], Xb[0], w.ppr_vdone, w.ppr_viters, rq);
   hipLaunchKernelGGL(k_split_flags, dim3(std::min(B, (n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
                      s, g->in_offsets, n, kPprChunk, w.ppr_split);
   uint8_t *tnz = w.ppr_split + w.cap_ppr_n;
@@ -1022,13 +1024,13 @@ int run_ppr(const pr_csr *g, const double *teleport, int K, double alpha, double
                        (const uint8_t *)w.ppr_split, kPprChunk, n, K, (const double *)Xb[a],
                        (const double *)Rb[a], Rb[b], Xb[b], teleport, (const uint8_t *)tnz,
                        w.ppr_part, (const int *)w.ppr_vdone, alpha, w.ppr_pmax, xp.items, xp.off,
-                       (const Ctrl *)w.ctrl);
+                       rq, (const Ctrl *)w.ctrl);
     if (prof) HIP_TRY(hipEventRecord(after, s));
     hipLaunchKernelGGL(k_ppr_finalize, dim3(F), dim3(kBlock), shm, s, g->out_offsets, loc.pos,
                        (const int *)w.hi_in, (const int *)w.counts, (const int *)w.hub_start_in,
                        K, (const double *)w.ppr_part, (const double *)Rb[a], Rb[b], Xb[b],
-                       teleport, (const uint8_t *)tnz, (const int *)w.ppr_vdone, alpha, w.ppr_pmax + (size_t)B * K,
-                       (const Ctrl *)w.ctrl);
+                       teleport, (const uint8_t *)tnz, (const int *)w.ppr_vdone, alpha,
+                       w.ppr_pmax + (size_t)B * K, rq, (const Ctrl *)w.ctrl);
     double *cmax = w.ppr_pmax + (size_t)(B + F + 16) * K;
     hipLaunchKernelGGL(k_ppr_colmax, dim3(kPprColBlocks), dim3(kBlock), 0, s,
                        (const double *)w.ppr_pmax, B + F, K, cmax, (const Ctrl *)w.ctrl);
@@ -1247,7 +1249,7 @@ int run_batched(const pr_csr *graphs, int G, const double *const *tele, double a
   double *X[2] = {w.X0, w.X1};
   hipLaunchKernelGGL(k_batched_init, dim3(ub), dim3(kBlock), 0, s, n, G, (const int *)w.u_gid,
                      (const int *)w.b_vbase, (const int *)w.u_out_off, loc.pos, R[0], X[0],
-                     w.b_gdone, w.b_giters);
+                     w.b_gdone, w.b_giters, w.counts + kTileQueue);
   LAUNCH_TRY();
   // kReplayIters iterations captured on the library stream, after the work above
   hipStream_t cs = w.cap_stream;
@@ -1265,14 +1267,14 @@ int run_batched(const pr_csr *graphs, int G, const double *const *tele, double a
                        (const int *)w.chunk_hub_in, w.hub_part, CH, n, t1, xp.items, xp.off,
                        (const int *)w.u_gid, (const double *)w.b_c0, dtele,
                        (const int *)w.b_vbase, (const int *)w.b_gdone, G, alpha, w.b_gpart,
-                       (const Ctrl *)w.ctrl);
+                       w.counts + kTileQueue, (const Ctrl *)w.ctrl);
     hipLaunchKernelGGL(k_hub_finalize_batched, dim3(F), dim3(kBlock), shm, cs,
                        (const int *)w.hi_in, (const int *)w.counts, (const int *)w.hub_start_in,
                        (const double *)w.hub_part, (const int *)w.u_out_off, loc.pos,
                        (const double *)R[a], R[b], X[b], (const int *)w.u_gid,
                        (const double *)w.b_c0, dtele, (const int *)w.b_vbase,
                        (const int *)w.b_gdone, G, alpha, w.b_gpart + (size_t)B * G,
-                       (const Ctrl *)w.ctrl);
+                       w.counts + kTileQueue, (const Ctrl *)w.ctrl);
     hipLaunchKernelGGL(k_batched_final, dim3(G), dim3(kBlock), 0, cs, (const double *)w.b_gpart,
                        B + F, G, w.b_gdone, w.b_giters, w.b_gdelta, (const Ctrl *)w.ctrl, tol);
     hipLaunchKernelGGL(k_batched_done, dim3(1), dim3(kBlock), 0, cs, (const int *)w.b_gdone, G,
@@ -1462,7 +1464,7 @@ int run_static_noalloc(const pr_csr *g, double alpha, double tol, int max_iter,
                      chunk_hub);
   hipLaunchKernelGGL(k_static_init, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n,
                      g->out_offsets, (const int *)nullptr, (const double *)nullptr,
-                     1.0 / (double)n, 0, R[0], X[0]);
+                     1.0 / (double)n, 0, R[0], X[0], counts + kTileQueue);
   LAUNCH_TRY();
   const double C0 = (1.0 - alpha) / (double)n;
   const int np = B + kHubFinalizeBlocks;
@@ -1480,12 +1482,12 @@ int run_static_noalloc(const pr_csr *g, double alpha, double tol, int max_iter,
                          X[b], (const int *)hi, (const int *)counts, (const int *)hub_start,
                          (const int *)chunk_hub, hub_part, CH, n, t1, (const int4 *)nullptr,
                          (const int *)nullptr, C0, alpha, (const double *)nullptr, 0.0, partials,
-                         (const Ctrl *)ctrl);
+                         counts + kTileQueue, (const Ctrl *)ctrl);
       hipLaunchKernelGGL(k_hub_finalize_static, dim3(kHubFinalizeBlocks), dim3(kBlock), 0, s,
                          (const int *)hi, (const int *)counts, (const int *)hub_start,
                          (const double *)hub_part, g->out_offsets, (const int *)nullptr,
                          (const double *)R[a], R[b], X[b], C0, alpha, (const double *)nullptr,
-                         0.0, 0, partials + B, (const Ctrl *)ctrl);
+                         0.0, 0, partials + B, counts + kTileQueue, (const Ctrl *)ctrl);
       hipLaunchKernelGGL(k_linf_final, dim3(1), dim3(kFinalBlock), 0, s,
                          (const double *)partials, np, ctrl, tol, it);
       LAUNCH_TRY();
