@@ -160,7 +160,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_finalize_batched(
     const int *__restrict__ gdone, int G, double alpha, double *__restrict__ gpart,
     int *__restrict__ tq, const Ctrl *__restrict__ ctrl) {
   if (ctrl->done) return;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *tq = 0;  // the next rank update's tile queue
+  if (blockIdx.x == 0 && threadIdx.x < kXcds) tq[threadIdx.x] = 0;  // next launch's queues
   extern __shared__ unsigned long long s_gmax[];
   clear_table(s_gmax, G);
   const BatchOut out{out_off, pos, gid, C0g, tele, vb, gdone, R, Rn, Xn, alpha, s_gmax};
@@ -215,7 +215,7 @@ __global__ __launch_bounds__(kBlock) void k_batched_init(int N, int G, const int
                                                          double *__restrict__ X, int *gdone,
                                                          int *giters, int *__restrict__ tq) {
   const int stride = gridDim.x * kBlock;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *tq = 0;  // the first rank update's tile queue
+  if (blockIdx.x == 0 && threadIdx.x < kXcds) tq[threadIdx.x] = 0;  // first launch's queues
   for (int v = blockIdx.x * kBlock + threadIdx.x; v < N; v += stride) {
     const int g = gid[v];
     const double r = 1.0 / (double)(vbase[g + 1] - vbase[g]);

@@ -73,10 +73,11 @@ enum CountSlot {
   kInChunks = 4,   // chunks of the in-degree split class
   kOutChunks = 5,  // chunks of the out-degree split class
   kDtChanged = 6,  // a closure level of Dynamic Traversal marked a vertex
-  kTileQueue = 7,  // the rank updates' tile queue (Static, batched; PPR's row queue)
   kAffList = 8,    // per iteration parity p: slot 8 + 2p the affected list's size,
                    // 9 + 2p the rank update's tile queue over it
-  kNumCounts = 12
+  kTileQueue = 12, // slots 12 .. 19: the Static and batched rank updates' per-die
+                   // tile queues (slot 12 alone: PPR's row queue)
+  kNumCounts = 20
 };
 
 // Streamed data (CSR arrays, a vertex's own rank, new ranks) is read and
@@ -466,7 +467,7 @@ __global__ __launch_bounds__(kBlock) void k_static_init(int n, const int *__rest
                                                         double *__restrict__ X,
                                                         int *__restrict__ tq) {
   const int v = blockIdx.x * kBlock + threadIdx.x;
-  if (tq && v == 0) *tq = 0;  // the first rank update's tile queue
+  if (tq && v < kXcds) tq[v] = 0;  // the first rank update's tile queues
   if (v < n) {
     const double r = init ? init[v] : r0;
     R[v] = r;
@@ -618,12 +619,22 @@ __device__ __forceinline__ long long item_of(int beg, int gwx, long long s, long
 // see k_compact_affected), 256 to a tile, instead of over ID tiles of every
 // vertex; vertices not in the list had their dN flag cleared by the
 // compaction, which is what `inactive` does in the ID-tile sweep.
-// tq (may be null): the lane class's tiles are taken from this queue (an
-// atomic counter that the previous kernel on the stream cleared) instead of
-// round robin, so workgroups that finished their long-row work early take
-// more tiles; every workgroup leaves once the queue passes the last tile. A
-// list's tiles are few and of very uneven cost, so LIST always uses one
-// (acount[1], cleared by the compaction).
+// Tile queues: with more tiles than workgroups, the lane class's tiles are
+// taken from atomic counters that the previous kernel on the stream cleared,
+// instead of being dealt round robin, so workgroups that finished their
+// long-row work early take more tiles; a workgroup leaves once its counter
+// passes the last tile.
+//  - tq (Static, batched; may be null): 8 counters, one per die; die x's
+//    workgroups take the round robin's tiles x, x + 8, x + 16, ... from
+//    counter x.
+//  - LIST: a sparse list (at most n/4 affected vertices), whose tiles are
+//    few and of very uneven cost, is shared out by the whole chip from one
+//    counter (acount[1], cleared by the compaction); a denser list is dealt
+//    round robin, like the ID tiles it then resembles.
+// Measured and not kept: one counter for all Static tiles, each die taking
+// the tiles of its own vertex range, and workgroups moving on to other dies'
+// counters once theirs ran out were all slower; so was claiming the next
+// tile before summing the current one.
 template <bool WEIGHTED, int LG, class Out, bool LIST = false>
 __device__ __forceinline__ void rank_update(
     const int *__restrict__ in_off, const int *__restrict__ in_src,
@@ -756,10 +767,16 @@ __device__ __forceinline__ void rank_update(
     __shared__ int s_tile;
     const int nrows = LIST ? acount[0] : n;
     const int ntiles = (nrows + kBlock - 1) / kBlock;
-    int *queue = LIST ? acount + 1 : tq;
+    int *queue = (ntiles > B && B >= kXcds && (!LIST || nrows <= n / 4))
+                     ? (LIST ? acount + 1 : tq)
+                     : nullptr;
+    const int qd = (int)blockIdx.x % kXcds;
     for (int t = blockIdx.x;; t += B) {
       if (queue) {
-        if (tid == 0) s_tile = atomicAdd(queue, 1);
+        if (tid == 0) {
+          if (LIST) s_tile = atomicAdd(queue, 1);
+          else s_tile = qd + kXcds * atomicAdd(queue + qd, 1);
+        }
         __syncthreads();
         t = s_tile;
       }
@@ -898,7 +915,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_finalize_static(
     double tscale, int weighted, double *__restrict__ partials, int *__restrict__ tq,
     const Ctrl *__restrict__ ctrl) {
   if (ctrl->done) return;
-  if (tq && blockIdx.x == 0 && threadIdx.x == 0) *tq = 0;  // the next rank update's tile queue
+  if (tq && blockIdx.x == 0 && threadIdx.x < kXcds) tq[threadIdx.x] = 0;  // next launch's queues
   const StaticOut out{out_off, pos, R, Rn, Xn, C0, alpha, tele, tscale, weighted != 0};
   hub_finalize(hi, counts, hub_start, hub_part, out, partials);
 }
@@ -990,18 +1007,32 @@ __device__ __forceinline__ void mark(uint8_t *dV, int v) {
 }
 
 // The affected set after a marking, compacted: every v with dV[v] is
-// appended to list (*count slots reserved with one atomic per workgroup and
-// round, so the list order varies run to run; the results do not, since each
-// vertex is summed by its own lane in row order whatever tile it lands in).
-// A vertex that is not affected has its dN flag cleared: the clearing of
-// delta_N at the start of the next iteration (Alg. 2), which the rank update
-// then skips for the vertices it does not visit. A workgroup round covers
-// kCompactRun vertices, 16 per thread, read as one 16-byte load of each flag
-// array (the flag arrays are 256-byte aligned and padded to a multiple of 256).
-// It also clears `queue`, the tile queue the next rank update takes its list
-// tiles from.
+// appended to list. A vertex that is not affected has its dN flag cleared:
+// the clearing of delta_N at the start of the next iteration (Alg. 2), which
+// the rank update then skips for the vertices it does not visit. Workgroup b
+// owns a contiguous run of rounds of kCompactRun vertices (16 per thread,
+// read as one 16-byte load of each flag array; the flag arrays are 256-byte
+// aligned and padded to a multiple of 256). A first pass counts its affected
+// vertices and clears dN, one atomic add reserves its slots in the list, and
+// a second pass (the flags again, now from L2) writes them in ascending
+// order. The list is ascending inside each workgroup's run and the runs land
+// in atomic order, which varies run to run; the results do not, since each
+// vertex is summed by its own lane in row order whatever tile it lands in.
+// One atomic per workgroup, not per round: many adds on one address queue up.
+// It also clears `queue`, the 8 per-die counters the next rank update takes
+// its list tiles from.
 constexpr int kCompactPer = 16;
 constexpr int kCompactRun = kBlock * kCompactPer;
+__device__ __forceinline__ uint32_t affected_bits(const uint8_t *__restrict__ dV, int v0, int n) {
+  if (v0 >= n) return 0;
+  const uint4 f = *(const uint4 *)(dV + v0);
+  const uint32_t w[4] = {f.x, f.y, f.z, f.w};
+  uint32_t keep = 0;  // bit j: vertex v0 + j is affected
+#pragma unroll
+  for (int j = 0; j < kCompactPer; ++j)
+    if (v0 + j < n && ((w[j >> 2] >> (8 * (j & 3))) & 0xFF) != 0) keep |= 1u << j;
+  return keep;
+}
 __global__ __launch_bounds__(kBlock) void k_compact_affected(const uint8_t *__restrict__ dV,
                                                              uint8_t *__restrict__ dN, int n,
                                                              int *__restrict__ list,
@@ -1012,42 +1043,47 @@ __global__ __launch_bounds__(kBlock) void k_compact_affected(const uint8_t *__re
   if (blockIdx.x == 0 && threadIdx.x == 0) *queue = 0;  // tile queue of the next rank update
   __shared__ int s_base;
   const int tid = threadIdx.x;
-  for (long long r0 = (long long)blockIdx.x * kCompactRun; r0 < n;
-       r0 += (long long)gridDim.x * kCompactRun) {
-    const int v0 = (int)r0 + tid * kCompactPer;
-    uint4 fv = make_uint4(0, 0, 0, 0), fn = make_uint4(0, 0, 0, 0);
+  const long long rounds = ((long long)n + kCompactRun - 1) / kCompactRun;
+  const long long per = (rounds + gridDim.x - 1) / gridDim.x;
+  const long long q0 = (long long)blockIdx.x * per, q1 = min(rounds, q0 + per);
+  // pass 1: count, and clear dN of the vertices that are not affected
+  int mine = 0;
+  for (long long q = q0; q < q1; ++q) {
+    const int v0 = (int)(q * kCompactRun) + tid * kCompactPer;
+    const uint32_t keep = affected_bits(dV, v0, n);
+    mine += __popc(keep);
     if (v0 < n) {
-      fv = *(const uint4 *)(dV + v0);
-      fn = *(const uint4 *)(dN + v0);
-    }
-    const uint32_t wv[4] = {fv.x, fv.y, fv.z, fv.w};
-    uint32_t wn[4] = {fn.x, fn.y, fn.z, fn.w};
-    uint32_t keep = 0;  // bit j: vertex v0 + j is affected
-    bool clear = false;
+      const uint4 fn = *(const uint4 *)(dN + v0);
+      uint32_t wn[4] = {fn.x, fn.y, fn.z, fn.w};
+      bool clear = false;
 #pragma unroll
-    for (int j = 0; j < kCompactPer; ++j) {
-      const uint32_t sh = 8 * (j & 3);
-      const bool in = v0 + j < n;
-      const bool a = in && ((wv[j >> 2] >> sh) & 0xFF) != 0;
-      if (a) keep |= 1u << j;
-      if (in && !a && ((wn[j >> 2] >> sh) & 0xFF) != 0) {
-        wn[j >> 2] &= ~(0xFFu << sh);
-        clear = true;
+      for (int j = 0; j < kCompactPer; ++j) {
+        const uint32_t sh = 8 * (j & 3);
+        if (v0 + j < n && !((keep >> j) & 1) && ((wn[j >> 2] >> sh) & 0xFF) != 0) {
+          wn[j >> 2] &= ~(0xFFu << sh);
+          clear = true;
+        }
       }
+      if (clear) *(uint4 *)(dN + v0) = make_uint4(wn[0], wn[1], wn[2], wn[3]);
     }
-    if (clear) *(uint4 *)(dN + v0) = make_uint4(wn[0], wn[1], wn[2], wn[3]);
-    const int c = __popc(keep);
-    int total;
-    const int off = block_exclusive_scan<kBlock>(c, &total);
-    if (tid == 0) s_base = total ? atomicAdd(count, total) : 0;
-    __syncthreads();
-    int at = s_base + off;
+  }
+  int total;
+  (void)block_exclusive_scan<kBlock>(mine, &total);
+  if (tid == 0) s_base = total ? atomicAdd(count, total) : 0;
+  __syncthreads();
+  int base = s_base;
+  // pass 2: write the affected vertices in order
+  for (long long q = q0; q < q1 && total; ++q) {
+    const int v0 = (int)(q * kCompactRun) + tid * kCompactPer;
+    uint32_t keep = affected_bits(dV, v0, n);
+    int rt;
+    int at = base + block_exclusive_scan<kBlock>(__popc(keep), &rt);
     while (keep) {
       const int j = __ffs(keep) - 1;
       keep &= keep - 1;
       list[at++] = v0 + j;
     }
-    __syncthreads();
+    base += rt;
   }
 }
 

@@ -809,7 +809,7 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
   // compaction of the affected set after the marking of iteration it, for
   // iteration it + 1 (list by parity of it + 1)
   const int cgrid_list =
-      std::max(1, std::min((n + kCompactRun - 1) / kCompactRun, 8 * std::max(1, w.num_cus)));
+      std::max(1, std::min((n + kCompactRun - 1) / kCompactRun, 2 * std::max(1, w.num_cus)));
   auto compact = [&](int it) {
     const int q = (it + 1) & 1;
     hipLaunchKernelGGL(k_compact_affected, dim3(cgrid_list), dim3(kBlock), 0, s,
