@@ -43,7 +43,7 @@ __device__ __forceinline__ double ppr_row_sum(const int *__restrict__ src,
 // One PPR iteration. Work items: chunks of the split class (rows with
 // in-degree > CH, listed in hi[n1 + i] with their chunk plan) first,
 // wavefront gw of W taking items gw, gw + W, ...; then all other vertices,
-// 64 consecutive rows per take from a row queue.
+// 64 consecutive rows per take from per-die row queues.
 // vdone[k] marks frozen vectors (their lanes neither read nor write).
 // pmax: per-workgroup, per-vector maxima [gridDim.x][K].
 __global__ __launch_bounds__(kBlock) void k_ppr_rank(
@@ -90,17 +90,23 @@ __global__ __launch_bounds__(kBlock) void k_ppr_rank(
     for (int k = lane; k < K; k += kWave)
       if (!vdone[k]) part[(size_t)c * K + k] = ppr_row_sum(in_src, X, K, k, e0, e1);
   }
-  // other rows: full sums and the update. A wavefront takes the next 64
-  // consecutive rows from the row queue rq (an atomic counter the previous
-  // kernel on the stream cleared), loads their metadata (one row per lane) in
-  // one round trip and walks them one by one; row costs vary with in-degree,
-  // so wavefronts that drew short rows take more. Every wavefront leaves once
-  // the queue passes n.
+  // other rows: full sums and the update, in runs of 64 consecutive rows.
+  // Run c belongs to die c mod 8 (as when runs are dealt round robin); a
+  // wavefront takes its die's next run from that die's counter in rq (8
+  // atomic counters the previous kernel on the stream cleared), loads the
+  // run's metadata (one row per lane) in one round trip and walks its rows
+  // one by one. Row costs vary with in-degree, so wavefronts that drew short
+  // rows take more runs. Every wavefront leaves once its counter passes n.
+  // A grid of fewer than 8 workgroups has no workgroup on some dies: then
+  // all runs come from the one counter rq[0].
+  const bool per_die = gridDim.x >= kXcds;
+  const int die = per_die ? (int)blockIdx.x % kXcds : 0, stride = per_die ? kXcds : 1;
   for (;;) {
-    int r0 = 0;
-    if (lane == 0) r0 = atomicAdd(rq, kWave);
-    r0 = __shfl(r0, 0);
-    if (r0 >= n) break;
+    int run = 0;
+    if (lane == 0) run = die + stride * atomicAdd(rq + die, 1);
+    const long long first = (long long)__shfl(run, 0) * kWave;
+    if (first >= n) break;
+    const int r0 = (int)first;
     const long long vl = (long long)r0 + lane;
     int me0 = 0, me1 = 0, mdeg = 1, mpx = 0, mt = 0;
     bool ok = false;
@@ -148,7 +154,7 @@ __global__ __launch_bounds__(kBlock) void k_ppr_finalize(
     const int *__restrict__ vdone, double alpha, double *__restrict__ pmax,
     int *__restrict__ rq, const Ctrl *__restrict__ ctrl) {
   if (ctrl->done) return;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *rq = 0;  // the next rank update's row queue
+  if (blockIdx.x == 0 && threadIdx.x < kXcds) rq[threadIdx.x] = 0;  // next launch's row queues
   extern __shared__ double s_max[];
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   for (int k = lane; k < K; k += kWave) s_max[wid * K + k] = 0.0;
@@ -252,7 +258,7 @@ __global__ __launch_bounds__(kBlock) void k_ppr_init(int n, int K, const int *__
                                                      double *__restrict__ X, int *vdone,
                                                      int *viters, int *__restrict__ rq) {
   const size_t total = (size_t)n * K;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *rq = 0;  // the first rank update's row queue
+  if (blockIdx.x == 0 && threadIdx.x < kXcds) rq[threadIdx.x] = 0;  // first launch's row queues
   const double r0 = 1.0 / (double)n;
   for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total;
        i += (size_t)gridDim.x * kBlock) {
