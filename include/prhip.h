@@ -319,6 +319,7 @@ typedef struct pr_tuning {
   int32_t xcd_split_degree;
   int32_t expand_pull_per_mille;
   int32_t frontier_list;
+  int32_t chain_numbering;
 } pr_tuning;
 
 /* frontier_list       DF/DF-P/DT: 1 = after each marking the affected set is
@@ -327,13 +328,27 @@ typedef struct pr_tuning {
  *                     of 256 affected vertices); 0 = both sweep ID tiles of
  *                     every vertex and skip the unaffected ones. The same
  *                     ranks either way (bit for bit).
+ * chain_numbering     DF/DF-P/DT with relabel and the die split on: 1 = the
+ *                     gather-side numbering is kept from one such call to
+ *                     the next on graphs of the same n, and each call maps
+ *                     its in-CSR from the mapping the previous call left (a
+ *                     streamed copy of the rows whose sources match, a
+ *                     lookup elsewhere; nothing about the caller's arrays
+ *                     is assumed); the numbering is rebuilt once the
+ *                     entries not found that way, summed since it was
+ *                     built, pass 1/8 of the edges. 0 = numbering and
+ *                     mapping built inside each call (the next such call
+ *                     releases what was kept). The same ranks either
+ *                     way (bit for bit). Keeping it costs 16 m + 12 n bytes
+ *                     of device memory beyond the workspace.
  * Defaults: lane_max_degree 128, wave_max_degree 4096, expand_lane_max_degree
  * 32, iters_per_sync 2, hub_chunk_edges 4096, grid_blocks 0, relabel -1,
- * xcd_split_degree 129, expand_pull_per_mille 20, frontier_list 1. */
+ * xcd_split_degree 129, expand_pull_per_mille 20, frontier_list 1,
+ * chain_numbering 1. */
 
 /* Set (NULL = defaults) or read the process-wide tuning. PR_EINVAL if a
  * field is out of range (degrees < 0, lane > wave, iters_per_sync < 1,
- * xcd_split_degree == 1, frontier_list not 0 or 1). */
+ * xcd_split_degree == 1, frontier_list or chain_numbering not 0 or 1). */
 int pr_set_tuning(const pr_tuning *t);
 int pr_get_tuning(pr_tuning *t);
 
@@ -356,7 +371,8 @@ typedef struct pr_stats {
   int64_t affected_initial;
   double rank_kernel_ms;
   int32_t rank_kernel_launches;
-  int32_t reserved0;
+  int32_t numbering;         /* gather-side numbering of the call: 0 none, 1 built */
+                             /* by it, 2 kept from an earlier DF/DF-P/DT call     */
   double total_ms;
   int64_t affected_max;      /* DF/DF-P/DT, profiling level 2: largest affected set */
   int64_t edges_processed;   /* of an iteration, and the in-edges of the affected */

@@ -75,9 +75,10 @@ enum CountSlot {
   kDtChanged = 6,  // a closure level of Dynamic Traversal marked a vertex
   kAffList = 8,    // per iteration parity p: slot 8 + 2p the affected list's size,
                    // 9 + 2p the rank update's tile queue over it
-  kTileQueue = 12, // slots 12 .. 19: the Static and batched rank updates' per-die
-                   // tile queues (slot 12 alone: PPR's row queue)
-  kNumCounts = 20
+  kTileQueue = 12, // slots 12 .. 19: per-die work queues of the Static and batched
+                   // rank updates (tiles) and of the PPR update (runs of rows)
+  kMapMiss = 20,   // entries a mapping from a kept mapping did not find there
+  kNumCounts = 21
 };
 
 // Streamed data (CSR arrays, a vertex's own rank, new ranks) is read and
@@ -1525,18 +1526,184 @@ __global__ __launch_bounds__(kBlock) void k_map_sources(const int *__restrict__ 
     st_nt(dst + e, newid[ld_nt(src + e)]);
 }
 
+// A mapping kept from an earlier in-CSR of the same vertex set under the
+// same numbering: its row offsets, its sources and their numbers, with
+// old_map[p] == newid[old_raw[p]] at every p < old_m. A source u read at
+// entry e may take old_map[p] for any p with old_raw[p] == u, wherever p
+// lies; the guess p = e + old_off[v] - off[v] (v = e's row) finds it in every
+// row that an update left alone, so the random newid reads are left to the
+// rows it changed. Maps written with the copies (raw_out, off_out) are the
+// next call's kept mapping, and the invariant carries over.
+//   MODE 0: dst[e] = newid[src[e]]
+//   MODE 1: the same, also writing raw_out and off_out
+//   MODE 2: as MODE 1, probing the kept mapping first
+struct MapCache {
+  const int *old_off, *old_raw, *old_map;
+  int old_m;
+  int *raw_out, *off_out;
+  int *miss;  // MODE 2: entries not found by the guess (one atomic per wavefront)
+};
+
+// Entries [a, b) of a run whose kept positions are e + shift (MODE 2), e.g.
+// the rows of a wavefront that all kept their offsets' shift: every lane keeps
+// kMapUnroll strides of the wavefront in flight (their loads first, then the
+// lookups of the entries not found, then the stores), the last pass with the
+// strides past b switched off.
+constexpr int kMapUnroll = 8;
+
+template <int MODE>
+__device__ __forceinline__ void map_run(const int *__restrict__ src,
+                                        const int *__restrict__ newid, int *__restrict__ dst,
+                                        int a, int b, int shift, const MapCache &c, int &miss) {
+  const int lane = threadIdx.x & (kWave - 1);
+  for (int e = a + lane; e - lane < b; e += kMapUnroll * kWave) {
+    int u[kMapUnroll], o[kMapUnroll], mm[kMapUnroll];
+#pragma unroll
+    for (int k = 0; k < kMapUnroll; ++k) {
+      const int ek = e + k * kWave;
+      u[k] = 0;
+      o[k] = 0;
+      mm[k] = 0;
+      if (ek < b) {
+        u[k] = ld_nt(src + ek);
+        if (MODE == 2) {
+          const int p = ek + shift;
+          const bool in = (unsigned)p < (unsigned)c.old_m;
+          o[k] = in ? ld_nt(c.old_raw + p) : -1;  // sources are >= 0
+          mm[k] = in ? ld_nt(c.old_map + p) : 0;
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kMapUnroll; ++k) {
+      const int ek = e + k * kWave;
+      if (ek < b) {
+        int id;
+        if (MODE == 2 && o[k] == u[k]) {
+          id = mm[k];
+        } else {
+          id = newid[u[k]];
+          if (MODE == 2) ++miss;
+        }
+        st_nt(dst + ek, id);
+        if (MODE >= 1) st_nt(c.raw_out + ek, u[k]);
+      }
+    }
+  }
+}
+
+// One wavefront-wide chunk of ONE row (MODE 2) at [cb, cb + 64) clipped to
+// b, from the guess e + shift. Rows are ascending, so within one row the kept
+// entries a wavefront loads at e + shift are ascending too: an entry not
+// found at its own lane is looked for among the wavefront's 64 (a cross-lane
+// binary search), which finds it when an update moved it by less than 64
+// places, and the shift that the last entry so found shows is carried to the
+// rest of the row.
+__device__ __forceinline__ void map_chunk_kept(const int *__restrict__ src,
+                                               const int *__restrict__ newid,
+                                               int *__restrict__ dst, int cb, int b, int &shift,
+                                               const MapCache &c, int &miss) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int e = cb + lane;
+  const bool v = e < b;
+  const int u = v ? ld_nt(src + e) : 0;
+  const int p = e + shift;
+  const bool in = (unsigned)p < (unsigned)c.old_m;
+  // places outside the kept entries read as -1 below and +infinity above
+  const int o = in ? ld_nt(c.old_raw + p) : (p < 0 ? -1 : 0x7fffffff);
+  const int mm = in ? ld_nt(c.old_map + p) : 0;
+  bool hit = v && o == u;
+  int id = mm;
+  if (__ballot(v && !hit)) {
+    int lo = 0;  // last lane j with o_j <= u
+#pragma unroll
+    for (int st = kWave / 2; st >= 1; st >>= 1) {
+      const int oj = __shfl(o, lo + st);
+      if (lo + st < kWave && oj <= u) lo += st;
+    }
+    const int oj = __shfl(o, lo), mj = __shfl(mm, lo);
+    const bool found = v && !hit && oj == u;  // u >= 0 never equals the fillers
+    if (found) id = mj;
+    const unsigned long long fb = __ballot(found);
+    if (fb) {
+      const int L = 63 - __clzll(fb);
+      shift += __shfl(lo - lane, L);
+    }
+    hit = hit || found;
+  }
+  if (v) {
+    if (!hit) {
+      id = newid[u];
+      ++miss;
+    }
+    st_nt(dst + e, id);
+    st_nt(c.raw_out + e, u);
+  }
+}
+
+// Entries [a, b) of ONE row (MODE 2): four chunks loaded at once at the
+// current shift; when all of their entries are found where guessed they are
+// stored as loaded, otherwise the four are done one by one by map_chunk_kept.
+__device__ __forceinline__ void map_row_kept(const int *__restrict__ src,
+                                             const int *__restrict__ newid,
+                                             int *__restrict__ dst, int a, int b, int shift,
+                                             const MapCache &c, int &miss) {
+  const int lane = threadIdx.x & (kWave - 1);
+  for (int cb = a; cb < b; cb += 4 * kWave) {
+    int u[4], mm[4];
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int e = cb + k * kWave + lane, p = e + shift;
+      u[k] = 0;
+      mm[k] = 0;
+      if (e < b) {
+        u[k] = ld_nt(src + e);
+        const bool in = (unsigned)p < (unsigned)c.old_m;
+        const int o = in ? ld_nt(c.old_raw + p) : -1;
+        mm[k] = in ? ld_nt(c.old_map + p) : 0;
+        ok = ok && o == u[k];
+      }
+    }
+    if (__ballot(!ok) == 0) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int e = cb + k * kWave + lane;
+        if (e < b) {
+          st_nt(dst + e, mm[k]);
+          st_nt(c.raw_out + e, u[k]);
+        }
+      }
+      continue;
+    }
+    for (int k = 0; k < 4 && cb + k * kWave < b; ++k)
+      map_chunk_kept(src, newid, dst, cb + k * kWave, b, shift, c, miss);
+  }
+}
+
+template <int MODE>
+__device__ __forceinline__ void map_misses(int miss, const MapCache &c) {
+  if (MODE != 2) return;
+  miss = wave_sum_int(miss);
+  if ((threadIdx.x & (kWave - 1)) == 0 && miss) atomicAdd(c.miss, miss);
+}
+
 // The same renumbering split by the die-split plan. Rows with at least T
 // in-edges are mapped item by item, list x by the workgroups on die x (the
 // items of list x have their sources in range x, so the newid entries a die
 // reads are that range's eighth of the table, as the rank kernel's gathers
 // are). A wavefront loads 64 items, one per lane, dealt out as in the rank
 // kernel (item_of), and maps them one after the other with all its lanes.
-template <int LG>
+// MODE 2 takes only the items of rows with at least min_len entries (the
+// others go to k_map_short).
+template <int LG, int MODE>
 __global__ __launch_bounds__(kBlock) void k_map_split(const int4 *__restrict__ xitems,
                                                       const int *__restrict__ xoff,
+                                                      const int *__restrict__ row_off,
                                                       const int *__restrict__ src,
                                                       const int *__restrict__ newid,
-                                                      int *__restrict__ dst) {
+                                                      int *__restrict__ dst, MapCache c,
+                                                      int min_len) {
   const int B = gridDim.x, lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   const int x0 = B >= kXcds ? (int)blockIdx.x % kXcds : (int)blockIdx.x;
   const int xstep = B >= kXcds ? kXcds : B;
@@ -1544,69 +1711,115 @@ __global__ __launch_bounds__(kBlock) void k_map_split(const int4 *__restrict__ x
   const int nloc = B >= kXcds ? (B - 1 - x0) / kXcds + 1 : 1;
   const long long Wd = (long long)nloc * kWavesPerBlock;
   const int gwx = loc * kWavesPerBlock + wid;
+  int miss = 0;
   for (int x = x0; x < kXcds; x += xstep) {
     const int beg = xoff[x], end = xoff[x + 1];
     for (long long k0 = 0; item_of<LG>(beg, gwx, k0, Wd) < end; k0 += kWave) {
       const long long j = item_of<LG>(beg, gwx, k0 + lane, Wd);
       const int4 it = j < end ? xitems[j] : make_int4(0, 0, 0, 0);
-      unsigned long long vm = __ballot(j < end);
+      bool take = j < end;
+      int sh = 0;  // the shift of the item's row between the two layouts
+      if (MODE == 2 && take) {
+        const int r0 = row_off[it.w];
+        take = row_off[it.w + 1] - r0 >= min_len;
+        sh = c.old_off[it.w] - r0;
+      }
+      unsigned long long vm = __ballot(take);
       while (vm) {
         const int q = __ffsll(vm) - 1;
         vm &= vm - 1;
-        const int e0 = __shfl(it.y, q), e1 = __shfl(it.z, q);
-        for (int e = e0 + lane; e < e1; e += kWave) st_nt(dst + e, newid[ld_nt(src + e)]);
+        const int e0 = __shfl(it.y, q), e1 = __shfl(it.z, q), shq = __shfl(sh, q);
+        if (MODE == 2) map_row_kept(src, newid, dst, e0, e1, shq, c, miss);
+        else map_run<MODE>(src, newid, dst, e0, e1, 0, c, miss);
       }
     }
   }
+  map_misses<MODE>(miss, c);
 }
 
-// Rows with fewer than T in-edges: a wavefront takes 64 consecutive rows.
-// When none of them is long their entries are one contiguous run; otherwise
-// the short rows are laid end to end (a scan of their lengths) and entry k
-// belongs to the last row whose start excl_j is <= k (a cross-lane binary
-// search). Either way the loads of a wavefront are contiguous runs.
+// Rows with fewer than T in-edges: a wavefront takes 64 consecutive rows and
+// cuts them into segments, maximal runs of consecutive such rows (which lie
+// end to end in memory) with one shift to the kept layout (MODE 2; 0
+// otherwise), and maps each segment as one run. In MODE 2 a row of at least
+// kKeptSearchLen entries whose length changed (the next row's shift differs
+// from its own) is a segment of its own, mapped as one row with the in-row
+// search; in a shorter changed row the entries after the change are looked
+// up. MODE >= 1 also copies the row offsets.
+constexpr int kKeptSearchLen = 256;
+
+template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_map_short(const int *__restrict__ in_off,
                                                       const int *__restrict__ src, int n, int T,
                                                       const int *__restrict__ newid,
-                                                      int *__restrict__ dst) {
+                                                      int *__restrict__ dst, MapCache c) {
   const int lane = threadIdx.x & (kWave - 1);
   const long long nw = (long long)gridDim.x * kWavesPerBlock;
-  for (long long wv = (long long)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; wv * kWave < n;
-       wv += nw) {
-    const int r = (int)(wv * kWave) + lane;
-    int e0 = 0, cnt = 0;
-    bool lng = false;
-    if (r < n) {
-      e0 = in_off[r];
-      const int d = in_off[r + 1] - e0;
-      lng = d >= T;
-      if (!lng) cnt = d;
+  int miss = 0;
+  long long wv = (long long)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+  // the offsets of the wavefront's next 64 rows (and their kept ones), loaded
+  // while the current rows are mapped
+  int ne0 = 0, ne1 = 0, no0 = 0, no1 = 0;
+  auto fetch = [&](long long g) {
+    const long long rr = g * kWave + lane;
+    if (rr < n) {
+      ne0 = in_off[rr];
+      ne1 = in_off[rr + 1];
+      if (MODE == 2) {
+        no0 = c.old_off[rr];
+        no1 = c.old_off[rr + 1];
+      }
     }
-    int x = cnt;
+  };
+  if (wv * kWave < n) fetch(wv);
+  for (; wv * kWave < n; wv += nw) {
+    const int r = (int)(wv * kWave) + lane;
+    const int ce0 = ne0, ce1 = ne1, co0 = no0, co1 = no1;
+    if ((wv + nw) * kWave < n) fetch(wv + nw);
+    int e0 = 0, cnt = 0, sh = 0;
+    bool mine = false, alone = false;
+    if (r < n) {
+      e0 = ce0;
+      const int e1 = ce1, d = e1 - e0;
+      mine = d < T;
+      if (mine) cnt = d;
+      if (MODE == 2) {
+        sh = co0 - e0;
+        alone = mine && d >= kKeptSearchLen && co1 - e1 != sh;
+      }
+      if (MODE >= 1) {
+        c.off_out[r] = e0;
+        if (r == n - 1) c.off_out[n] = e1;
+      }
+    }
+    // a segment starts at a row of this kernel unless the previous row is
+    // one too, of the same shift, and neither is mapped alone
+    const int psh = __shfl_up(sh, 1);
+    const bool pmine = __shfl_up((int)mine, 1) != 0, palone = __shfl_up((int)alone, 1) != 0;
+    const bool start = mine && (lane == 0 || !pmine || palone || alone || psh != sh);
+    // ... and ends before the next start or the next row not of this kernel
+    const unsigned long long starts = __ballot(start), stops = __ballot(!mine) | starts;
+    int x = cnt;  // inclusive scan of the lengths of this kernel's rows
 #pragma unroll
     for (int o = 1; o < kWave; o <<= 1) {
       const int y = __shfl_up(x, o);
       if (lane >= o) x += y;
     }
-    const int excl = x - cnt, total = __shfl(x, kWave - 1);
-    if (__ballot(lng) == 0) {
-      const int base = __shfl(e0, 0);
-      for (int k = lane; k < total; k += kWave) st_nt(dst + base + k, newid[ld_nt(src + base + k)]);
-      continue;
-    }
-    for (int k0 = 0; k0 < total; k0 += kWave) {
-      const int k = min(k0 + lane, total - 1);
-      int lo = 0, hi = kWave;
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (__shfl(excl, mid) <= k) lo = mid;
-        else hi = mid;
-      }
-      const int e = __shfl(e0, lo) + (k - __shfl(excl, lo));
-      const int u = ld_nt(src + e);
-      if (k0 + lane < total) st_nt(dst + e, newid[u]);
+    unsigned long long sm = starts;
+    while (sm) {
+      const int j = __ffsll(sm) - 1;
+      sm &= sm - 1;
+      const unsigned long long after = stops & ~((2ull << j) - 1);
+      const int jend = after ? __ffsll(after) - 1 : kWave;  // rows j .. jend - 1
+      // entries of rows j .. jend - 1, end to end
+      const int len = __shfl(x, jend - 1) - __shfl(x, j) + __shfl(cnt, j);
+      const int a = __shfl(e0, j), shj = __shfl(sh, j);
+      if (MODE == 2 && __shfl((int)alone, j))
+        map_row_kept(src, newid, dst, a, a + len, shj, c, miss);
+      else
+        map_run<MODE>(src, newid, dst, a, a + len, shj, c, miss);
     }
   }
+  map_misses<MODE>(miss, c);
 }
 
 // Count of affected vertices (profiling only).

@@ -54,6 +54,7 @@ pr_tuning default_tuning() {
   t.xcd_split_degree = 129;
   t.expand_pull_per_mille = 20;
   t.frontier_list = 1;
+  t.chain_numbering = 1;
   return t;
 }
 pr_tuning g_tuning = default_tuning();
@@ -75,6 +76,15 @@ struct Workspace {
   int *alist = nullptr;        // [2][n] affected lists of DF/DF-P/DT (by iteration parity)
   int *newid = nullptr;        // [n] gather-side numbering
   int *src_p = nullptr;        // [m] in-CSR sources in that numbering
+  // DF/DF-P/DT chains (tuning chain_numbering): the numbering of such calls,
+  // kept across them, and the in-CSR the last one mapped (row offsets,
+  // sources, their numbers), two of each so that a call maps from one pair
+  // while writing the other. nc_cur < 0: nothing kept.
+  int *nc_newid = nullptr;
+  int *nc_off[2] = {}, *nc_raw[2] = {}, *nc_map[2] = {};
+  size_t nc_cap_n = 0, nc_cap_m = 0;
+  int nc_cur = -1, nc_n = 0, nc_m[2] = {};
+  long long nc_miss = 0, nc_built_m = 0;  // entries missed since the numbering was built
   int *tile_counts = nullptr;  // [kGroups][ntiles]
   int *counts = nullptr;       // [kNumCounts]
   int *group_totals = nullptr; // [kGroups]
@@ -183,6 +193,17 @@ void free_batch(Workspace &w) {
   w.cap_u_n = w.cap_u_m = w.cap_b_g = w.cap_b_part = 0;
 }
 
+void free_chain(Workspace &w) {
+  (void)hipFree(w.nc_newid);
+  w.nc_newid = nullptr;
+  for (int i = 0; i < 2; ++i) {
+    (void)hipFree(w.nc_off[i]); (void)hipFree(w.nc_raw[i]); (void)hipFree(w.nc_map[i]);
+    w.nc_off[i] = w.nc_raw[i] = w.nc_map[i] = nullptr;
+  }
+  w.nc_cap_n = w.nc_cap_m = 0;
+  w.nc_cur = -1;
+}
+
 void free_xsplit(Workspace &w) {
   (void)hipFree(w.xmat); (void)hipFree(w.xitems);
   w.xmat = nullptr;
@@ -192,6 +213,7 @@ void free_xsplit(Workspace &w) {
 
 void free_ws(Workspace &w) {
   free_arrays(w);
+  free_chain(w);
   free_xsplit(w);
   (void)hipFree(w.xrs);
   free_ppr(w);
@@ -511,6 +533,54 @@ struct Locality {
   const int *pos;
   const int *src;
 };
+
+bool relabel_on(const pr_tuning &tn, int n) {
+  return tn.relabel > 0 || (tn.relabel < 0 && n >= (1 << 20));
+}
+
+// newid = the degree-based grouping of group_off (inside the ranges rs, if
+// given).
+int build_numbering(Workspace &w, int n, const int *group_off, const int *rs, int *newid,
+                    hipStream_t s) {
+  const int nt = (int)ntiles_for(n);
+  hipLaunchKernelGGL(k_group_count, dim3(nt), dim3(kBlock), 0, s, group_off, n, w.tile_counts,
+                     nt);
+  hipLaunchKernelGGL(k_scan_rows, dim3(kGroups), dim3(kFinalBlock), 0, s, w.tile_counts, nt,
+                     w.group_totals, (const int *)nullptr);
+  hipLaunchKernelGGL(k_group_scatter, dim3(nt), dim3(kBlock), 0, s, group_off, n,
+                     (const int *)w.tile_counts, (const int *)w.group_totals, nt, rs, newid);
+  LAUNCH_TRY();
+  return PR_OK;
+}
+
+// dst = newid applied to the entries of the in-CSR (row_off, idx): rows with
+// at least T entries item by item along the die-split plan xp (if it has
+// items), the others by k_map_short. From a kept mapping (MODE 2), whose
+// hits read no newid and so gain nothing from the die split, k_map_short
+// streams every row below kKeptItemLen entries too, and only the longer
+// rows are left to the items.
+constexpr int kKeptItemLen = 4096;
+
+template <int MODE>
+int map_rows(Workspace &w, const XPlan &xp, const int *row_off, const int *idx, int n, int T,
+             const int *newid, int *dst, const MapCache &c, hipStream_t s) {
+  const int Ts = MODE == 2 ? std::max(T, kKeptItemLen) : T;
+  if (xp.items) {
+    const int gs = kXcds * 4 * std::max(1, w.num_cus);
+    auto map_fn = item_lg(w, xp, gs) ? k_map_split<4, MODE> : k_map_split<0, MODE>;
+    hipLaunchKernelGGL(map_fn, dim3(gs), dim3(kBlock), 0, s, (const int4 *)xp.items,
+                       (const int *)xp.off, row_off, idx, newid, dst, c, Ts);
+  }
+  // a few groups of 64 rows per wavefront, so that their offsets are
+  // fetched ahead
+  const int gr = (int)std::min<long long>(((long long)n + kBlock - 1) / kBlock,
+                                          64LL * std::max(1, w.num_cus));
+  hipLaunchKernelGGL(k_map_short<MODE>, dim3(gr), dim3(kBlock), 0, s, row_off, idx, n, Ts,
+                     newid, dst, c);
+  LAUNCH_TRY();
+  return PR_OK;
+}
+
 // With a die-split plan `xp` over the rows of row_off (those with at least T
 // entries, ranges rs), the split rows are mapped on the die that owns each
 // segment and the shorter rows by k_map_short; otherwise one edge-parallel
@@ -519,33 +589,105 @@ int locality(Workspace &w, int n, int m, const int *group_off, const int *idx,
              const pr_tuning &tn, bool allowed, hipStream_t s, Locality *out,
              const int *rs = nullptr, const XPlan *xp = nullptr, const int *row_off = nullptr,
              int T = 0) {
-  const bool on = allowed && (tn.relabel > 0 || (tn.relabel < 0 && n >= (1 << 20)));
-  if (!on) {
+  if (!allowed || !relabel_on(tn, n)) {
     *out = Locality{nullptr, idx};
     return PR_OK;
   }
-  const int nt = (int)ntiles_for(n);
-  hipLaunchKernelGGL(k_group_count, dim3(nt), dim3(kBlock), 0, s, group_off, n, w.tile_counts,
-                     nt);
-  hipLaunchKernelGGL(k_scan_rows, dim3(kGroups), dim3(kFinalBlock), 0, s, w.tile_counts, nt,
-                     w.group_totals, (const int *)nullptr);
-  hipLaunchKernelGGL(k_group_scatter, dim3(nt), dim3(kBlock), 0, s, group_off, n,
-                     (const int *)w.tile_counts, (const int *)w.group_totals, nt, rs, w.newid);
+  int rc = build_numbering(w, n, group_off, rs, w.newid, s);
+  if (rc) return rc;
+  t_stats.numbering = 1;
   if (xp && xp->items && rs && row_off && T > 0) {
-    const int gs = kXcds * 4 * std::max(1, w.num_cus);
-    auto map_fn = item_lg(w, *xp, gs) ? k_map_split<4> : k_map_split<0>;
-    hipLaunchKernelGGL(map_fn, dim3(gs), dim3(kBlock), 0, s, (const int4 *)xp->items,
-                       (const int *)xp->off, idx, (const int *)w.newid, w.src_p);
-    const int gr = (int)std::min<long long>(((long long)n + kBlock - 1) / kBlock, 65536);
-    hipLaunchKernelGGL(k_map_short, dim3(gr), dim3(kBlock), 0, s, row_off, idx, n, T,
-                       (const int *)w.newid, w.src_p);
+    if ((rc = map_rows<0>(w, *xp, row_off, idx, n, T, w.newid, w.src_p, MapCache{}, s)))
+      return rc;
   } else {
     const int mb = std::min((m + kBlock - 1) / kBlock, 8 * std::max(1, w.num_cus) * 4);
     hipLaunchKernelGGL(k_map_sources, dim3(mb), dim3(kBlock), 0, s, idx, m, (const int *)w.newid,
                        w.src_p);
+    LAUNCH_TRY();
   }
-  LAUNCH_TRY();
   *out = Locality{w.newid, w.src_p};
+  return PR_OK;
+}
+
+// Storage of the numbering kept along DF/DF-P/DT chains (grow-only; the edge
+// arrays get 1/16 headroom, as a chain's edge count drifts). Growing drops
+// what was kept.
+int chain_ws(Workspace &w, size_t n, size_t m) {
+  if (n <= w.nc_cap_n && m <= w.nc_cap_m) return PR_OK;
+  const size_t nn = std::max(n, w.nc_cap_n), mm = std::max(m + m / 16 + 1024, w.nc_cap_m);
+  free_chain(w);
+  hipError_t e = hipMalloc(&w.nc_newid, nn * sizeof(int));
+  for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+    if ((e = hipMalloc(&w.nc_off[i], (nn + 1) * sizeof(int))) != hipSuccess) break;
+    if ((e = hipMalloc(&w.nc_raw[i], mm * sizeof(int))) != hipSuccess) break;
+    e = hipMalloc(&w.nc_map[i], mm * sizeof(int));
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    free_chain(w);
+    return fail(e == hipErrorOutOfMemory ? PR_ENOMEM : PR_EHIP,
+                std::string("chain numbering allocation: ") + hipGetErrorString(e));
+  }
+  w.nc_cap_n = nn;
+  w.nc_cap_m = mm;
+  return PR_OK;
+}
+
+// Kept numbering is rebuilt once the entries that its kept mappings did not
+// find, added over the calls since it was built, pass 1/kChainRebuild of the
+// edges it was built on (a measure of how far the graph has moved from it).
+constexpr long long kChainRebuild = 8;
+
+// Gather-side numbering of a DF/DF-P/DT call with the die split (arguments
+// as for locality). With chain_numbering on, the numbering is kept across
+// such calls on graphs of n vertices, and each call maps its in-CSR from the
+// mapping the previous one left (MapCache: a streamed copy wherever the rows
+// match, the numbering itself elsewhere) and leaves its own. The rank sums
+// do not depend on the numbering (rows keep their order, and the die
+// segments follow this call's ranges rs), so the ranks are the same bits
+// whether the numbering is kept or built anew.
+int locality_chain(Workspace &w, int n, int m, const int *group_off, const int *idx,
+                   const pr_tuning &tn, hipStream_t s, Locality *out, const int *rs,
+                   const XPlan &xp, const int *row_off, int T) {
+  if (!tn.chain_numbering && w.nc_cap_n) {
+    HIP_TRY(hipStreamSynchronize(s));
+    free_chain(w);  // turned off: what was kept is released
+  }
+  if (!tn.chain_numbering || !relabel_on(tn, n) || !rs || T <= 0)
+    return locality(w, n, m, group_off, idx, tn, true, s, out, rs, &xp, row_off, T);
+  int rc = chain_ws(w, (size_t)n, (size_t)m);
+  if (rc) return rc;
+  const int cur = w.nc_cur;
+  const bool keep = cur >= 0 && w.nc_n == n && w.nc_miss * kChainRebuild <= w.nc_built_m;
+  const int nx = cur >= 0 ? 1 - cur : 0;
+  w.nc_cur = -1;  // until this call's mapping is enqueued
+  MapCache c{};
+  c.raw_out = w.nc_raw[nx];
+  c.off_out = w.nc_off[nx];
+  if (keep) {
+    c.old_off = w.nc_off[cur];
+    c.old_raw = w.nc_raw[cur];
+    c.old_map = w.nc_map[cur];
+    c.old_m = w.nc_m[cur];
+    c.miss = w.counts + kMapMiss;
+    HIP_TRY(hipMemsetAsync(c.miss, 0, sizeof(int), s));
+    rc = map_rows<2>(w, xp, row_off, idx, n, T, w.nc_newid, w.nc_map[nx], c, s);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(w.host_counts + kMapMiss, c.miss, sizeof(int),
+                           hipMemcpyDeviceToHost, s));
+  } else {
+    if ((rc = build_numbering(w, n, group_off, rs, w.nc_newid, s))) return rc;
+    rc = map_rows<1>(w, xp, row_off, idx, n, T, w.nc_newid, w.nc_map[nx], c, s);
+    if (rc) return rc;
+    w.host_counts[kMapMiss] = 0;
+    w.nc_miss = 0;
+    w.nc_built_m = m;
+  }
+  w.nc_cur = nx;
+  w.nc_n = n;
+  w.nc_m[nx] = m;
+  t_stats.numbering = keep ? 2 : 1;
+  *out = Locality{w.nc_newid, w.nc_map[nx]};
   return PR_OK;
 }
 
@@ -784,9 +926,9 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
   auto rank_d = lg ? (use_list ? k_rank_dfp<false, 4, true> : k_rank_dfp<false, 4, false>)
                    : (use_list ? k_rank_dfp<false, 0, true> : k_rank_dfp<false, 0, false>);
   Locality loc;
-  if ((rc = locality(w, n, g->m, g->out_offsets, g->in_sources, tn, true, s, &loc,
-                     xs ? w.xrs : nullptr, &xp, g->in_offsets,
-                     std::max(xsplit_min_degree(tn), t1 + 1))))
+  if ((rc = locality_chain(w, n, g->m, g->out_offsets, g->in_sources, tn, s, &loc,
+                           xs ? w.xrs : nullptr, xp, g->in_offsets,
+                           std::max(xsplit_min_degree(tn), t1 + 1))))
     return rc;
   double *X = w.X0;
   hipLaunchKernelGGL(k_dfp_init, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n,
@@ -929,6 +1071,7 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
   if (rc) return rc;
   timer.stop();
   HIP_TRY(hipStreamSynchronize(s));
+  if (w.nc_cur >= 0 && loc.pos == w.nc_newid) w.nc_miss += w.host_counts[kMapMiss];
   const Ctrl &last = w.host_ctrl[(launched - 1) % kRing];
   if (last.err) return fail(PR_EBATCH, "batch vertex ID outside [0, n)");
   if (counters) {
@@ -1006,7 +1149,7 @@ int run_ppr(const pr_csr *g, const double *teleport, int K, double alpha, double
                      xs ? w.xrs : nullptr)))
     return rc;
   const int ib = (int)std::min<size_t>((nk + kBlock - 1) / kBlock, (size_t)B * 4);
-  int *rq = w.counts + kTileQueue;  // the rank kernel's row queue
+  int *rq = w.counts + kTileQueue;  // the rank kernel's 8 per-die row queues
   hipLaunchKernelGGL(k_ppr_init, dim3(ib), dim3(kBlock), 0, s, n, K, g->out_offsets, loc.pos,
                      Rb[0], Xb[0], w.ppr_vdone, w.ppr_viters, rq);
   hipLaunchKernelGGL(k_split_flags, dim3(std::min(B, (n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
@@ -1767,7 +1910,8 @@ int pr_set_tuning(const pr_tuning *t) {
       t->iters_per_sync < 1 || t->iters_per_sync >= kRing || t->hub_chunk_edges < 0 ||
       t->grid_blocks < 0 || t->grid_blocks > (1 << 20) || t->relabel < -1 || t->relabel > 1 ||
       t->xcd_split_degree < 0 || t->xcd_split_degree == 1 || t->expand_pull_per_mille < 0 ||
-      t->expand_pull_per_mille > 1000 || t->frontier_list < 0 || t->frontier_list > 1)
+      t->expand_pull_per_mille > 1000 || t->frontier_list < 0 || t->frontier_list > 1 ||
+      t->chain_numbering < 0 || t->chain_numbering > 1)
     return fail(PR_EINVAL, "tuning field out of range");
   g_tuning = *t;
   if (g_tuning.hub_chunk_edges == 0) g_tuning.hub_chunk_edges = 4096;

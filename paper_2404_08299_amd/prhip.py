@@ -51,19 +51,20 @@ class PrTuning(ctypes.Structure):
                 ("expand_lane_max_degree", ctypes.c_int32), ("iters_per_sync", ctypes.c_int32),
                 ("hub_chunk_edges", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
                 ("relabel", ctypes.c_int32), ("xcd_split_degree", ctypes.c_int32),
-                ("expand_pull_per_mille", ctypes.c_int32), ("frontier_list", ctypes.c_int32)]
+                ("expand_pull_per_mille", ctypes.c_int32), ("frontier_list", ctypes.c_int32),
+                ("chain_numbering", ctypes.c_int32)]
 
 
 TUNING_FIELDS = ("lane_max_degree", "wave_max_degree", "expand_lane_max_degree",
                  "iters_per_sync", "hub_chunk_edges", "grid_blocks", "relabel",
-                 "xcd_split_degree", "expand_pull_per_mille", "frontier_list")
+                 "xcd_split_degree", "expand_pull_per_mille", "frontier_list", "chain_numbering")
 
 
 class PrStats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("final_delta", ctypes.c_double), ("affected_initial", ctypes.c_int64),
                 ("rank_kernel_ms", ctypes.c_double), ("rank_kernel_launches", ctypes.c_int32),
-                ("reserved0", ctypes.c_int32), ("total_ms", ctypes.c_double),
+                ("numbering", ctypes.c_int32), ("total_ms", ctypes.c_double),
                 ("affected_max", ctypes.c_int64), ("edges_processed", ctypes.c_int64),
                 ("reserved", ctypes.c_double * 2)]
 
@@ -263,7 +264,8 @@ def last_stats() -> dict:
     return dict(iterations=s.iterations, converged=bool(s.converged), final_delta=s.final_delta,
                 affected_initial=s.affected_initial, rank_kernel_ms=s.rank_kernel_ms,
                 rank_kernel_launches=s.rank_kernel_launches, total_ms=s.total_ms,
-                affected_max=s.affected_max, edges_processed=s.edges_processed)
+                affected_max=s.affected_max, edges_processed=s.edges_processed,
+                numbering=s.numbering)
 
 
 def _result(rc, out):

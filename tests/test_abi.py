@@ -43,7 +43,7 @@ def test_status_codes_match_header():
 def test_struct_layouts():
     assert ctypes.sizeof(prhip.PrCsr) == 8 + 4 * 8
     assert ctypes.sizeof(prhip.PrEdges) == 24
-    assert ctypes.sizeof(prhip.PrTuning) == 10 * 4
+    assert ctypes.sizeof(prhip.PrTuning) == 11 * 4
     # the binding's tuning fields are the header's, in order
     text = open(os.path.join(ROOT, "include", "prhip.h")).read()
     body = re.search(r"typedef struct pr_tuning \{(.*?)\} pr_tuning;", text, re.S).group(1)

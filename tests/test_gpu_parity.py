@@ -398,3 +398,82 @@ def test_dfp_affected_count_and_bad_batch():
     with pytest.raises(prhip.PrError) as e:
         gpu_dfp(g1, bad, prev)
     assert e.value.code == prhip.PR_EBATCH
+
+
+def row_aligned_misses(old, new):
+    """Entries of new's in-CSR whose source is not at the same place of its
+    row in old's in-CSR (position e + old_off[v] - new_off[v], inside old's
+    entries): an upper bound, in practice, on what a kept mapping misses."""
+    v = np.repeat(np.arange(new.n), np.diff(new.in_offsets))
+    e = np.arange(new.m)
+    p = e + old.in_offsets[v].astype(np.int64) - new.in_offsets[v]
+    ok = (p >= 0) & (p < old.m)
+    hit = np.zeros(new.m, bool)
+    hit[ok] = old.in_sources[p[ok]] == new.in_sources[e[ok]]
+    return int(new.m - hit.sum())
+
+
+@pytest.mark.parametrize("mode", ["dfp", "df", "dt"])
+@pytest.mark.parametrize("tuning", [dict(relabel=1), dict(relabel=1, grid_blocks=13),
+                                    dict(relabel=1, lane_max_degree=4, xcd_split_degree=16,
+                                         hub_chunk_edges=8)])
+def test_chain_numbering_same_bits(mode, tuning):
+    """A chain of updates G1 -> G2 -> G3 (each R^t from the previous call),
+    then G3 with its vertices renamed at random (same n, rows unrelated to
+    the kept ones), then G3 again and a graph of another n. With the
+    numbering kept across the calls (chain_numbering = 1) every call gives
+    the same bits and iteration count as with it built inside each call
+    (chain_numbering = 0). The calls report a kept numbering for G2, G3 and
+    the renamed graph, whose mapping misses most entries, so that the next
+    call builds it anew, as does the one with another n."""
+    # R-MAT plus one row of 6000 in-edges (kept mappings take rows of 4096
+    # entries and more item by item, with the in-row search)
+    base = gg.rmat_graph(13, 12, seed=21)
+    s0, d0 = base.edges()
+    hub = np.random.default_rng(21).choice(base.n, 6000, replace=False).astype(np.int32)
+    g0 = gg.from_edges(base.n, np.concatenate([s0, hub]),
+                       np.concatenate([d0, np.full(hub.size, 5, np.int32)]))
+    assert np.diff(g0.in_offsets).max() >= 6000
+    b1 = gg.random_batch(g0, gg.batch_size_for(g0, 1e-3), seed=31)
+    g1 = gg.apply_batch(g0, b1)
+    prev0 = oracle.static(g0.n, *g0.edges()).ranks
+    b2 = gg.random_batch(g1, gg.batch_size_for(g1, 1e-4), seed=22)
+    g2 = gg.apply_batch(g1, b2)
+    b3 = gg.random_batch(g2, gg.batch_size_for(g2, 3e-3), seed=23)
+    g3 = gg.apply_batch(g2, b3)
+    # the hub row changed within the chain, so its mapping needs the search
+    assert np.diff(g3.in_offsets)[5] != np.diff(g1.in_offsets)[5]
+    gr = gg.relabel(g3, np.random.default_rng(24).permutation(g3.n))
+    br = gg.random_batch(gr, 40, seed=25)
+    gr1 = gg.apply_batch(gr, br)
+    gs = gg.rmat_graph(12, 12, seed=26)
+    bs = gg.random_batch(gs, 30, seed=27)
+    gs1 = gg.apply_batch(gs, bs)
+    prev_s = oracle.static(gs.n, *gs.edges()).ranks
+    # the rebuild rule: misses summed since the build <= 1/8 of its edges
+    assert (row_aligned_misses(g1, g2) + row_aligned_misses(g2, g3)) * 8 <= g1.m
+    assert row_aligned_misses(g3, gr1) * 8 > g1.m
+
+    def run_chain(keep):
+        prhip.set_tuning()
+        prhip.set_tuning(**tuning, chain_numbering=keep)
+        outs, prev = [], prev0
+        steps = [(g1, b1), (g2, b2), (g3, b3), (gr1, br), (g3, b3), (gs1, bs)]
+        for k, (g, b) in enumerate(steps):
+            p = prev_s if g is gs1 else prev
+            r, res = gpu_dfp(g, b, p, mode=mode)
+            outs.append((r, res.iterations, prhip.last_stats()["numbering"]))
+            if k < 2:
+                prev = r  # R^t of the chain
+        return outs
+
+    fresh = run_chain(0)   # also releases anything kept by earlier tests
+    kept = run_chain(1)
+    for k, ((rf, itf, nf), (rk, itk, nk)) in enumerate(zip(fresh, kept)):
+        assert nf == 1, k
+        assert itf == itk and np.array_equal(rf, rk), k
+    assert [o[2] for o in kept] == [1, 2, 2, 2, 1, 1]
+    # the chain's first step against the oracle
+    o = oracle.dfp(g1.n, *g1.edges(), b1, prev0, prune=(mode == "dfp")) if mode != "dt" \
+        else oracle.dt(g1.n, *g1.edges(), b1, prev0)
+    assert np.abs(kept[0][0] - o.ranks).max() <= 1e-9
