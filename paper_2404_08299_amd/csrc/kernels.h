@@ -78,7 +78,9 @@ enum CountSlot {
   kTileQueue = 12, // slots 12 .. 19: per-die work queues of the Static and batched
                    // rank updates (tiles) and of the PPR update (runs of rows)
   kMapMiss = 20,   // entries a mapping from a kept mapping did not find there
-  kNumCounts = 21
+  kCands = 21,     // per iteration parity p: slot 21 + p the size of the list of
+                   // frontier vertices in the out-degree wavefront class
+  kNumCounts = 23
 };
 
 // Streamed data (CSR arrays, a vertex's own rank, new ranks) is read and
@@ -979,25 +981,47 @@ __global__ __launch_bounds__(kBlock) void k_dfp_init(int n, const int *__restric
 
 // initialAffected (Alg. 5): deletion (u, v) sets dN[u] and dV[v]; insertion
 // (u, .) sets dN[u]. Out-of-range IDs are skipped and reported in ctrl->err.
+// cand (may be null): the sources in the out-degree wavefront class
+// (t_exp < |out| <= wmax) are listed for the initial expansion, as
+// k_expand_cands lists the later frontiers (a source of several batch edges
+// may appear more than once; marking twice changes nothing).
 __global__ __launch_bounds__(kBlock) void k_mark_initial(const int *__restrict__ del_src,
                                                          const int *__restrict__ del_dst, int nd,
                                                          const int *__restrict__ ins_src, int ni,
                                                          int n, uint8_t *dV, uint8_t *dN,
-                                                         Ctrl *ctrl) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
+                                                         const int *__restrict__ out_off,
+                                                         int t_exp, int wmax,
+                                                         int *__restrict__ cand,
+                                                         int *__restrict__ ccount, Ctrl *ctrl) {
+  const int i = blockIdx.x * kBlock + threadIdx.x, lane = threadIdx.x & (kWave - 1);
+  int u = -1;  // the frontier vertex this thread sets
   if (i < nd) {
-    const int u = del_src[i], v = del_dst[i];
-    if (u >= 0 && u < n && v >= 0 && v < n) {
-      dN[u] = 1;
+    const int s = del_src[i], v = del_dst[i];
+    if (s >= 0 && s < n && v >= 0 && v < n) {
+      u = s;
       dV[v] = 1;
     } else {
       ctrl->err = 1;
     }
   } else if (i < nd + ni) {
-    const int u = ins_src[i - nd];
-    if (u >= 0 && u < n) dN[u] = 1;
+    const int s = ins_src[i - nd];
+    if (s >= 0 && s < n) u = s;
     else ctrl->err = 1;
   }
+  if (u >= 0) dN[u] = 1;
+  if (!cand) return;
+  bool c = false;
+  if (u >= 0) {
+    const int d = out_off[u + 1] - out_off[u];
+    c = d > t_exp && d <= wmax;
+  }
+  const unsigned long long mask = __ballot(c);
+  if (!mask) return;
+  int base = 0;
+  if (lane == 0) base = atomicAdd(ccount, __popcll(mask));
+  base = __shfl(base, 0);
+  const int at = base + __popcll(mask & ((1ull << lane) - 1));
+  if (c && at < n) cand[at] = u;  // a longer list (count > n) is not used
 }
 
 // markNeighbors (Alg. 5) for one target: a store of 1, skipped when the flag
@@ -1088,13 +1112,64 @@ __global__ __launch_bounds__(kBlock) void k_compact_affected(const uint8_t *__re
   }
 }
 
+// The frontier's vertices of the out-degree wavefront class (t_exp < |out| <=
+// wmax), listed for expandAffected of iteration `it` from that iteration's
+// affected list, which holds every vertex with dN set. Workgroup b owns a
+// contiguous run of rounds of kCandRun list entries (16 per thread, strided
+// by the workgroup) and reserves each round's slots with one atomic add.
+// Skipped when the marking will not push (converged, or the frontier is
+// pulled). The other parity's count is cleared for the next iteration.
+constexpr int kCandPer = 16;
+constexpr int kCandRun = kBlock * kCandPer;
+__global__ __launch_bounds__(kBlock) void k_expand_cands(
+    const int *__restrict__ alist, const int *__restrict__ acount, const uint8_t *__restrict__ dN,
+    const int *__restrict__ out_off, int t_exp, int wmax, long long pull_thresh,
+    int *__restrict__ cand, int *__restrict__ ccount, int *__restrict__ cnext,
+    const Ctrl *__restrict__ ctrl, int it) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *cnext = 0;
+  if (ctrl->done || (pull_thresh >= 0 && ctrl->aux[2 + (it & 1)] > pull_thresh)) return;
+  __shared__ int s_base;
+  const int L = *acount, tid = threadIdx.x;
+  const long long rounds = ((long long)L + kCandRun - 1) / kCandRun;
+  const long long per = (rounds + gridDim.x - 1) / gridDim.x;
+  const long long q0 = (long long)blockIdx.x * per, q1 = min(rounds, q0 + per);
+  for (long long q = q0; q < q1; ++q) {
+    int vv[kCandPer];
+    uint32_t keep = 0;
+#pragma unroll
+    for (int k = 0; k < kCandPer; ++k) {
+      const long long i = q * kCandRun + k * kBlock + tid;
+      vv[k] = 0;
+      if (i < L) {
+        const int v = alist[i];
+        vv[k] = v;
+        if (dN[v]) {
+          const int d = out_off[v + 1] - out_off[v];
+          if (d > t_exp && d <= wmax) keep |= 1u << k;
+        }
+      }
+    }
+    int total;
+    int at = block_exclusive_scan<kBlock>(__popc(keep), &total);
+    if (tid == 0) s_base = total ? atomicAdd(ccount, total) : 0;
+    __syncthreads();
+    at += s_base;
+#pragma unroll
+    for (int k = 0; k < kCandPer; ++k)
+      if ((keep >> k) & 1u) cand[at++] = vv[k];
+    __syncthreads();  // s_base is rewritten by the next round
+  }
+}
+
 // After the convergence check of iteration `it`: copy the new ranks of the
 // vertices updated in it, with their contributions (the swap of Alg. 2;
 // vertices not updated keep their rank), then, unless it converged, expandAffected (Alg. 5): every u
 // with dN[u] marks out(u) in dV. Out-degree classes as for the rank update:
 // lane per vertex over ID tiles, a wavefront per vertex, or one workgroup per
 // chunk of out-edges. dV stores are all 1s (benign races, no atomics).
-// it = -1 is the initial expansion.
+// it = -1 is the initial expansion. cand (with ccount): the wavefront-class
+// vertices of the frontier (k_expand_cands, k_mark_initial), else, or when
+// the count exceeds n, every wavefront-class vertex is checked.
 __global__ __launch_bounds__(kBlock) void k_apply_expand(
     const int *__restrict__ out_off, const int *__restrict__ out_tgt, const int *__restrict__ pos,
     double *__restrict__ R, double *__restrict__ X, const double *__restrict__ T, uint8_t *dV,
@@ -1103,6 +1178,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_expand(
     const int *__restrict__ hub_start, const int *__restrict__ chunk_hub, int CH, int n,
     int t_exp, const int *__restrict__ rt, long long pull_thresh, int do_mark,
     const int *__restrict__ alist, const int *__restrict__ acount,
+    const int *__restrict__ cand, const int *__restrict__ ccount,
     const Ctrl *__restrict__ ctrl, int it) {
   const int done = ctrl->done;
   if (done && ctrl->iters < it + 1) return;  // converged before this iteration
@@ -1119,8 +1195,11 @@ __global__ __launch_bounds__(kBlock) void k_apply_expand(
     // x mark only targets in [rt[x], rt[x+1]), found by binary search in the
     // ascending out-row, so the flags they read and write stay in that die's
     // L2. Candidates: the wavefront-class rows, then the split-class chunks.
+    // wavefront-class candidates [0, nw), then split-class chunks
     const int n1 = counts[kOutWave], nch = counts[kOutChunks];
-    const long long ncand = (long long)n1 + nch;
+    const bool listed = cand && *ccount <= n;
+    const int nw = listed ? *ccount : n1;
+    const long long ncand = (long long)nw + nch;
     const int x0 = B >= kXcds ? (int)blockIdx.x % kXcds : (int)blockIdx.x;
     const int xstep = B >= kXcds ? kXcds : B;
     const int loc = B >= kXcds ? (int)blockIdx.x / kXcds : 0;
@@ -1133,13 +1212,13 @@ __global__ __launch_bounds__(kBlock) void k_apply_expand(
         const long long ii = gwx + (k0 + lane) * Wx;
         bool f = false;
         int a = 0, b = 0;
-        if (ii < n1) {
-          const int u = hi_out[ii];
-          f = dN[u] != 0;
+        if (ii < nw) {
+          const int u = listed ? cand[ii] : hi_out[ii];
+          f = listed || dN[u] != 0;
           a = out_off[u];
           b = out_off[u + 1];
         } else if (ii < ncand) {
-          const int c = (int)(ii - n1);
+          const int c = (int)(ii - nw);
           const int i = chunk_hub[c];
           const int u = hi_out[n1 + i];
           f = dN[u] != 0;
@@ -1193,15 +1272,17 @@ __global__ __launch_bounds__(kBlock) void k_apply_expand(
     __syncthreads();
     }
     // wavefront class
+    const bool listed = cand && *ccount <= n;
+    const int nw = listed ? *ccount : n1;
     const int W = B * kWavesPerBlock;
     const int gw = blockIdx.x * kWavesPerBlock + wid;
-    for (long long k0 = 0; gw + k0 * W < n1; k0 += kWave) {
+    for (long long k0 = 0; gw + k0 * W < nw; k0 += kWave) {
       const long long ii = gw + (k0 + lane) * W;
       int u = -1;
       bool g = false;
-      if (ii < n1) {
-        u = hi_out[ii];
-        g = dN[u] != 0;
+      if (ii < nw) {
+        u = listed ? cand[ii] : hi_out[ii];
+        g = listed || dN[u] != 0;
       }
       unsigned long long mask = __ballot(g);
       while (mask) {

@@ -73,7 +73,8 @@ struct Workspace {
   double *hub_part = nullptr;                             // [cap_chunks]
   double *w_out = nullptr;     // [m] edge weights in out-CSR order (adjoint)
   size_t cap_w_out = 0;
-  int *alist = nullptr;        // [2][n] affected lists of DF/DF-P/DT (by iteration parity)
+  int *alist = nullptr;        // [3][n] affected lists of DF/DF-P/DT (by iteration parity),
+                               // then the frontier's wavefront-class vertices
   int *newid = nullptr;        // [n] gather-side numbering
   int *src_p = nullptr;        // [m] in-CSR sources in that numbering
   // DF/DF-P/DT chains (tuning chain_numbering): the numbering of such calls,
@@ -336,7 +337,7 @@ int get_ws(size_t n, size_t m, int CH, int B, Workspace **out) {
         (e = hipMalloc(&w.hub_part, nc * sizeof(double))) != hipSuccess ||
         (e = hipMalloc(&w.tile_counts, (size_t)kGroups * nt * sizeof(int) + 64)) != hipSuccess ||
         (e = hipMalloc(&w.newid, nn * sizeof(int))) != hipSuccess ||
-        (e = hipMalloc(&w.alist, 2 * nn * sizeof(int))) != hipSuccess ||
+        (e = hipMalloc(&w.alist, 3 * nn * sizeof(int))) != hipSuccess ||
         (e = hipMalloc(&w.src_p, mm * sizeof(int))) != hipSuccess ||
         (e = hipMalloc(&w.partials, np * sizeof(double))) != hipSuccess) {
       (void)hipGetLastError();
@@ -899,6 +900,8 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
   int *alist[2] = {w.alist, w.alist + (size_t)n};
   // per parity: {list size, tile queue of the rank update}
   int *acnt[2] = {w.counts + kAffList, w.counts + kAffList + 2};
+  // the frontier's wavefront-class vertices and their count per parity
+  int *cand = w.alist + 2 * (size_t)n, *ccnt = w.counts + kCands;
   const int np = B + kHubFinalizeBlocks;
   CallTimer timer(w, s);
   const size_t fs = flag_stride((size_t)n);  // each flag array 256-byte aligned
@@ -906,6 +909,7 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
   double *R = ranks_out;
   const int t1 = tn.lane_max_degree, t_exp = tn.expand_lane_max_degree, CH = tn.hub_chunk_edges;
   hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, s, w.ctrl);
+  if (use_list) HIP_TRY(hipMemsetAsync(ccnt, 0, 2 * sizeof(int), s));
   const bool xs = xsplit_min_degree(tn) > 0;
   if (xs && (rc = xcd_ranges(w, g->out_offsets, n, s))) return rc;
   if (xs) {
@@ -941,7 +945,8 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
   if (nd + ni > 0) {
     hipLaunchKernelGGL(k_mark_initial, dim3((nd + ni + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
                        del ? del->src : nullptr, del ? del->dst : nullptr, nd,
-                       ins ? ins->src : nullptr, ni, n, dV, dN, w.ctrl);
+                       ins ? ins->src : nullptr, ni, n, dV, dN, g->out_offsets, t_exp,
+                       tn.wave_max_degree, use_list ? cand : nullptr, ccnt + 1, w.ctrl);
     LAUNCH_TRY();
   }
   // frontier size above which expandAffected pulls (-1: always push)
@@ -971,6 +976,16 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
                          xp.off, (const uint32_t *)w.fbits, dV, n, t1, pull_thresh,
                          (uint8_t *)nullptr, (int *)nullptr, (const Ctrl *)w.ctrl, it);
     }
+    // with the list, the frontier's wavefront-class vertices are listed
+    // first (for the initial expansion by k_mark_initial, in parity 1), so
+    // the marking does not check the whole class
+    const bool cands = use_list && mark;
+    if (lst && mark)
+      hipLaunchKernelGGL(k_expand_cands, dim3(cgrid_list), dim3(kBlock), 0, s,
+                         (const int *)alist[it & 1], (const int *)acnt[it & 1],
+                         (const uint8_t *)dN, g->out_offsets, t_exp, tn.wave_max_degree,
+                         pull_thresh, cand, ccnt + (it & 1), ccnt + ((it + 1) & 1),
+                         (const Ctrl *)w.ctrl, it);
     hipLaunchKernelGGL(k_apply_expand, dim3(B), dim3(kBlock), 0, s, g->out_offsets,
                        g->out_targets, loc.pos, R, X, (const double *)w.T, dV,
                        (const uint8_t *)dN, cv,
@@ -978,7 +993,9 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
                        (const int *)w.hub_start_out, (const int *)w.chunk_hub_out, CH, n, t_exp,
                        xs ? (const int *)w.xrt : nullptr, pull_thresh, mark ? 1 : 0,
                        lst ? (const int *)alist[it & 1] : nullptr,
-                       lst ? (const int *)acnt[it & 1] : nullptr, (const Ctrl *)w.ctrl, it);
+                       lst ? (const int *)acnt[it & 1] : nullptr,
+                       cands ? (const int *)cand : nullptr,
+                       cands ? (const int *)ccnt + (it & 1) : nullptr, (const Ctrl *)w.ctrl, it);
     if (use_list) compact(it);
   };
   // initial expandAffected (Alg. 2, after initialAffected)

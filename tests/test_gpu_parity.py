@@ -477,3 +477,31 @@ def test_chain_numbering_same_bits(mode, tuning):
     o = oracle.dfp(g1.n, *g1.edges(), b1, prev0, prune=(mode == "dfp")) if mode != "dt" \
         else oracle.dt(g1.n, *g1.edges(), b1, prev0)
     assert np.abs(kept[0][0] - o.ranks).max() <= 1e-9
+
+
+@pytest.mark.parametrize("mode", ["dfp", "df", "dt"])
+@pytest.mark.parametrize("tuning", [dict(expand_lane_max_degree=2),
+                                    dict(expand_lane_max_degree=2, xcd_split_degree=0)])
+def test_initial_frontier_list_overflow(mode, tuning):
+    """A batch of more updates than vertices: the initial frontier's list (an
+    entry per batch edge whose source is in the out-degree wavefront class)
+    would hold more than n entries, so the initial marking checks the whole
+    class instead. Same bits and iterations as the ID-tile sweeps, and the
+    oracle's ranks."""
+    g0 = gg.rmat_graph(6, 12, seed=41)  # n = 64
+    b = gg.random_batch(g0, 200, seed=42)
+    g1 = gg.apply_batch(g0, b)
+    prev = oracle.static(g0.n, *g0.edges()).ranks
+    deg = np.diff(g1.out_offsets)
+    src = np.concatenate([b.del_src, b.ins_src])
+    assert ((deg[src] > 2) & (deg[src] <= 4096)).sum() > g1.n
+    outs = []
+    for fl in (0, 1):
+        prhip.set_tuning()
+        prhip.set_tuning(**tuning, frontier_list=fl)
+        r, res = gpu_dfp(g1, b, prev, mode=mode)
+        outs.append((r, res.iterations))
+    assert outs[0][1] == outs[1][1] and np.array_equal(outs[0][0], outs[1][0])
+    o = oracle.dt(g1.n, *g1.edges(), b, prev) if mode == "dt" else \
+        oracle.dfp(g1.n, *g1.edges(), b, prev, prune=(mode == "dfp"))
+    assert np.abs(outs[1][0] - o.ranks).max() <= 1e-9
