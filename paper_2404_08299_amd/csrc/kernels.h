@@ -1321,12 +1321,15 @@ __global__ __launch_bounds__(kBlock) void k_apply_expand(
 // ------------------------------------------------------------ pull expansion
 // The frontier of iteration `it` as a bitmap, bit v of fb[v / 32] = dN[v]
 // (dN bytes are 0 or 1), and its size added to ctrl->aux[2 + (it & 1)]; the
-// other counter is cleared for the next iteration.
+// other counter is cleared for the next iteration. gate >= 0: the size is
+// already counted (k_frontier_count), and the bitmap is only built when the
+// frontier is larger than gate (when the marking pulls).
 __global__ __launch_bounds__(kBlock) void k_frontier(const uint8_t *__restrict__ dN, int n,
                                                      uint32_t *__restrict__ fb, Ctrl *ctrl,
-                                                     int it) {
+                                                     int it, long long gate) {
   if (ctrl->done) return;
-  if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->aux[2 + ((it + 1) & 1)] = 0;
+  if (gate >= 0 && ctrl->aux[2 + (it & 1)] <= gate) return;
+  if (gate < 0 && blockIdx.x == 0 && threadIdx.x == 0) ctrl->aux[2 + ((it + 1) & 1)] = 0;
   const int nw = (n + 31) / 32;
   int cnt = 0;
   for (int w = blockIdx.x * kBlock + threadIdx.x; w < nw; w += gridDim.x * kBlock) {
@@ -1346,6 +1349,26 @@ __global__ __launch_bounds__(kBlock) void k_frontier(const uint8_t *__restrict__
     fb[w] = word;
     cnt += __popc(word);
   }
+  if (gate >= 0) return;
+  cnt = wave_sum_int(cnt);
+  if ((threadIdx.x & (kWave - 1)) == 0 && cnt)
+    atomicAdd((unsigned long long *)&ctrl->aux[2 + (it & 1)], (unsigned long long)cnt);
+}
+
+// The size of the frontier of iteration `it`, counted over that iteration's
+// affected list (which holds every vertex with dN set), into
+// ctrl->aux[2 + (it & 1)]; the other counter is cleared for the next
+// iteration.
+__global__ __launch_bounds__(kBlock) void k_frontier_count(const int *__restrict__ alist,
+                                                           const int *__restrict__ acount,
+                                                           const uint8_t *__restrict__ dN,
+                                                           Ctrl *ctrl, int it) {
+  if (ctrl->done) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->aux[2 + ((it + 1) & 1)] = 0;
+  const int L = *acount;
+  int cnt = 0;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < L; i += gridDim.x * kBlock)
+    cnt += dN[alist[i]] != 0;
   cnt = wave_sum_int(cnt);
   if ((threadIdx.x & (kWave - 1)) == 0 && cnt)
     atomicAdd((unsigned long long *)&ctrl->aux[2 + (it & 1)], (unsigned long long)cnt);
