@@ -320,6 +320,7 @@ typedef struct pr_tuning {
   int32_t expand_pull_per_mille;
   int32_t frontier_list;
   int32_t chain_numbering;
+  int32_t ppr_chunk_edges;
 } pr_tuning;
 
 /* frontier_list       DF/DF-P/DT: 1 = after each marking the affected set is
@@ -341,14 +342,23 @@ typedef struct pr_tuning {
  *                     releases what was kept). The same ranks either
  *                     way (bit for bit). Keeping it costs 16 m + 12 n bytes
  *                     of device memory beyond the workspace.
+ * ppr_chunk_edges     pr_ppr: a row with at most this many in-edges is
+ *                     summed whole by one wavefront (lane = vector); a longer
+ *                     row is summed in chunks of this many edges whose
+ *                     partial rows are added in chunk order, and with the
+ *                     die split on it is cut by source range first (the die
+ *                     split's threshold is then this + 1, whatever
+ *                     xcd_split_degree says beyond 0). 0 = default 256;
+ *                     16 .. 2^20.
  * Defaults: lane_max_degree 128, wave_max_degree 4096, expand_lane_max_degree
  * 32, iters_per_sync 2, hub_chunk_edges 4096, grid_blocks 0, relabel -1,
  * xcd_split_degree 129, expand_pull_per_mille 20, frontier_list 1,
- * chain_numbering 1. */
+ * chain_numbering 1, ppr_chunk_edges 256. */
 
 /* Set (NULL = defaults) or read the process-wide tuning. PR_EINVAL if a
  * field is out of range (degrees < 0, lane > wave, iters_per_sync < 1,
- * xcd_split_degree == 1, frontier_list or chain_numbering not 0 or 1). */
+ * xcd_split_degree == 1, frontier_list or chain_numbering not 0 or 1,
+ * ppr_chunk_edges not 0 or in 16 .. 2^20). */
 int pr_set_tuning(const pr_tuning *t);
 int pr_get_tuning(pr_tuning *t);
 

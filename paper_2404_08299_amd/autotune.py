@@ -38,6 +38,14 @@ DEFAULT_SPACE = {
 }
 DFP_SPACE = dict(DEFAULT_SPACE, expand_lane_max_degree=[8, 32, 128],
                  expand_pull_per_mille=[0, 5, 20, 100], frontier_list=[0, 1])
+# pr_ppr reads the row-split size, the die split on/off, the relabel switch
+# and the pipelining depth (its long rows are split at ppr_chunk_edges)
+PPR_SPACE = {
+    "ppr_chunk_edges": [64, 128, 256, 512, 1024],
+    "xcd_split_degree": [0, 129],
+    "relabel": [0, 1],
+    "iters_per_sync": [1, 2, 4],
+}
 
 CACHE_PATH = os.environ.get("PRHIP_TUNING_CACHE",
                             os.path.join(os.path.expanduser("~"), ".cache", "prhip_tuning.json"))
@@ -163,6 +171,23 @@ def tune_batched(graphs, expected_iters: int = 64, cache_path: str | None = None
 
     return _cached(f"batched{len(graphs)}", n, m,
                    lambda: coordinate_descent(run, DEFAULT_SPACE, k1=2, k2=6,
+                                              expected_iters=expected_iters, log=log),
+                   cache_path, refresh)
+
+
+def tune_ppr(g: "prhip.DeviceGraph", teleport, expected_iters: int = 64,
+             cache_path: str | None = None, refresh: bool = False, log=None) -> dict:
+    """Tune pr_ppr on graph g with the [n][k] teleport matrix (the cache key
+    includes k)."""
+    import torch
+    k = int(teleport.shape[1])
+    out = torch.empty(g.n, k, dtype=torch.float64, device=g.in_offsets.device)
+
+    def run(it):
+        prhip.ppr(g, teleport, tol=0.0, max_iter=it, out=out)
+
+    return _cached(f"ppr{k}", g.n, g.m,
+                   lambda: coordinate_descent(run, PPR_SPACE, k1=2, k2=6,
                                               expected_iters=expected_iters, log=log),
                    cache_path, refresh)
 

@@ -55,6 +55,7 @@ pr_tuning default_tuning() {
   t.expand_pull_per_mille = 20;
   t.frontier_list = 1;
   t.chain_numbering = 1;
+  t.ppr_chunk_edges = 256;
   return t;
 }
 pr_tuning g_tuning = default_tuning();
@@ -258,12 +259,11 @@ int xsplit_min_degree(const pr_tuning &tn) {
   if (tn.xcd_split_degree <= 0) return 0;
   return std::max(tn.xcd_split_degree, tn.lane_max_degree + 1);
 }
-size_t xsplit_rows_bound(size_t n, size_t m) {
-  const int T = xsplit_min_degree(g_tuning);
+size_t xsplit_rows_bound(size_t n, size_t m, int T) {
   return T ? std::min(n, m / (size_t)T) + 1 : 0;
 }
-size_t xsplit_items_bound(size_t n, size_t m, int CH) {
-  const size_t nb = xsplit_rows_bound(n, m);
+size_t xsplit_items_bound(size_t n, size_t m, int CH, int T) {
+  const size_t nb = xsplit_rows_bound(n, m, T);
   return nb ? kXcds * nb + m / (size_t)std::max(CH, 1) + kXcds : 0;
 }
 
@@ -311,7 +311,8 @@ int get_ws(size_t n, size_t m, int CH, int B, Workspace **out) {
   // chunks of the split class: sum over its vertices of ceil(deg / CH)
   // <= m / CH + (number of split vertices) <= m / CH + n; die-split rows have
   // up to kXcds segments each
-  const size_t need_chunks = std::max(m / (size_t)CH + n + 1, xsplit_items_bound(n, m, CH));
+  const size_t need_chunks =
+      std::max(m / (size_t)CH + n + 1, xsplit_items_bound(n, m, CH, xsplit_min_degree(g_tuning)));
   const size_t need_partials = (size_t)B + kHubFinalizeBlocks + 16;
   if (n > w.cap_n || m > w.cap_m || need_chunks > w.cap_chunks ||
       need_partials > w.cap_partials) {
@@ -443,7 +444,8 @@ int xcd_ranges(Workspace &w, const int *goff, int n, hipStream_t s) {
 // Degree classes of the rows `off` (Alg. 4 with three classes) and the plan of
 // the top class. With `xidx` (the rows' original, ascending indices; needs
 // the ranges in w.xrs) the top class is the die-split class of rows with
-// degree >= xsplit_min_degree; otherwise rows above t2, cut into chunks.
+// degree >= Tx (Tx = 0: max(xsplit_min_degree, t1 + 1)); otherwise rows above
+// t2, cut into chunks.
 // Exclusive scan of `nrows` rows of `rows` (row r at rows + r * stride), each
 // min(stride, *dlen) long (dlen a device count, or null), in place; totals[r]
 // gets row r's sum. Rows longer than a few thousand entries are scanned by
@@ -468,9 +470,9 @@ void scan_rows(int *rows, int nrows, int stride, int *totals, const int *dlen, i
 int partition(Workspace &w, const int *off, int n, int m, int t1, int t2, int CH, int *hi,
               int slot, int chunk_slot, int *hub_start, int *chunk_hub, hipStream_t s,
               const int *xidx = nullptr, XPlan *xp = nullptr, const int *xrs = nullptr,
-              const int *gid = nullptr) {
+              const int *gid = nullptr, int Tx = 0) {
   if (!xrs) xrs = w.xrs;
-  const int T = xidx ? std::max(xsplit_min_degree(g_tuning), t1 + 1) : 0;
+  const int T = !xidx ? 0 : Tx > 0 ? Tx : std::max(xsplit_min_degree(g_tuning), t1 + 1);
   if (T) t2 = T - 1;
   const int nt = (int)ntiles_for(n);
   hipLaunchKernelGGL(k_part_count, dim3(nt), dim3(kBlock), 0, s, off, n, t1, t2, w.tile_counts,
@@ -486,8 +488,8 @@ int partition(Workspace &w, const int *off, int n, int m, int t1, int t2, int CH
     if (xp) *xp = XPlan{};
     return PR_OK;
   }
-  const size_t nb = xsplit_rows_bound((size_t)n, (size_t)m);
-  int rc = xsplit_ws(w, nb, xsplit_items_bound((size_t)n, (size_t)m, CH));
+  const size_t nb = xsplit_rows_bound((size_t)n, (size_t)m, T);
+  int rc = xsplit_ws(w, nb, xsplit_items_bound((size_t)n, (size_t)m, CH, T));
   if (rc) return rc;
   const int gb = (int)std::min<size_t>((nb + kBlock - 1) / kBlock, 16 * std::max(1, w.num_cus));
   hipLaunchKernelGGL(k_xsplit_count, dim3(gb), dim3(kBlock), 0, s, off, xidx, (const int *)hi,
@@ -1107,11 +1109,14 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
   return t_stats.converged ? PR_OK : PR_NOT_CONVERGED;
 }
 
-constexpr int kPprChunk = 256;  // in-edges per wavefront before a row is split
+// In-edges per wavefront before a PPR row is split (tuning ppr_chunk_edges):
+// rows up to C are summed whole, longer ones in chunks of C, and with the die
+// split on every row longer than C is a die-split row.
+int ppr_chunk(const pr_tuning &tn) { return tn.ppr_chunk_edges > 0 ? tn.ppr_chunk_edges : 256; }
 
-int ppr_ws(Workspace &w, size_t n, size_t m, size_t K, size_t B) {
+int ppr_ws(Workspace &w, size_t n, size_t m, size_t K, size_t B, int C) {
   const size_t nbuf = 4 * n * K;
-  const size_t npart = std::max(m / kPprChunk + n + 1, xsplit_items_bound(n, m, kPprChunk)) * K;
+  const size_t npart = std::max(m / C + n + 1, xsplit_items_bound(n, m, C, C + 1)) * K;
   // partial maxima of the rank and finalize workgroups, then the chunk maxima
   const size_t npmax = (B + kHubFinalizeBlocks + 16 + kPprColBlocks) * K;
   if (nbuf > w.cap_ppr_buf || npart > w.cap_ppr_part || npmax > w.cap_ppr_pmax ||
@@ -1148,24 +1153,27 @@ int run_ppr(const pr_csr *g, const double *teleport, int K, double alpha, double
   const int n = g->n;
   const pr_tuning tn = g_tuning;
   Workspace *wp = nullptr;
-  int rc = get_ws((size_t)n, (size_t)g->m, kPprChunk, tn.grid_blocks, &wp);
+  const int C = ppr_chunk(tn);
+  int rc = get_ws((size_t)n, (size_t)g->m, C, tn.grid_blocks, &wp);
   if (rc) return rc;
   Workspace &w = *wp;
   const int B = grid_blocks(w, tn, k_ppr_rank);
   const int F = kHubFinalizeBlocks;
-  if ((rc = ppr_ws(w, (size_t)n, (size_t)g->m, (size_t)K, (size_t)B))) return rc;
+  if ((rc = ppr_ws(w, (size_t)n, (size_t)g->m, (size_t)K, (size_t)B, C))) return rc;
   CallTimer timer(w, s);
   const size_t nk = (size_t)n * K;
   double *Rb[2] = {w.ppr_buf, w.ppr_buf + nk};
   double *Xb[2] = {w.ppr_buf + 2 * nk, w.ppr_buf + 3 * nk};
   hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, s, w.ctrl);
-  // rows longer than kPprChunk form the split class (class 1 of Alg. 4
-  // empty), cut by source range as well when the die split is on
+  // rows longer than C form the split class (class 1 of Alg. 4 empty), cut
+  // by source range as well when the die split is on: its threshold is C + 1
+  // here, whatever the tuning's, so that every split row is in the plan
   const bool xs = xsplit_min_degree(tn) > 0;
   if (xs && (rc = xcd_ranges(w, g->out_offsets, n, s))) return rc;
   XPlan xp;
-  rc = partition(w, g->in_offsets, n, g->m, kPprChunk, kPprChunk, kPprChunk, w.hi_in, kInWave,
-                 kInChunks, w.hub_start_in, w.chunk_hub_in, s, xs ? g->in_sources : nullptr, &xp);
+  rc = partition(w, g->in_offsets, n, g->m, C, C, C, w.hi_in, kInWave, kInChunks,
+                 w.hub_start_in, w.chunk_hub_in, s, xs ? g->in_sources : nullptr, &xp, nullptr,
+                 nullptr, C + 1);
   if (rc) return rc;
   Locality loc;
   if ((rc = locality(w, n, g->m, g->out_offsets, g->in_sources, tn, true, s, &loc,
@@ -1176,7 +1184,7 @@ int run_ppr(const pr_csr *g, const double *teleport, int K, double alpha, double
   hipLaunchKernelGGL(k_ppr_init, dim3(ib), dim3(kBlock), 0, s, n, K, g->out_offsets, loc.pos,
                      Rb[0], Xb[0], w.ppr_vdone, w.ppr_viters, rq);
   hipLaunchKernelGGL(k_split_flags, dim3(std::min(B, (n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                     s, g->in_offsets, n, kPprChunk, w.ppr_split);
+                     s, g->in_offsets, n, C, w.ppr_split);
   uint8_t *tnz = w.ppr_split + w.cap_ppr_n;
   hipLaunchKernelGGL(k_tele_flags, dim3(std::min((n + kWavesPerBlock - 1) / kWavesPerBlock, 65536)),
                      dim3(kBlock), 0, s, teleport, n, K, tnz);
@@ -1187,7 +1195,7 @@ int run_ppr(const pr_csr *g, const double *teleport, int K, double alpha, double
     hipLaunchKernelGGL(k_ppr_rank, dim3(B), dim3(kBlock), shm, s, g->in_offsets, loc.src,
                        g->out_offsets, loc.pos, (const int *)w.hi_in, (const int *)w.counts,
                        (const int *)w.hub_start_in, (const int *)w.chunk_hub_in,
-                       (const uint8_t *)w.ppr_split, kPprChunk, n, K, (const double *)Xb[a],
+                       (const uint8_t *)w.ppr_split, C, n, K, (const double *)Xb[a],
                        (const double *)Rb[a], Rb[b], Xb[b], teleport, (const uint8_t *)tnz,
                        w.ppr_part, (const int *)w.ppr_vdone, alpha, w.ppr_pmax, xp.items, xp.off,
                        rq, (const Ctrl *)w.ctrl);
@@ -1934,10 +1942,12 @@ int pr_set_tuning(const pr_tuning *t) {
       t->grid_blocks < 0 || t->grid_blocks > (1 << 20) || t->relabel < -1 || t->relabel > 1 ||
       t->xcd_split_degree < 0 || t->xcd_split_degree == 1 || t->expand_pull_per_mille < 0 ||
       t->expand_pull_per_mille > 1000 || t->frontier_list < 0 || t->frontier_list > 1 ||
-      t->chain_numbering < 0 || t->chain_numbering > 1)
+      t->chain_numbering < 0 || t->chain_numbering > 1 || t->ppr_chunk_edges < 0 ||
+      (t->ppr_chunk_edges > 0 && t->ppr_chunk_edges < 16) || t->ppr_chunk_edges > (1 << 20))
     return fail(PR_EINVAL, "tuning field out of range");
   g_tuning = *t;
   if (g_tuning.hub_chunk_edges == 0) g_tuning.hub_chunk_edges = 4096;
+  if (g_tuning.ppr_chunk_edges == 0) g_tuning.ppr_chunk_edges = 256;
   return PR_OK;
 }
 

@@ -52,12 +52,13 @@ class PrTuning(ctypes.Structure):
                 ("hub_chunk_edges", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
                 ("relabel", ctypes.c_int32), ("xcd_split_degree", ctypes.c_int32),
                 ("expand_pull_per_mille", ctypes.c_int32), ("frontier_list", ctypes.c_int32),
-                ("chain_numbering", ctypes.c_int32)]
+                ("chain_numbering", ctypes.c_int32), ("ppr_chunk_edges", ctypes.c_int32)]
 
 
 TUNING_FIELDS = ("lane_max_degree", "wave_max_degree", "expand_lane_max_degree",
                  "iters_per_sync", "hub_chunk_edges", "grid_blocks", "relabel",
-                 "xcd_split_degree", "expand_pull_per_mille", "frontier_list", "chain_numbering")
+                 "xcd_split_degree", "expand_pull_per_mille", "frontier_list", "chain_numbering",
+                 "ppr_chunk_edges")
 
 
 class PrStats(ctypes.Structure):

@@ -43,7 +43,7 @@ def test_status_codes_match_header():
 def test_struct_layouts():
     assert ctypes.sizeof(prhip.PrCsr) == 8 + 4 * 8
     assert ctypes.sizeof(prhip.PrEdges) == 24
-    assert ctypes.sizeof(prhip.PrTuning) == 11 * 4
+    assert ctypes.sizeof(prhip.PrTuning) == 12 * 4
     # the binding's tuning fields are the header's, in order
     text = open(os.path.join(ROOT, "include", "prhip.h")).read()
     body = re.search(r"typedef struct pr_tuning \{(.*?)\} pr_tuning;", text, re.S).group(1)
@@ -107,7 +107,12 @@ def test_tuning_validation(lib):
                 prhip.PrTuning(1, 5, 3, 1, 64, 0, 0, -1),  # die-split degree < 0
                 prhip.PrTuning(1, 5, 3, 1, 64, 0, 0, 1),   # die-split degree 1
                 prhip.PrTuning(1, 5, 3, 1, 64, 0, 0, 0, -1),   # pull threshold < 0
-                prhip.PrTuning(1, 5, 3, 1, 64, 0, 0, 0, 1001)]:  # pull threshold > 1000
+                prhip.PrTuning(1, 5, 3, 1, 64, 0, 0, 0, 1001),   # pull threshold > 1000
+                prhip.PrTuning(1, 5, 3, 1, 64, 0, 0, 0, 0, 2),   # frontier_list not 0/1
+                prhip.PrTuning(1, 5, 3, 1, 64, 0, 0, 0, 0, 1, 2),  # chain_numbering not 0/1
+                prhip.PrTuning(1, 5, 3, 1, 64, 0, 0, 0, 0, 1, 1, 8),  # PPR chunk < 16
+                prhip.PrTuning(1, 5, 3, 1, 64, 0, 0, 0, 0, 1, 1, (1 << 20) + 1),
+                prhip.PrTuning(1, 5, 3, 1, 64, 0, 0, 0, 0, 1, 1, -1)]:
         assert lib.pr_set_tuning(ctypes.byref(bad)) == prhip.PR_EINVAL
     assert default["xcd_split_degree"] == 129 and default["expand_pull_per_mille"] == 20
     good = prhip.PrTuning(4, 64, 8, 3, 0, 100, 1, 2)
@@ -115,6 +120,10 @@ def test_tuning_validation(lib):
     got = prhip.get_tuning()
     assert got["wave_max_degree"] == 64 and got["hub_chunk_edges"] == 4096 and got["grid_blocks"] == 100
     assert got["xcd_split_degree"] == 2
+    assert got["ppr_chunk_edges"] == 256 and default["ppr_chunk_edges"] == 256  # 0: default
+    assert default["chain_numbering"] == 1 and default["frontier_list"] == 1
+    prhip.set_tuning(ppr_chunk_edges=16)
+    assert prhip.get_tuning()["ppr_chunk_edges"] == 16
     prhip.set_tuning(hub_chunk_edges=128)
     assert prhip.get_tuning()["hub_chunk_edges"] == 128
     with pytest.raises(KeyError):

@@ -87,3 +87,34 @@ def test_tuned_static_same_ranks(tmp_path):
     assert prhip.get_tuning() == best
     got = prhip.static(dg, tol=1e-13, max_iter=1000).ranks
     assert float((got - ref).abs().max()) <= 1e-13
+
+
+def test_ppr_space_is_valid():
+    """Every value of the PPR search space is a tuning the library accepts,
+    and the space's fields are tuning fields."""
+    for field, values in autotune.PPR_SPACE.items():
+        assert field in prhip.TUNING_FIELDS
+        for v in values:
+            prhip.set_tuning(**{field: v})
+            assert prhip.get_tuning()[field] == v
+            prhip.set_tuning()
+
+
+@pytest.mark.gpu
+def test_tuned_ppr_same_ranks(tmp_path):
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2404_08299_amd import graphgen as gg
+    g = gg.rmat_graph(13, 8, seed=2)
+    dg = prhip.DeviceGraph.from_host(g)
+    sets = gg.distinct_vertices(g.n, 8, 16, seed=3)
+    T = np.zeros((g.n, 8))
+    for j in range(8):
+        T[sets[j], j] = 1.0 / 16
+    Td = torch.from_numpy(T).cuda()
+    ref = prhip.ppr(dg, Td, tol=1e-13, max_iter=1000)[0].ranks.clone()
+    best = autotune.tune_ppr(dg, Td, cache_path=str(tmp_path / "t.json"))
+    assert prhip.get_tuning() == best
+    got = prhip.ppr(dg, Td, tol=1e-13, max_iter=1000)[0].ranks
+    assert float((got - ref).abs().max()) <= 1e-13

@@ -90,3 +90,30 @@ def test_ppr_max_iter():
     assert res.status == prhip.PR_NOT_CONVERGED and list(its) == [3] * 4
     Ro, _ = oracle.ppr(g.n, *g.edges(), T, tol=0.0, max_iter=3)
     assert np.abs(res.ranks.cpu().numpy() - Ro).max() <= 1e-15
+
+
+@pytest.mark.parametrize("tuning", [dict(ppr_chunk_edges=16), dict(ppr_chunk_edges=64),
+                                    dict(ppr_chunk_edges=1024, grid_blocks=13),
+                                    dict(ppr_chunk_edges=64, xcd_split_degree=0),
+                                    # a die-split threshold above the chunk size and a lane
+                                    # class above it: PPR still splits every row longer than
+                                    # the chunk, by source range
+                                    dict(xcd_split_degree=1000),
+                                    dict(lane_max_degree=512, relabel=1)])
+def test_ppr_chunk_sizes(tuning):
+    """Rows split at the tuned chunk size (ppr_chunk_edges), with and without
+    the die split, on R-MAT plus an in-star hub of in-degree 3000: the
+    oracle's ranks, and the vectors stop in the oracle's iteration."""
+    prhip.set_tuning(**tuning)
+    base = gg.rmat_graph(12, 16, seed=5)
+    s0, d0 = base.edges()
+    hub = np.random.default_rng(5).choice(base.n, 3000, replace=False).astype(np.int32)
+    g = gg.from_edges(base.n, np.concatenate([s0, hub]),
+                      np.concatenate([d0, np.full(hub.size, 7, np.int32)]))
+    deg = np.diff(g.in_offsets)
+    assert ((deg > 256) & (deg < 1000)).any() and deg.max() >= 3000
+    T = teleports(g.n, 24, 16, seed=3)
+    res, its = prhip.ppr(prhip.DeviceGraph.from_host(g), torch.from_numpy(T).cuda())
+    Ro, ito = oracle.ppr(g.n, *g.edges(), T)
+    assert np.abs(res.ranks.cpu().numpy() - Ro).max() <= 1e-9
+    assert np.abs(np.asarray(its) - np.asarray(ito)).max() <= 1
