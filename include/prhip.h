@@ -245,8 +245,8 @@ typedef struct pr_csr_out {
  * The batch must be normalised (the set differences): a repeated pair, a
  * deletion that is absent or an insertion that is present returns
  * PR_EBATCH (out then holds unspecified values; nothing is written outside
- * its arrays). Uses rocPRIM's radix sort for the batch keys and allocates
- * stream-ordered scratch.
+ * its arrays). Sorts the batch keys on the device (its own radix sort) and
+ * allocates stream-ordered scratch.
  */
 int pr_apply_batch(const pr_csr *old, const pr_edges *deletions, const pr_edges *insertions,
                    const pr_csr_out *out);

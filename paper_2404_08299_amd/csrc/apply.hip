@@ -5,7 +5,8 @@
 // reverse). Rows stay ascending.
 //
 //  1. keys (row << 32 | col) of the deletions and of the insertions, sorted
-//     (rocPRIM radix sort), duplicates rejected;
+//     (least-significant-digit radix sort over the bits IDs below n can set),
+//     duplicates rejected;
 //  2. per-row change counts, new degrees, new offsets (multi-workgroup scan);
 //  3. one pass over the rows: a wavefront owns 64 consecutive rows; it copies
 //     their unchanged short rows edge-parallel, laid end to end, then handles
@@ -14,8 +15,6 @@
 //     over the row's (sorted) deletions and insertions. A deletion that is
 //     not in the row or an insertion that already is raises the error flag.
 #include <hip/hip_runtime.h>
-#include <rocprim/device/device_radix_sort.hpp>
-
 #include <cstdint>
 
 #include "apply.h"
@@ -45,6 +44,223 @@ __global__ __launch_bounds__(kBlock) void k_keys(const int *__restrict__ row, co
       keys[i] = key_of(r, c);
     }
   }
+}
+
+// ------------------------------------------------------------ radix sort
+// Keys are sorted by 8-bit digits, least significant first, and only the
+// digits that IDs below n can set (a row or column ID of b bits leaves the
+// others 0). Each pass is a stable counting sort. A list of at most
+// kRsSmall keys is sorted by one workgroup in one launch, the keys held in
+// registers and moved through LDS. A longer one takes three launches per
+// pass: per-tile digit histograms (tiles of kRsTile keys, stored tile-major),
+// a scan of each digit's column over the tiles (one workgroup per digit),
+// and a scatter: digit d of tile t starts where all smaller digits, and
+// digit d of the earlier tiles, end (each scatter workgroup scans the 256
+// digit totals itself).
+// Either way a key's place within its tile is its rank among the tile's keys
+// with the same digit, in input order: rounds of kBlock keys in order; in a
+// round the lanes of a wavefront with the same digit are found with eight
+// ballots, and the wavefronts before it and the rounds before add their
+// counts, kept per digit in LDS.
+constexpr int kRsBins = 256;
+constexpr int kRsPer = 4;                 // keys per thread in a tile of the long path
+constexpr int kRsTile = kBlock * kRsPer;
+constexpr int kRsSmallPer = 16;           // keys per thread on the one-workgroup path
+constexpr int kRsSmall = kBlock * kRsSmallPer;
+constexpr int kRsWaves = kBlock / kWave;
+static_assert(kRsBins == kBlock, "one digit per thread");
+
+__device__ __forceinline__ int rs_digit(u64 k, int sh) { return (int)((k >> sh) & 0xFFu); }
+
+// Place of this thread's key (digit d; valid = it exists) in a round: the
+// count of the digit before the round (s_run[d]) plus its rank in the
+// round. s_w must be zero on entry; on return s_run holds the counts after
+// the round and s_w is zero again.
+__device__ __forceinline__ int rs_rank(bool valid, int d, int *s_run, int (*s_w)[kRsBins]) {
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+  unsigned long long same = __ballot(valid);
+#pragma unroll
+  for (int bit = 0; bit < 8; ++bit) {
+    const bool on = (d >> bit) & 1;
+    const unsigned long long bb = __ballot(valid && on);
+    same &= on ? bb : ~bb;
+  }
+  const int r = __popcll(same & ((1ull << lane) - 1));
+  if (valid && r == 0) s_w[w][d] = __popcll(same);
+  __syncthreads();
+  int pos = 0;
+  if (valid) {
+    pos = s_run[d] + r;
+    for (int j = 0; j < w; ++j) pos += s_w[j][d];
+  }
+  __syncthreads();
+  int add = 0;
+#pragma unroll
+  for (int j = 0; j < kRsWaves; ++j) {
+    add += s_w[j][tid];
+    s_w[j][tid] = 0;
+  }
+  s_run[tid] += add;
+  __syncthreads();
+  return pos;
+}
+
+// one workgroup sorts keys[0 .. cnt), cnt <= kRsSmall, in place
+__global__ __launch_bounds__(kBlock) void k_rs_small(u64 *__restrict__ keys, int cnt, int b) {
+  __shared__ u64 buf[kRsSmall];
+  __shared__ int s_run[kRsBins];
+  __shared__ int s_w[kRsWaves][kRsBins];
+  const int tid = threadIdx.x;
+  u64 v[kRsSmallPer];
+#pragma unroll
+  for (int k = 0; k < kRsSmallPer; ++k) {
+    const int i = k * kBlock + tid;
+    v[k] = i < cnt ? keys[i] : 0;
+  }
+  for (int j = 0; j < kRsWaves; ++j) s_w[j][tid] = 0;
+  for (int half = 0; half < 2; ++half)
+    for (int lo = 0; lo < b; lo += 8) {
+      const int sh = 32 * half + lo;
+      s_run[tid] = 0;
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < kRsSmallPer; ++k)
+        if (k * kBlock + tid < cnt) atomicAdd(&s_run[rs_digit(v[k], sh)], 1);
+      __syncthreads();
+      if (tid == 0) {  // exclusive scan over the digits
+        int run = 0;
+        for (int d = 0; d < kRsBins; ++d) {
+          const int x = s_run[d];
+          s_run[d] = run;
+          run += x;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < kRsSmallPer; ++k) {
+        if (k * kBlock >= cnt) break;  // rounds past the keys (uniform)
+        const bool valid = k * kBlock + tid < cnt;
+        const int pos = rs_rank(valid, rs_digit(v[k], sh), s_run, s_w);
+        if (valid) buf[pos] = v[k];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < kRsSmallPer; ++k) {
+        const int i = k * kBlock + tid;
+        if (i < cnt) v[k] = buf[i];
+      }
+      __syncthreads();
+    }
+#pragma unroll
+  for (int k = 0; k < kRsSmallPer; ++k) {
+    const int i = k * kBlock + tid;
+    if (i < cnt) keys[i] = v[k];
+  }
+}
+
+// hist[t * kRsBins + d] = keys of tile t with digit d
+__global__ __launch_bounds__(kBlock) void k_rs_hist(const u64 *__restrict__ keys, int cnt, int sh,
+                                                    int *__restrict__ hist) {
+  __shared__ int h[kRsBins];
+  const int tid = threadIdx.x, t = blockIdx.x;
+  h[tid] = 0;
+  __syncthreads();
+  for (int k = 0; k < kRsPer; ++k) {
+    const long long i = (long long)t * kRsTile + k * kBlock + tid;
+    if (i < cnt) atomicAdd(&h[rs_digit(keys[i], sh)], 1);
+  }
+  __syncthreads();
+  hist[(size_t)t * kRsBins + tid] = h[tid];
+}
+
+// Exclusive scan over the workgroup (kBlock threads); *total gets the sum.
+__device__ __forceinline__ int rs_block_scan(int x, int *total) {
+  __shared__ int wsum[kRsWaves];
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+  int v = x;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int y = __shfl_up(v, o);
+    if (lane >= o) v += y;
+  }
+  if (lane == kWave - 1) wsum[w] = v;
+  __syncthreads();
+  int before = 0, all = 0;
+#pragma unroll
+  for (int j = 0; j < kRsWaves; ++j) {
+    if (j < w) before += wsum[j];
+    all += wsum[j];
+  }
+  __syncthreads();
+  *total = all;
+  return before + v - x;
+}
+
+// Column d of the tile-major histograms (workgroup d): each entry becomes
+// the count of digit d in the tiles before it, and tot[d] the column's sum.
+__global__ __launch_bounds__(kBlock) void k_rs_colscan(int *__restrict__ hist, int ntiles,
+                                                       int *__restrict__ tot) {
+  const int d = blockIdx.x;
+  int carry = 0;
+  for (int t0 = 0; t0 < ntiles; t0 += kBlock) {
+    const int t = t0 + (int)threadIdx.x;
+    const size_t i = (size_t)t * kRsBins + d;
+    const int x = t < ntiles ? hist[i] : 0;
+    int sum;
+    const int ex = rs_block_scan(x, &sum);
+    if (t < ntiles) hist[i] = carry + ex;
+    carry += sum;
+  }
+  if (threadIdx.x == 0) tot[d] = carry;
+}
+
+// out[start of (digit, tile) + rank within the tile] = key
+__global__ __launch_bounds__(kBlock) void k_rs_scatter(const u64 *__restrict__ in,
+                                                       u64 *__restrict__ out, int cnt, int sh,
+                                                       const int *__restrict__ start,
+                                                       const int *__restrict__ tot) {
+  __shared__ int s_run[kRsBins];
+  __shared__ int s_w[kRsWaves][kRsBins];
+  const int tid = threadIdx.x, t = blockIdx.x;
+  int all;
+  s_run[tid] = rs_block_scan(tot[tid], &all) + start[(size_t)t * kRsBins + tid];
+  for (int j = 0; j < kRsWaves; ++j) s_w[j][tid] = 0;
+  __syncthreads();
+  for (int k = 0; k < kRsPer; ++k) {
+    const long long i = (long long)t * kRsTile + k * kBlock + tid;
+    const bool valid = i < cnt;
+    const u64 key = valid ? in[i] : 0;
+    const int pos = rs_rank(valid, rs_digit(key, sh), s_run, s_w);
+    if (valid) out[pos] = key;
+  }
+}
+
+// sorts keys[0 .. cnt) (IDs below n in both halves); the result is in
+// *keys or *tmp, returned through *sorted
+void rs_sort(u64 *keys, u64 *tmp, int cnt, int n, int *hist, hipStream_t s, u64 **sorted) {
+  int b = 0;  // bits of an ID below n
+  while (b < 31 && (1ll << b) < n) ++b;
+  if (cnt <= kRsSmall) {
+    if (b > 0) hipLaunchKernelGGL(k_rs_small, dim3(1), dim3(kBlock), 0, s, keys, cnt, b);
+    *sorted = keys;
+    return;
+  }
+  const int ntiles = (int)(((long long)cnt + kRsTile - 1) / kRsTile);
+  u64 *src = keys, *dst = tmp;
+  for (int half = 0; half < 2; ++half)
+    for (int lo = 0; lo < b; lo += 8) {
+      const int sh = 32 * half + lo;
+      hipLaunchKernelGGL(k_rs_hist, dim3(ntiles), dim3(kBlock), 0, s, (const u64 *)src, cnt, sh,
+                         hist);
+      hipLaunchKernelGGL(k_rs_colscan, dim3(kRsBins), dim3(kBlock), 0, s, hist, ntiles,
+                         hist + (size_t)kRsBins * ntiles);
+      hipLaunchKernelGGL(k_rs_scatter, dim3(ntiles), dim3(kBlock), 0, s, (const u64 *)src, dst,
+                         cnt, sh, (const int *)hist, (const int *)hist + (size_t)kRsBins * ntiles);
+      u64 *x = src;
+      src = dst;
+      dst = x;
+    }
+  *sorted = src;
 }
 
 // per-row counts of a sorted key list (cnt zeroed before); a repeated key
@@ -406,7 +622,6 @@ int prhip_apply_view(int n, const int *off, const int *cols, int m_old, int m_ne
   u64 *dk_in = nullptr, *dk = nullptr, *ik_in = nullptr, *ik = nullptr;
   int *dcnt = nullptr, *icnt = nullptr, *deg = nullptr, *tsum = nullptr, *err = nullptr;
   void *tmp = nullptr;
-  size_t tmp_d = 0, tmp_i = 0;
   hipError_t e = hipSuccess;
   auto done = [&](hipError_t code, const char *msg) {
     (void)hipFreeAsync(dk_in, s); (void)hipFreeAsync(dk, s); (void)hipFreeAsync(ik_in, s);
@@ -414,17 +629,16 @@ int prhip_apply_view(int n, const int *off, const int *cols, int m_old, int m_ne
     if (code != hipSuccess && !*what) *what = msg;
     return (int)code;
   };
-  if ((e = rocprim::radix_sort_keys(nullptr, tmp_d, (u64 *)nullptr, (u64 *)nullptr, (unsigned)nd, 0, 64, s)) != hipSuccess ||
-      (e = rocprim::radix_sort_keys(nullptr, tmp_i, (u64 *)nullptr, (u64 *)nullptr, (unsigned)ni, 0, 64, s)) != hipSuccess)
-    return done(e, "radix sort size query");
-  const size_t tmp_b = tmp_d > tmp_i ? tmp_d : tmp_i;
+  // radix sort: per-tile digit histograms of the longer list
+  const long long kmax = nd > ni ? nd : ni;
+  const size_t nhist = (size_t)kRsBins * (size_t)((kmax + kRsTile - 1) / kRsTile + 1);
   bytes = (size_t)(nd + 1) * 2 * sizeof(u64) + (size_t)(ni + 1) * 2 * sizeof(u64);
   if ((e = hipMallocAsync((void **)&dk_in, (size_t)(nd + 1) * sizeof(u64), s)) != hipSuccess ||
       (e = hipMallocAsync((void **)&dk, (size_t)(nd + 1) * sizeof(u64), s)) != hipSuccess ||
       (e = hipMallocAsync((void **)&ik_in, (size_t)(ni + 1) * sizeof(u64), s)) != hipSuccess ||
       (e = hipMallocAsync((void **)&ik, (size_t)(ni + 1) * sizeof(u64), s)) != hipSuccess ||
       (e = hipMallocAsync((void **)&dcnt, ((size_t)3 * n + nt + 16 + nbk + 1) * sizeof(int), s)) != hipSuccess ||
-      (e = hipMallocAsync(&tmp, tmp_b + 16, s)) != hipSuccess)
+      (e = hipMallocAsync(&tmp, nhist * sizeof(int), s)) != hipSuccess)
     return done(e, "scratch allocation");
   (void)bytes;
   icnt = dcnt + n;
@@ -436,19 +650,21 @@ int prhip_apply_view(int n, const int *off, const int *cols, int m_old, int m_ne
       (e = hipMemsetAsync(err, 0, sizeof(int), s)) != hipSuccess ||
       (e = hipMemsetAsync(rowat, 0xff, (size_t)(nbk + 1) * sizeof(int), s)) != hipSuccess)
     return done(e, "memset");
+  // the sorted lists (dk_in / dk and ik_in / ik are each other's ping-pong)
+  const u64 *dsorted = dk, *isorted = ik;
   if (nd > 0) {
     hipLaunchKernelGGL(k_keys, dim3(grid_for(nd)), dim3(kBlock), 0, s, del_row, del_col, nd, n, dk_in, err);
-    size_t tb = tmp_d;
-    if ((e = rocprim::radix_sort_keys(tmp, tb, dk_in, dk, (unsigned)nd, 0, 64, s)) != hipSuccess)
-      return done(e, "radix sort");
-    hipLaunchKernelGGL(k_count, dim3(grid_for(nd)), dim3(kBlock), 0, s, (const u64 *)dk, nd, dcnt, err);
+    u64 *out = nullptr;
+    rs_sort(dk_in, dk, nd, n, (int *)tmp, s, &out);
+    dsorted = out;
+    hipLaunchKernelGGL(k_count, dim3(grid_for(nd)), dim3(kBlock), 0, s, dsorted, nd, dcnt, err);
   }
   if (ni > 0) {
     hipLaunchKernelGGL(k_keys, dim3(grid_for(ni)), dim3(kBlock), 0, s, ins_row, ins_col, ni, n, ik_in, err);
-    size_t tb = tmp_i;
-    if ((e = rocprim::radix_sort_keys(tmp, tb, ik_in, ik, (unsigned)ni, 0, 64, s)) != hipSuccess)
-      return done(e, "radix sort");
-    hipLaunchKernelGGL(k_count, dim3(grid_for(ni)), dim3(kBlock), 0, s, (const u64 *)ik, ni, icnt, err);
+    u64 *out = nullptr;
+    rs_sort(ik_in, ik, ni, n, (int *)tmp, s, &out);
+    isorted = out;
+    hipLaunchKernelGGL(k_count, dim3(grid_for(ni)), dim3(kBlock), 0, s, isorted, ni, icnt, err);
   }
   hipLaunchKernelGGL(k_tile_sums, dim3(nt), dim3(kBlock), 0, s, off, (const int *)dcnt, (const int *)icnt, n,
                      deg, tsum);
@@ -458,13 +674,13 @@ int prhip_apply_view(int n, const int *off, const int *cols, int m_old, int m_ne
   hipLaunchKernelGGL(k_check_total, dim3(1), dim3(64), 0, s, (const int *)new_off, (const int *)deg, n, m_new,
                      err);
   hipLaunchKernelGGL(k_check_deg, dim3(grid_for((long long)n)), dim3(kBlock), 0, s, (const int *)deg, n, err);
-  hipLaunchKernelGGL(k_rows, dim3(grid_for((long long)n)), dim3(kBlock), 0, s, off, cols, (const u64 *)dk, nd,
-                     (const u64 *)ik, ni, (const int *)dcnt, (const int *)icnt, n, (const int *)new_off,
+  hipLaunchKernelGGL(k_rows, dim3(grid_for((long long)n)), dim3(kBlock), 0, s, off, cols, dsorted, nd,
+                     isorted, ni, (const int *)dcnt, (const int *)icnt, n, (const int *)new_off,
                      m_new, new_cols, err);
   if (nbk > 0) {
     hipLaunchKernelGGL(k_rowat, dim3(grid_for((long long)n)), dim3(kBlock), 0, s, off, n, nbk, rowat);
     hipLaunchKernelGGL(k_long_rows, dim3(nbk < 65536 ? nbk : 65536), dim3(kBlock), 0, s, off, cols,
-                       (const u64 *)dk, nd, (const u64 *)ik, ni, (const int *)dcnt, (const int *)icnt, n,
+                       dsorted, nd, isorted, ni, (const int *)dcnt, (const int *)icnt, n,
                        (const int *)rowat, nbk, (const int *)new_off, m_new, new_cols, err);
   }
   if ((e = hipGetLastError()) != hipSuccess) return done(e, "kernel launch");

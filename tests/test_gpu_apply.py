@@ -50,6 +50,16 @@ def test_random_batches(frac, ins):
     check(g, b)
 
 
+@pytest.mark.parametrize("n,size", [(70001, 30000), (300, 2500), (1 << 16, 12289)])
+def test_batches_over_many_sort_tiles(n, size):
+    """Batches of several 4096-key tiles of the batch sort, with IDs of 17, 9
+    and 16 bits (the sort covers only the digits IDs below n can set)."""
+    scale = int(np.ceil(np.log2(n)))
+    g = gg.rmat_graph(scale, 10, seed=n, n=n)
+    b = gg.random_batch(g, size, seed=n + 1, insert_frac=0.7)
+    check(g, b)
+
+
 def test_hub_rows_empty_batch_and_in_view_only():
     k = 5000  # in-star and out-star hubs: rows longer than one lane copies
     src = np.concatenate([np.arange(1, k + 1), np.zeros(k, np.int64)]).astype(np.int32)
