@@ -329,7 +329,7 @@ typedef struct pr_tuning {
  *                     of 256 affected vertices); 0 = both sweep ID tiles of
  *                     every vertex and skip the unaffected ones. The same
  *                     ranks either way (bit for bit).
- * chain_numbering     DF/DF-P/DT with relabel and the die split on: 1 = the
+ * chain_numbering     DF/DF-P/DT with relabel and the die split on. 1: the
  *                     gather-side numbering is kept from one such call to
  *                     the next on graphs of the same n, and each call maps
  *                     its in-CSR from the mapping the previous call left (a
@@ -337,11 +337,14 @@ typedef struct pr_tuning {
  *                     lookup elsewhere; nothing about the caller's arrays
  *                     is assumed); the numbering is rebuilt once the
  *                     entries not found that way, summed since it was
- *                     built, pass 1/8 of the edges. 0 = numbering and
+ *                     built, pass 1/8 of the edges. 0: numbering and
  *                     mapping built inside each call (the next such call
- *                     releases what was kept). The same ranks either
- *                     way (bit for bit). Keeping it costs 16 m + 12 n bytes
- *                     of device memory beyond the workspace.
+ *                     releases what was kept). -1 (automatic): 1 when
+ *                     n >= 2^23, where the numbering no longer fits the
+ *                     dies' L2 caches and a fresh map's lookups miss, else
+ *                     0 without the release. The same ranks either way (bit
+ *                     for bit). Keeping it costs 16 m + 12 n bytes of device
+ *                     memory beyond the workspace.
  * ppr_chunk_edges     pr_ppr: a row with at most this many in-edges is
  *                     summed whole by one wavefront (lane = vector); a longer
  *                     row is summed in chunks of this many edges whose
@@ -353,11 +356,12 @@ typedef struct pr_tuning {
  * Defaults: lane_max_degree 128, wave_max_degree 4096, expand_lane_max_degree
  * 32, iters_per_sync 2, hub_chunk_edges 4096, grid_blocks 0, relabel -1,
  * xcd_split_degree 129, expand_pull_per_mille 20, frontier_list 1,
- * chain_numbering 1, ppr_chunk_edges 256. */
+ * chain_numbering -1, ppr_chunk_edges 256. */
 
 /* Set (NULL = defaults) or read the process-wide tuning. PR_EINVAL if a
  * field is out of range (degrees < 0, lane > wave, iters_per_sync < 1,
- * xcd_split_degree == 1, frontier_list or chain_numbering not 0 or 1,
+ * xcd_split_degree == 1, frontier_list not 0 or 1, chain_numbering not in
+ * -1 .. 1,
  * ppr_chunk_edges not 0 or in 16 .. 2^20). */
 int pr_set_tuning(const pr_tuning *t);
 int pr_get_tuning(pr_tuning *t);

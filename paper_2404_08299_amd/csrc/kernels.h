@@ -80,7 +80,8 @@ enum CountSlot {
   kMapMiss = 20,   // entries a mapping from a kept mapping did not find there
   kCands = 21,     // per iteration parity p: slot 21 + p the size of the list of
                    // frontier vertices in the out-degree wavefront class
-  kNumCounts = 23
+  kMapRows = 23,   // rows a mapping from a kept mapping leaves to k_map_rows_kept
+  kNumCounts = 24
 };
 
 // Streamed data (CSR arrays, a vertex's own rank, new ranks) is read and
@@ -1696,92 +1697,77 @@ __device__ __forceinline__ void map_run(const int *__restrict__ src,
   }
 }
 
-// One wavefront-wide chunk of ONE row (MODE 2) at [cb, cb + 64) clipped to
-// b, from the guess e + shift. Rows are ascending, so within one row the kept
-// entries a wavefront loads at e + shift are ascending too: an entry not
-// found at its own lane is looked for among the wavefront's 64 (a cross-lane
-// binary search), which finds it when an update moved it by less than 64
-// places, and the shift that the last entry so found shows is carried to the
-// rest of the row.
-__device__ __forceinline__ void map_chunk_kept(const int *__restrict__ src,
-                                               const int *__restrict__ newid,
-                                               int *__restrict__ dst, int cb, int b, int &shift,
-                                               const MapCache &c, int &miss) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int e = cb + lane;
-  const bool v = e < b;
-  const int u = v ? ld_nt(src + e) : 0;
-  const int p = e + shift;
-  const bool in = (unsigned)p < (unsigned)c.old_m;
-  // places outside the kept entries read as -1 below and +infinity above
-  const int o = in ? ld_nt(c.old_raw + p) : (p < 0 ? -1 : 0x7fffffff);
-  const int mm = in ? ld_nt(c.old_map + p) : 0;
-  bool hit = v && o == u;
-  int id = mm;
-  if (__ballot(v && !hit)) {
-    int lo = 0;  // last lane j with o_j <= u
-#pragma unroll
-    for (int st = kWave / 2; st >= 1; st >>= 1) {
-      const int oj = __shfl(o, lo + st);
-      if (lo + st < kWave && oj <= u) lo += st;
-    }
-    const int oj = __shfl(o, lo), mj = __shfl(mm, lo);
-    const bool found = v && !hit && oj == u;  // u >= 0 never equals the fillers
-    if (found) id = mj;
-    const unsigned long long fb = __ballot(found);
-    if (fb) {
-      const int L = 63 - __clzll(fb);
-      shift += __shfl(lo - lane, L);
-    }
-    hit = hit || found;
-  }
-  if (v) {
-    if (!hit) {
-      id = newid[u];
-      ++miss;
-    }
-    st_nt(dst + e, id);
-    st_nt(c.raw_out + e, u);
-  }
-}
-
-// Entries [a, b) of ONE row (MODE 2): four chunks loaded at once at the
-// current shift; when all of their entries are found where guessed they are
-// stored as loaded, otherwise the four are done one by one by map_chunk_kept.
+// Entries [a, b) of ONE row (MODE 2), four wavefront-wide chunks at a time,
+// all loaded at the current shift. When every entry is found where guessed
+// the chunks are stored as loaded. Otherwise each chunk looks for its
+// entries not found among its own 64 kept entries: rows are ascending, so
+// the kept entries a wavefront loads at e + shift are ascending too, and a
+// cross-lane binary search finds an entry that an update moved by fewer
+// than 64 places. The four searches are independent (their shuffles
+// overlap); the entries still not found are looked up in the numbering
+// together, and the shift that the last entry found by a search shows is
+// carried to the rest of the row.
 __device__ __forceinline__ void map_row_kept(const int *__restrict__ src,
                                              const int *__restrict__ newid,
                                              int *__restrict__ dst, int a, int b, int shift,
                                              const MapCache &c, int &miss) {
   const int lane = threadIdx.x & (kWave - 1);
   for (int cb = a; cb < b; cb += 4 * kWave) {
-    int u[4], mm[4];
+    int u[4], o[4], mm[4];
     bool ok = true;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int e = cb + k * kWave + lane, p = e + shift;
-      u[k] = 0;
-      mm[k] = 0;
-      if (e < b) {
-        u[k] = ld_nt(src + e);
-        const bool in = (unsigned)p < (unsigned)c.old_m;
-        const int o = in ? ld_nt(c.old_raw + p) : -1;
-        mm[k] = in ? ld_nt(c.old_map + p) : 0;
-        ok = ok && o == u[k];
-      }
+      const bool in = (unsigned)p < (unsigned)c.old_m;
+      u[k] = e < b ? ld_nt(src + e) : 0;
+      // places outside the kept entries read as -1 below and +infinity above
+      o[k] = in ? ld_nt(c.old_raw + p) : (p < 0 ? -1 : 0x7fffffff);
+      mm[k] = in ? ld_nt(c.old_map + p) : 0;
+      ok = ok && (e >= b || o[k] == u[k]);
     }
-    if (__ballot(!ok) == 0) {
+    if (__ballot(!ok) != 0) {
+      int carry = 0;
+      bool carried = false;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const int e = cb + k * kWave + lane;
-        if (e < b) {
-          st_nt(dst + e, mm[k]);
-          st_nt(c.raw_out + e, u[k]);
+        const bool v = cb + k * kWave + lane < b;
+        const bool want = v && o[k] != u[k];
+        if (!__ballot(want)) continue;
+        int lo = 0;  // last lane j with o_j <= u
+#pragma unroll
+        for (int st = kWave / 2; st >= 1; st >>= 1) {
+          const int oj = __shfl(o[k], lo + st);
+          if (lo + st < kWave && oj <= u[k]) lo += st;
+        }
+        const int oj = __shfl(o[k], lo), mj = __shfl(mm[k], lo);
+        const bool found = want && oj == u[k];  // u >= 0 never equals the fillers
+        if (found) {
+          mm[k] = mj;
+          o[k] = u[k];
+        }
+        const unsigned long long fb = __ballot(found);
+        if (fb) {
+          const int L = 63 - __clzll(fb);
+          carry = __shfl(lo - lane, L);
+          carried = true;
         }
       }
-      continue;
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (cb + k * kWave + lane < b && o[k] != u[k]) {
+          mm[k] = newid[u[k]];
+          ++miss;
+        }
+      if (carried) shift += carry;
     }
-    for (int k = 0; k < 4 && cb + k * kWave < b; ++k)
-      map_chunk_kept(src, newid, dst, cb + k * kWave, b, shift, c, miss);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int e = cb + k * kWave + lane;
+      if (e < b) {
+        st_nt(dst + e, mm[k]);
+        st_nt(c.raw_out + e, u[k]);
+      }
+    }
   }
 }
 
@@ -1844,18 +1830,27 @@ __global__ __launch_bounds__(kBlock) void k_map_split(const int4 *__restrict__ x
 // Rows with fewer than T in-edges: a wavefront takes 64 consecutive rows and
 // cuts them into segments, maximal runs of consecutive such rows (which lie
 // end to end in memory) with one shift to the kept layout (MODE 2; 0
-// otherwise), and maps each segment as one run. In MODE 2 a row of at least
-// kKeptSearchLen entries whose length changed (the next row's shift differs
-// from its own) is a segment of its own, mapped as one row with the in-row
-// search; in a shorter changed row the entries after the change are looked
+// otherwise), and maps each segment as one run. In MODE 2, when the 64 rows
+// hold more than kKeptGroupLen entries, their rows of at least kKeptRowLen
+// entries are listed in dlist instead (one atomic per wavefront), and
+// k_map_rows_kept maps them a wavefront each: the long rows of a graph can
+// cluster in a few groups of 64 (on preferential-attachment graphs the early
+// vertices hold most in-edges), and one wavefront streaming all of them would
+// hold up the whole launch. A row of at least kKeptRowLen entries whose
+// length changed (the next row's shift differs from its own) is listed there
+// too, since its walk with the in-row search (map_row_kept) is slower than a
+// stream; in a shorter changed row the entries after the change are looked
 // up. MODE >= 1 also copies the row offsets.
-constexpr int kKeptSearchLen = 256;
+constexpr int kKeptRowLen = 256;
+constexpr int kKeptGroupLen = 16384;
 
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_map_short(const int *__restrict__ in_off,
                                                       const int *__restrict__ src, int n, int T,
                                                       const int *__restrict__ newid,
-                                                      int *__restrict__ dst, MapCache c) {
+                                                      int *__restrict__ dst, MapCache c,
+                                                      int *__restrict__ dlist,
+                                                      int *__restrict__ dcount) {
   const int lane = threadIdx.x & (kWave - 1);
   const long long nw = (long long)gridDim.x * kWavesPerBlock;
   int miss = 0;
@@ -1879,27 +1874,43 @@ __global__ __launch_bounds__(kBlock) void k_map_short(const int *__restrict__ in
     const int r = (int)(wv * kWave) + lane;
     const int ce0 = ne0, ce1 = ne1, co0 = no0, co1 = no1;
     if ((wv + nw) * kWave < n) fetch(wv + nw);
-    int e0 = 0, cnt = 0, sh = 0;
+    int e0 = 0, cnt = 0, sh = 0, d = 0;
     bool mine = false, alone = false;
     if (r < n) {
       e0 = ce0;
-      const int e1 = ce1, d = e1 - e0;
+      const int e1 = ce1;
+      d = e1 - e0;
       mine = d < T;
       if (mine) cnt = d;
       if (MODE == 2) {
         sh = co0 - e0;
-        alone = mine && d >= kKeptSearchLen && co1 - e1 != sh;
+        alone = mine && d >= kKeptRowLen && co1 - e1 != sh;
       }
       if (MODE >= 1) {
         c.off_out[r] = e0;
         if (r == n - 1) c.off_out[n] = e1;
       }
     }
+    if (MODE == 2) {
+      const bool heavy = wave_sum_int(cnt) > kKeptGroupLen;  // every lane takes part
+      const bool later = alone || (mine && d >= kKeptRowLen && heavy);
+      const unsigned long long lm = __ballot(later);
+      if (lm) {
+        int base = 0;
+        if (lane == 0) base = atomicAdd(dcount, __popcll(lm));
+        base = __shfl(base, 0);
+        if (later) {
+          dlist[base + __popcll(lm & ((1ull << lane) - 1))] = r;
+          mine = false;
+          cnt = 0;
+        }
+      }
+    }
     // a segment starts at a row of this kernel unless the previous row is
-    // one too, of the same shift, and neither is mapped alone
+    // one too, of the same shift
     const int psh = __shfl_up(sh, 1);
-    const bool pmine = __shfl_up((int)mine, 1) != 0, palone = __shfl_up((int)alone, 1) != 0;
-    const bool start = mine && (lane == 0 || !pmine || palone || alone || psh != sh);
+    const bool pmine = __shfl_up((int)mine, 1) != 0;
+    const bool start = mine && (lane == 0 || !pmine || psh != sh);
     // ... and ends before the next start or the next row not of this kernel
     const unsigned long long starts = __ballot(start), stops = __ballot(!mine) | starts;
     int x = cnt;  // inclusive scan of the lengths of this kernel's rows
@@ -1917,13 +1928,29 @@ __global__ __launch_bounds__(kBlock) void k_map_short(const int *__restrict__ in
       // entries of rows j .. jend - 1, end to end
       const int len = __shfl(x, jend - 1) - __shfl(x, j) + __shfl(cnt, j);
       const int a = __shfl(e0, j), shj = __shfl(sh, j);
-      if (MODE == 2 && __shfl((int)alone, j))
-        map_row_kept(src, newid, dst, a, a + len, shj, c, miss);
-      else
-        map_run<MODE>(src, newid, dst, a, a + len, shj, c, miss);
+      map_run<MODE>(src, newid, dst, a, a + len, shj, c, miss);
     }
   }
   map_misses<MODE>(miss, c);
+}
+
+// The rows k_map_short listed (MODE 2), a wavefront per row, each walked from
+// its offsets' shift with the in-row search.
+__global__ __launch_bounds__(kBlock) void k_map_rows_kept(const int *__restrict__ in_off,
+                                                          const int *__restrict__ src,
+                                                          const int *__restrict__ newid,
+                                                          int *__restrict__ dst, MapCache c,
+                                                          const int *__restrict__ dlist,
+                                                          const int *__restrict__ dcount) {
+  const int L = *dcount;
+  const int W = gridDim.x * kWavesPerBlock;
+  int miss = 0;
+  for (int i = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; i < L; i += W) {
+    const int r = dlist[i];
+    const int e0 = in_off[r], e1 = in_off[r + 1];
+    map_row_kept(src, newid, dst, e0, e1, c.old_off[r] - e0, c, miss);
+  }
+  map_misses<2>(miss, c);
 }
 
 // Count of affected vertices (profiling only).

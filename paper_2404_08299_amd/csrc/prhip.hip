@@ -54,7 +54,7 @@ pr_tuning default_tuning() {
   t.xcd_split_degree = 129;
   t.expand_pull_per_mille = 20;
   t.frontier_list = 1;
-  t.chain_numbering = 1;
+  t.chain_numbering = -1;
   t.ppr_chunk_edges = 256;
   return t;
 }
@@ -564,10 +564,15 @@ int build_numbering(Workspace &w, int n, const int *group_off, const int *rs, in
 // rows are left to the items.
 constexpr int kKeptItemLen = 4096;
 
+// MODE 2 needs dlist (n ints of scratch) for the rows of kKeptRowLen .. Ts - 1
+// entries, which k_map_rows_kept maps after k_map_short.
 template <int MODE>
 int map_rows(Workspace &w, const XPlan &xp, const int *row_off, const int *idx, int n, int T,
-             const int *newid, int *dst, const MapCache &c, hipStream_t s) {
+             const int *newid, int *dst, const MapCache &c, hipStream_t s,
+             int *dlist = nullptr) {
   const int Ts = MODE == 2 ? std::max(T, kKeptItemLen) : T;
+  int *dcount = w.counts + kMapRows;
+  if (MODE == 2) HIP_TRY(hipMemsetAsync(dcount, 0, sizeof(int), s));
   if (xp.items) {
     const int gs = kXcds * 4 * std::max(1, w.num_cus);
     auto map_fn = item_lg(w, xp, gs) ? k_map_split<4, MODE> : k_map_split<0, MODE>;
@@ -579,7 +584,10 @@ int map_rows(Workspace &w, const XPlan &xp, const int *row_off, const int *idx, 
   const int gr = (int)std::min<long long>(((long long)n + kBlock - 1) / kBlock,
                                           64LL * std::max(1, w.num_cus));
   hipLaunchKernelGGL(k_map_short<MODE>, dim3(gr), dim3(kBlock), 0, s, row_off, idx, n, Ts,
-                     newid, dst, c);
+                     newid, dst, c, dlist, dcount);
+  if (MODE == 2)
+    hipLaunchKernelGGL(k_map_rows_kept, dim3(16 * std::max(1, w.num_cus)), dim3(kBlock), 0, s,
+                       row_off, idx, newid, dst, c, (const int *)dlist, (const int *)dcount);
   LAUNCH_TRY();
   return PR_OK;
 }
@@ -651,12 +659,16 @@ constexpr long long kChainRebuild = 8;
 // whether the numbering is kept or built anew.
 int locality_chain(Workspace &w, int n, int m, const int *group_off, const int *idx,
                    const pr_tuning &tn, hipStream_t s, Locality *out, const int *rs,
-                   const XPlan &xp, const int *row_off, int T) {
-  if (!tn.chain_numbering && w.nc_cap_n) {
+                   const XPlan &xp, const int *row_off, int T, int *dlist) {
+  if (tn.chain_numbering == 0 && w.nc_cap_n) {
     HIP_TRY(hipStreamSynchronize(s));
     free_chain(w);  // turned off: what was kept is released
   }
-  if (!tn.chain_numbering || !relabel_on(tn, n) || !rs || T <= 0)
+  // automatic: kept from 2^23 vertices on. Below, each die's eighth of the
+  // numbering (4n / 8 bytes) fits its 4 MB L2, so the fresh map's lookups hit
+  // L2 and its 8 bytes per entry beat the kept map's 20.
+  const bool on = tn.chain_numbering > 0 || (tn.chain_numbering < 0 && n >= (1 << 23));
+  if (!on || !relabel_on(tn, n) || !rs || T <= 0)
     return locality(w, n, m, group_off, idx, tn, true, s, out, rs, &xp, row_off, T);
   int rc = chain_ws(w, (size_t)n, (size_t)m);
   if (rc) return rc;
@@ -674,7 +686,7 @@ int locality_chain(Workspace &w, int n, int m, const int *group_off, const int *
     c.old_m = w.nc_m[cur];
     c.miss = w.counts + kMapMiss;
     HIP_TRY(hipMemsetAsync(c.miss, 0, sizeof(int), s));
-    rc = map_rows<2>(w, xp, row_off, idx, n, T, w.nc_newid, w.nc_map[nx], c, s);
+    rc = map_rows<2>(w, xp, row_off, idx, n, T, w.nc_newid, w.nc_map[nx], c, s, dlist);
     if (rc) return rc;
     HIP_TRY(hipMemcpyAsync(w.host_counts + kMapMiss, c.miss, sizeof(int),
                            hipMemcpyDeviceToHost, s));
@@ -932,9 +944,10 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
   auto rank_d = lg ? (use_list ? k_rank_dfp<false, 4, true> : k_rank_dfp<false, 4, false>)
                    : (use_list ? k_rank_dfp<false, 0, true> : k_rank_dfp<false, 0, false>);
   Locality loc;
+  // the frontier list's storage serves the mapping as scratch (n ints)
   if ((rc = locality_chain(w, n, g->m, g->out_offsets, g->in_sources, tn, s, &loc,
                            xs ? w.xrs : nullptr, xp, g->in_offsets,
-                           std::max(xsplit_min_degree(tn), t1 + 1))))
+                           std::max(xsplit_min_degree(tn), t1 + 1), cand)))
     return rc;
   double *X = w.X0;
   hipLaunchKernelGGL(k_dfp_init, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n,
@@ -1942,7 +1955,7 @@ int pr_set_tuning(const pr_tuning *t) {
       t->grid_blocks < 0 || t->grid_blocks > (1 << 20) || t->relabel < -1 || t->relabel > 1 ||
       t->xcd_split_degree < 0 || t->xcd_split_degree == 1 || t->expand_pull_per_mille < 0 ||
       t->expand_pull_per_mille > 1000 || t->frontier_list < 0 || t->frontier_list > 1 ||
-      t->chain_numbering < 0 || t->chain_numbering > 1 || t->ppr_chunk_edges < 0 ||
+      t->chain_numbering < -1 || t->chain_numbering > 1 || t->ppr_chunk_edges < 0 ||
       (t->ppr_chunk_edges > 0 && t->ppr_chunk_edges < 16) || t->ppr_chunk_edges > (1 << 20))
     return fail(PR_EINVAL, "tuning field out of range");
   g_tuning = *t;

@@ -109,7 +109,8 @@ def test_tuning_validation(lib):
                 prhip.PrTuning(1, 5, 3, 1, 64, 0, 0, 0, -1),   # pull threshold < 0
                 prhip.PrTuning(1, 5, 3, 1, 64, 0, 0, 0, 1001),   # pull threshold > 1000
                 prhip.PrTuning(1, 5, 3, 1, 64, 0, 0, 0, 0, 2),   # frontier_list not 0/1
-                prhip.PrTuning(1, 5, 3, 1, 64, 0, 0, 0, 0, 1, 2),  # chain_numbering not 0/1
+                prhip.PrTuning(1, 5, 3, 1, 64, 0, 0, 0, 0, 1, 2),  # chain_numbering > 1
+                prhip.PrTuning(1, 5, 3, 1, 64, 0, 0, 0, 0, 1, -2),  # chain_numbering < -1
                 prhip.PrTuning(1, 5, 3, 1, 64, 0, 0, 0, 0, 1, 1, 8),  # PPR chunk < 16
                 prhip.PrTuning(1, 5, 3, 1, 64, 0, 0, 0, 0, 1, 1, (1 << 20) + 1),
                 prhip.PrTuning(1, 5, 3, 1, 64, 0, 0, 0, 0, 1, 1, -1)]:
@@ -121,7 +122,7 @@ def test_tuning_validation(lib):
     assert got["wave_max_degree"] == 64 and got["hub_chunk_edges"] == 4096 and got["grid_blocks"] == 100
     assert got["xcd_split_degree"] == 2
     assert got["ppr_chunk_edges"] == 256 and default["ppr_chunk_edges"] == 256  # 0: default
-    assert default["chain_numbering"] == 1 and default["frontier_list"] == 1
+    assert default["chain_numbering"] == -1 and default["frontier_list"] == 1
     prhip.set_tuning(ppr_chunk_edges=16)
     assert prhip.get_tuning()["ppr_chunk_edges"] == 16
     prhip.set_tuning(hub_chunk_edges=128)

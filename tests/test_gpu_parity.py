@@ -469,9 +469,10 @@ def test_chain_numbering_same_bits(mode, tuning):
 
     fresh = run_chain(0)   # also releases anything kept by earlier tests
     kept = run_chain(1)
-    for k, ((rf, itf, nf), (rk, itk, nk)) in enumerate(zip(fresh, kept)):
-        assert nf == 1, k
-        assert itf == itk and np.array_equal(rf, rk), k
+    auto = run_chain(-1)   # the default: below 2^23 vertices, built in each call
+    for k, ((rf, itf, nf), (rk, itk, nk), (ra, ita, na)) in enumerate(zip(fresh, kept, auto)):
+        assert nf == 1 and na == 1, k
+        assert itf == itk == ita and np.array_equal(rf, rk) and np.array_equal(rf, ra), k
     assert [o[2] for o in kept] == [1, 2, 2, 2, 1, 1]
     # the chain's first step against the oracle
     o = oracle.dfp(g1.n, *g1.edges(), b1, prev0, prune=(mode == "dfp")) if mode != "dt" \
