@@ -1321,20 +1321,14 @@ __global__ __launch_bounds__(kBlock) void k_apply_expand(
 
 // ------------------------------------------------------------ pull expansion
 // The frontier of iteration `it` as a bitmap, bit v of fb[v / 32] = dN[v]
-// (dN bytes are 0 or 1), and its size added to ctrl->aux[2 + (it & 1)]; the
-// other counter is cleared for the next iteration. gate >= 0: the size is
-// already counted (k_frontier_count), and the bitmap is only built when the
-// frontier is larger than gate (when the marking pulls).
-__global__ __launch_bounds__(kBlock) void k_frontier(const uint8_t *__restrict__ dN, int n,
-                                                     uint32_t *__restrict__ fb, Ctrl *ctrl,
-                                                     int it, long long gate) {
-  if (ctrl->done) return;
-  if (gate >= 0 && ctrl->aux[2 + (it & 1)] <= gate) return;
-  if (gate < 0 && blockIdx.x == 0 && threadIdx.x == 0) ctrl->aux[2 + ((it + 1) & 1)] = 0;
+// (dN bytes are 0 or 1), over fb's words [w0, n/32) with stride ws.
+__device__ __forceinline__ int frontier_words(const uint8_t *__restrict__ dN, int n,
+                                              uint32_t *__restrict__ fb, long long w0,
+                                              long long ws) {
   const int nw = (n + 31) / 32;
   int cnt = 0;
-  for (int w = blockIdx.x * kBlock + threadIdx.x; w < nw; w += gridDim.x * kBlock) {
-    const int v0 = w * 32;
+  for (long long w = w0; w < nw; w += ws) {
+    const int v0 = (int)w * 32;
     uint32_t word = 0;
     if (v0 + 32 <= n && (reinterpret_cast<uintptr_t>(dN) & 3) == 0) {
       const uint32_t *q = reinterpret_cast<const uint32_t *>(dN + v0);
@@ -1350,29 +1344,54 @@ __global__ __launch_bounds__(kBlock) void k_frontier(const uint8_t *__restrict__
     fb[w] = word;
     cnt += __popc(word);
   }
-  if (gate >= 0) return;
+  return cnt;
+}
+
+__device__ __forceinline__ void frontier_add(int cnt, Ctrl *ctrl, int it) {
   cnt = wave_sum_int(cnt);
   if ((threadIdx.x & (kWave - 1)) == 0 && cnt)
     atomicAdd((unsigned long long *)&ctrl->aux[2 + (it & 1)], (unsigned long long)cnt);
 }
 
-// The size of the frontier of iteration `it`, counted over that iteration's
-// affected list (which holds every vertex with dN set), into
+// A list of at most n / kFrontierListShare vertices is counted over rather
+// than the n flags swept.
+constexpr int kFrontierListShare = 8;
+
+// The frontier's bitmap and its size added to ctrl->aux[2 + (it & 1)]; the
+// other counter is cleared for the next iteration. With the iteration's
+// affected list (alist, acount: it holds every vertex with dN set) and gate
+// >= 0: a short list is counted here and the bitmap is built only when the
+// frontier is larger than gate (when the marking pulls); a long list leaves
+// everything to the sweep, as without a list.
+__global__ __launch_bounds__(kBlock) void k_frontier(const uint8_t *__restrict__ dN, int n,
+                                                     uint32_t *__restrict__ fb, Ctrl *ctrl,
+                                                     int it, long long gate,
+                                                     const int *__restrict__ acount) {
+  if (ctrl->done) return;
+  const bool listed = acount && (long long)*acount * kFrontierListShare <= n;
+  if (listed && ctrl->aux[2 + (it & 1)] <= gate) return;
+  if (!listed && blockIdx.x == 0 && threadIdx.x == 0) ctrl->aux[2 + ((it + 1) & 1)] = 0;
+  const int cnt = frontier_words(dN, n, fb, (long long)blockIdx.x * kBlock + threadIdx.x,
+                                 (long long)gridDim.x * kBlock);
+  if (!listed) frontier_add(cnt, ctrl, it);
+}
+
+// The size of the frontier of iteration `it` counted over that iteration's
+// affected list, when the list is short (see k_frontier), into
 // ctrl->aux[2 + (it & 1)]; the other counter is cleared for the next
 // iteration.
 __global__ __launch_bounds__(kBlock) void k_frontier_count(const int *__restrict__ alist,
                                                            const int *__restrict__ acount,
-                                                           const uint8_t *__restrict__ dN,
+                                                           const uint8_t *__restrict__ dN, int n,
                                                            Ctrl *ctrl, int it) {
   if (ctrl->done) return;
-  if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->aux[2 + ((it + 1) & 1)] = 0;
   const int L = *acount;
+  if ((long long)L * kFrontierListShare > n) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->aux[2 + ((it + 1) & 1)] = 0;
   int cnt = 0;
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < L; i += gridDim.x * kBlock)
     cnt += dN[alist[i]] != 0;
-  cnt = wave_sum_int(cnt);
-  if ((threadIdx.x & (kWave - 1)) == 0 && cnt)
-    atomicAdd((unsigned long long *)&ctrl->aux[2 + (it & 1)], (unsigned long long)cnt);
+  frontier_add(cnt, ctrl, it);
 }
 
 __device__ __forceinline__ bool in_frontier(const uint32_t *__restrict__ fb, int u) {

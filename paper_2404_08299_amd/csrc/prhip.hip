@@ -983,14 +983,15 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
     // are in no list: it sweeps ID tiles
     const bool lst = use_list && it >= 0;
     if (mark && pull_thresh >= 0) {
-      // with the list, the frontier is counted over it, and the bitmap is
-      // only built when the marking pulls
+      // with a short list, the frontier is counted over it, and the bitmap
+      // is only built when the marking pulls
       if (lst)
         hipLaunchKernelGGL(k_frontier_count, dim3(cgrid_list), dim3(kBlock), 0, s,
                            (const int *)alist[it & 1], (const int *)acnt[it & 1],
-                           (const uint8_t *)dN, w.ctrl, it);
+                           (const uint8_t *)dN, n, w.ctrl, it);
       hipLaunchKernelGGL(k_frontier, dim3(fgrid), dim3(kBlock), 0, s, (const uint8_t *)dN, n,
-                         w.fbits, w.ctrl, it, lst ? pull_thresh : -1LL);
+                         w.fbits, w.ctrl, it, lst ? pull_thresh : -1LL,
+                         lst ? (const int *)acnt[it & 1] : nullptr);
       hipLaunchKernelGGL(k_pull_mark, dim3(B), dim3(kBlock), 0, s, g->in_offsets,
                          g->in_sources, (const int *)w.hi_in, (const int *)w.counts,
                          (const int *)w.hub_start_in, (const int *)w.chunk_hub_in, CH, xp.items,
@@ -1030,7 +1031,7 @@ int run_dynamic_frontier(const pr_csr *g, const pr_edges *del, const pr_edges *i
     int *changed = w.counts + kDtChanged;
     for (int level = 0;; ++level) {
       hipLaunchKernelGGL(k_frontier, dim3(fgrid), dim3(kBlock), 0, s, (const uint8_t *)dN, n,
-                         w.fbits, w.ctrl, level, -1LL);
+                         w.fbits, w.ctrl, level, -1LL, (const int *)nullptr);
       HIP_TRY(hipMemsetAsync(cv, 0, (size_t)n, s));
       HIP_TRY(hipMemsetAsync(changed, 0, sizeof(int), s));
       hipLaunchKernelGGL(k_pull_mark, dim3(B), dim3(kBlock), 0, s, g->in_offsets,
