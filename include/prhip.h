@@ -344,7 +344,8 @@ typedef struct pr_tuning {
  *                     dies' L2 caches and a fresh map's lookups miss, else
  *                     0 without the release. The same ranks either way (bit
  *                     for bit). Keeping it costs 16 m + 12 n bytes of device
- *                     memory beyond the workspace.
+ *                     memory beyond the workspace; when that cannot be
+ *                     allocated the call builds the numbering itself.
  * ppr_chunk_edges     pr_ppr: a row with at most this many in-edges is
  *                     summed whole by one wavefront (lane = vector); a longer
  *                     row is summed in chunks of this many edges whose

@@ -671,6 +671,10 @@ int locality_chain(Workspace &w, int n, int m, const int *group_off, const int *
   if (!on || !relabel_on(tn, n) || !rs || T <= 0)
     return locality(w, n, m, group_off, idx, tn, true, s, out, rs, &xp, row_off, T);
   int rc = chain_ws(w, (size_t)n, (size_t)m);
+  if (rc == PR_ENOMEM) {  // no room to keep it: built inside the call, as with 0
+    t_err.clear();
+    return locality(w, n, m, group_off, idx, tn, true, s, out, rs, &xp, row_off, T);
+  }
   if (rc) return rc;
   const int cur = w.nc_cur;
   const bool keep = cur >= 0 && w.nc_n == n && w.nc_miss * kChainRebuild <= w.nc_built_m;
