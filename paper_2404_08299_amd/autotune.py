@@ -29,7 +29,7 @@ import warnings
 from . import prhip
 
 DEFAULT_SPACE = {
-    "lane_max_degree": [32, 64, 128, 256],
+    "lane_max_degree": [4, 8, 32, 64, 128, 256],
     "wave_max_degree": [1024, 4096, 16384],
     "xcd_split_degree": [0, 65, 129, 257, 1024],
     "hub_chunk_edges": [1024, 4096, 8192],
