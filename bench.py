@@ -164,7 +164,7 @@ def temporal_leg(args, gg, prhip, torch, np):
     outs_df = [torch.empty(g0.n, dtype=torch.float64, device="cuda") for _ in range(2)]
     st_out = torch.empty(g0.n, dtype=torch.float64, device="cuda")
     ref = torch.empty(g0.n, dtype=torch.float64, device="cuda")
-    dfp_ms, df_ms, st_ms, dfp_it, df_it, errs = [], [], [], [], [], []
+    dfp_ms, df_ms, st_ms, dfp_it, df_it, st_it, errs = [], [], [], [], [], [], []
     for k, (dg, db) in enumerate(zip(dgs, dbs)):
         # DF-P and DF (no pruning, the paper's accuracy fallback) each chained
         # over the stream, and Static on G^t
@@ -176,6 +176,7 @@ def temporal_leg(args, gg, prhip, torch, np):
         _, ms_f = timed(lambda: prhip.dfp(dg, db, prev_df, mode="df", out=out_df))
         df_it.append(prhip.last_stats()["iterations"])
         _, ms_s = timed(lambda: prhip.static(dg, out=st_out))
+        st_it.append(prhip.last_stats()["iterations"])
         dfp_ms.append(ms_d)
         df_ms.append(ms_f)
         st_ms.append(ms_s)
@@ -207,6 +208,41 @@ def temporal_leg(args, gg, prhip, torch, np):
     log(f"temporal: DF-P {res['dfp_ms_geomean']} ms, DF {res['df_ms_geomean']} ms vs Static "
         f"{res['static_ms_geomean']} ms per batch (geomean), max L-inf DF-P "
         f"{res['max_dfp_linf']:.2e}, DF {res['max_df_linf']:.2e}")
+    if not args.no_tune:
+        # the same chain with the autotuner's choices for this graph size
+        # (untimed tuning: DF-P on the first batch, Static on G^0), DF taking
+        # DF-P's; the defaults were chosen at scale 24
+        from paper_2404_08299_amd import autotune
+        t = time.time()
+        prev0 = prhip.static(prhip.DeviceGraph.from_host(g0)).ranks
+        with tempfile.TemporaryDirectory() as td:
+            cache = os.path.join(td, "tuning.json")
+            tn_st = autotune.tune_static(dgs[0], expected_iters=int(np.median(st_it)),
+                                         cache_path=cache)
+            tn_dy = autotune.tune_dfp(dgs[0], dbs[0], prev0,
+                                      expected_iters=int(np.median(dfp_it)), cache_path=cache)
+        prhip.set_tuning()
+        defaults = prhip.get_tuning()
+        log(f"temporal autotune ({time.time() - t:.1f} s): Static {tn_st}, DF-P {tn_dy}")
+        prev, prev_df = prev0, prev0.clone()
+        t_dfp, t_df, t_st = [], [], []
+        for k, (dg, db) in enumerate(zip(dgs, dbs)):
+            out, out_df = outs[k & 1], outs_df[k & 1]
+            prhip.set_tuning(**tn_dy)
+            t_dfp.append(timed(lambda: prhip.dfp(dg, db, prev, out=out))[1])
+            t_df.append(timed(lambda: prhip.dfp(dg, db, prev_df, mode="df", out=out_df))[1])
+            prhip.set_tuning(**tn_st)
+            t_st.append(timed(lambda: prhip.static(dg, out=st_out))[1])
+            prev, prev_df = out, out_df
+        prhip.set_tuning()
+        res["tuned"] = {
+            "dfp_tuning": {k: v for k, v in tn_dy.items() if v != defaults[k]},
+            "static_tuning": {k: v for k, v in tn_st.items() if v != defaults[k]},
+            "dfp_ms_geomean": round(gm(t_dfp), 3), "df_ms_geomean": round(gm(t_df), 3),
+            "static_ms_geomean": round(gm(t_st), 3),
+            "dfp_speedup_geomean": round(gm(np.array(t_st) / np.array(t_dfp)), 2),
+            "df_speedup_geomean": round(gm(np.array(t_st) / np.array(t_df)), 2)}
+        log(f"temporal tuned: {res['tuned']}")
     if abl_cases and not args.no_compare:
         # Sec. 4.4's partitioning study on the first batches of the stream,
         # each from the DF-P chain's R^{t-1}

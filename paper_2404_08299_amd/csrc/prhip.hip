@@ -270,7 +270,9 @@ size_t xsplit_items_bound(size_t n, size_t m, int CH, int T) {
 int xsplit_ws(Workspace &w, size_t nb, size_t items) {
   const size_t need_mat = (kXcds + 1) * nb;
   if (need_mat > w.cap_xmat || items > w.cap_xitems) {
-    const size_t a = std::max(need_mat, w.cap_xmat), b = std::max(items, w.cap_xitems);
+    // 1/8 headroom, as for the workspace's edge-sized arrays
+    const size_t a = std::max(need_mat + need_mat / 8, w.cap_xmat);
+    const size_t b = std::max(items + items / 8, w.cap_xitems);
     free_xsplit(w);
     hipError_t e = hipSuccess;
     if ((e = hipMalloc(&w.xmat, a * sizeof(int))) != hipSuccess ||
@@ -316,9 +318,12 @@ int get_ws(size_t n, size_t m, int CH, int B, Workspace **out) {
   const size_t need_partials = (size_t)B + kHubFinalizeBlocks + 16;
   if (n > w.cap_n || m > w.cap_m || need_chunks > w.cap_chunks ||
       need_partials > w.cap_partials) {
+    // the edge-sized arrays grow with 1/8 headroom: along a chain of updates
+    // m drifts up by a batch at a time, and a reallocation per call would
+    // cost more than the call
     const size_t nn = std::max(n, w.cap_n);
-    const size_t mm = std::max(m, w.cap_m);
-    const size_t nc = std::max(need_chunks, w.cap_chunks);
+    const size_t mm = std::max(m + m / 8, w.cap_m);
+    const size_t nc = std::max(need_chunks + need_chunks / 8, w.cap_chunks);
     const size_t np = std::max(need_partials, w.cap_partials);
     free_arrays(w);
     const size_t nt = ntiles_for(nn);
