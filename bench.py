@@ -158,6 +158,7 @@ def temporal_leg(args, gg, prhip, torch, np):
     log(f"temporal: n={g0.n} m0={g0.m} m_end={dgs[-1].m}, {len(dgs)} batches "
         f"({time.time() - t:.1f} s)")
     prev = prhip.static(prhip.DeviceGraph.from_host(g0)).ranks
+    g0_ranks = prev.clone()
     prev_df = prev.clone()
     abl_cases = []
     outs = [torch.empty(g0.n, dtype=torch.float64, device="cuda") for _ in range(2)]
@@ -165,6 +166,7 @@ def temporal_leg(args, gg, prhip, torch, np):
     st_out = torch.empty(g0.n, dtype=torch.float64, device="cuda")
     ref = torch.empty(g0.n, dtype=torch.float64, device="cuda")
     dfp_ms, df_ms, st_ms, dfp_it, df_it, st_it, errs = [], [], [], [], [], [], []
+    refs = {}
     for k, (dg, db) in enumerate(zip(dgs, dbs)):
         # DF-P and DF (no pruning, the paper's accuracy fallback) each chained
         # over the stream, and Static on G^t
@@ -185,6 +187,7 @@ def temporal_leg(args, gg, prhip, torch, np):
             with warnings.catch_warnings():
                 warnings.simplefilter("ignore")
                 prhip.static(dg, tol=0.0, max_iter=500, out=ref)
+            refs[k] = ref.clone()
             d = (out - ref).abs()
             d_df = (out_df - ref).abs()
             errs.append({"batch": k + 1, "dfp_linf": float(d.max()), "dfp_l1": float(d.sum()),
@@ -208,6 +211,26 @@ def temporal_leg(args, gg, prhip, torch, np):
     log(f"temporal: DF-P {res['dfp_ms_geomean']} ms, DF {res['df_ms_geomean']} ms vs Static "
         f"{res['static_ms_geomean']} ms per batch (geomean), max L-inf DF-P "
         f"{res['max_dfp_linf']:.2e}, DF {res['max_df_linf']:.2e}")
+    # DF-P chained again with tighter frontier and prune tolerances (the
+    # paper's are 1e-6 each): what the speedup costs in accuracy on this
+    # stream, errors against the same reference runs
+    sweep = []
+    for tl in (1e-7, 1e-8):
+        p, t_ms, e_max = g0_ranks.clone(), [], 0.0
+        for k, (dg, db) in enumerate(zip(dgs, dbs)):
+            out = outs[k & 1]
+            t_ms.append(timed(lambda: prhip.dfp(dg, db, p, frontier_tol=tl, prune_tol=tl,
+                                                out=out))[1])
+            p = out
+            if k in refs:
+                e_max = max(e_max, float((out - refs[k]).abs().max()))
+        sweep.append({"frontier_tol": tl, "prune_tol": tl, "dfp_ms_geomean": round(gm(t_ms), 3),
+                      "dfp_speedup_geomean": round(gm(np.array(st_ms) / np.array(t_ms)), 2),
+                      "max_dfp_linf": e_max})
+    res["tolerance_sweep"] = sweep
+    log("temporal tolerance sweep: " + ", ".join(
+        f"{e['prune_tol']:g}: {e['dfp_ms_geomean']} ms ({e['dfp_speedup_geomean']}x), "
+        f"L-inf {e['max_dfp_linf']:.2e}" for e in sweep))
     if not args.no_tune:
         # the same chain with the autotuner's choices for this graph size
         # (untimed tuning: DF-P on the first batch, Static on G^0), DF taking
