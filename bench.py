@@ -115,6 +115,31 @@ def cpu_info():
     return {"cpu_model": model, "cpu_mhz": mhz, "nproc": os.cpu_count(), "affinity_cpus": aff}
 
 
+def size_sweep(gg, prhip, torch, np, scales=(18, 20, 22, 23, 24), calls=3):
+    """Static on R-MAT (edge factor 16, seed 1) at several sizes with the
+    lane-class bound (32, 128) and the die split (off, on) crossed: which
+    defaults hold at which size. One JSON object per case on stdout."""
+    for sc in scales:
+        g = gg.rmat_graph(sc, 16, seed=1)
+        dg = prhip.DeviceGraph.from_host(g)
+        del g
+        out = torch.empty(dg.n, dtype=torch.float64, device="cuda")
+        for lane in (32, 128):
+            for xs in (0, 129):
+                prhip.set_tuning(lane_max_degree=lane, xcd_split_degree=xs)
+                prhip.static(dg, out=out)
+                ts = [timed(lambda: prhip.static(dg, out=out))[1] for _ in range(calls)]
+                it = prhip.last_stats()["iterations"]
+                med = float(np.median(ts))
+                print(json.dumps({"scale": sc, "n": dg.n, "m": dg.m, "lane_max_degree": lane,
+                                  "xcd_split_degree": xs, "ms_per_call": round(med, 3),
+                                  "iterations": it,
+                                  "us_per_iteration": round(med * 1e3 / it, 1)}), flush=True)
+        prhip.set_tuning()
+        del dg, out
+        torch.cuda.empty_cache()
+
+
 def copy_probe(gib=1.0, reps=5):
     """A plain device copy of known size (torch's copy kernel), for
     calibrating the PMC byte counters and as a measured copy ceiling."""
@@ -406,6 +431,9 @@ def main():
                          "IDs, or relabelled by descending out-degree")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run the calibration copy kernel")
+    ap.add_argument("--size-sweep", action="store_true",
+                    help="only run Static over R-MAT scales 18-24, lane bound and die split "
+                         "crossed")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -426,6 +454,9 @@ def main():
     prhip.load_library()
     if args.copy_probe:
         copy_probe()
+        return
+    if args.size_sweep:
+        size_sweep(gg, prhip, torch, np)
         return
     legs = [x for x in args.legs.split(",") if x]
     for x in legs:
