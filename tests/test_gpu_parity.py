@@ -208,6 +208,26 @@ def test_dfp_vs_oracle(frac):
     assert np.abs(r - ref).max() <= 10 * 1e-6 * ref.max()
 
 
+@pytest.mark.parametrize("tol_fp", [1e-7, 1e-8])
+@pytest.mark.parametrize("tuning", [dict(), XSPLIT[1]])
+def test_dfp_tighter_tolerances(tol_fp, tuning):
+    """DF-P with the frontier and prune tolerances (Alg. 3) tightened below
+    the paper's 1e-6: the oracle's trajectory at the same tolerances, and an
+    error against the exact ranks that shrinks with them (within
+    10 * tau_p * max(R), as at 1e-6; the oracle comes to 3.3-4.8 times
+    tau_p * max(R) on these cases)."""
+    prhip.set_tuning(**tuning)
+    for seed, frac in ((5, 1e-3), (6, 1e-2)):
+        g0, g1, b, prev = dynamic_case(scale=12, frac=frac, seed=seed)
+        r, res = gpu_dfp(g1, b, prev, frontier_tol=tol_fp, prune_tol=tol_fp)
+        o = oracle.dfp(g1.n, *g1.edges(), b, prev, tau_f=tol_fp, tau_p=tol_fp)
+        assert res.converged
+        assert np.abs(r - o.ranks).max() <= 1e-9
+        assert abs(res.iterations - o.iters) <= 1
+        ref = oracle.static(g1.n, *g1.edges(), tol=1e-14, max_iter=5000).ranks
+        assert np.abs(r - ref).max() <= 10 * tol_fp * ref.max()
+
+
 @pytest.mark.parametrize("relabel", [0, 1])
 def test_dfp_all_lane_bitwise(relabel):
     prhip.set_tuning(**ALL_LANE, relabel=relabel)
