@@ -99,9 +99,10 @@ int pr_static(const pr_csr *csr, double alpha, double tol, int max_iter, double 
  * fixed device-resident array of PR_NOALLOC_SCRATCH_BYTES that each device
  * holds from the time the library's code is loaded on it until the process
  * ends, shared by every call on that device and left holding the last call's
- * contents (each call initialises what it reads). Calls on one device are
- * serialised within a process; calls that overlap on one device from several
- * processes race on that array.
+ * contents (each call initialises what it reads). Calls that overlapped on
+ * one device's array would race on it; they do not: a call returns only
+ * after its device work has finished, calls within a process are serialised,
+ * and each process that loads the library has its own copy of the array.
  * Limits: n <= PR_NOALLOC_MAX_N and about 44 n + 12 m / hub_chunk_edges
  * bytes of scratch (at most PR_NOALLOC_SCRATCH_BYTES); beyond them PR_EINVAL,
  * before any work is enqueued, with the reason in pr_last_error().
